@@ -1,0 +1,273 @@
+/*
+ * libqld: quadrature lock-in discrimination (QLD) imaging on AMD Instinct MI355X
+ * (gfx950).  C ABI.
+ *
+ * The operation (paper: Methods, the formula for R(j,k); Supplementary
+ * Information, "Timing sequence for hybrid parallelisation"): every pixel's
+ * intensity series S_t, sampled four times per modulation period, is
+ * multiplied by the cosine and the sine of the lock-in phase and summed,
+ *     I = sum_t S_t cos(2 pi (phase0 + t)/4) = sum over cycles (S0 - S2)
+ *     Q = sum_t S_t sin(2 pi (phase0 + t)/4) = sum over cycles (S1 - S3)
+ * and the image is the amplitude R = (I^2 + Q^2)^(1/2).  Accumulation starts
+ * with the first frame and proceeds frame by frame (section "Quadrature
+ * Lock-in Discrimination", on-the-fly processing); a sliding window of N
+ * frames refreshes the image at the camera rate (Supplementary, sliding
+ * sequence and buffer requirement).  The conventional alternative, a Fourier
+ * transform of the series evaluated at the lock-in frequency (Methods,
+ * Fourier map), is provided as the single-bin baseline dft_bin_baseline.
+ *
+ * General conventions
+ *   - Pointers are DEVICE pointers (hipMalloc or torch CUDA tensors on the
+ *     current device) unless the comment says "host".
+ *   - Frame stacks are [T][H][W] with element (t, y, x) at
+ *         base + t*frame_stride + y*row_pitch + x       (strides in ELEMENTS).
+ *     Frame t is sampled at lock-in phase (phase0 + t) mod 4.
+ *   - The caller owns every buffer it passes; libqld owns the handles it
+ *     creates (qld_window, qld_server) and the device memory behind them.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the legacy default
+ *     stream) and is asynchronous: outputs are valid once the stream reaches
+ *     the call.  Argument errors are detected synchronously, before anything
+ *     is enqueued, and leave every output untouched.
+ *   - A launch or runtime failure returns QLD_E_DEVICE; a fault inside a
+ *     kernel surfaces as QLD_E_DEVICE from a later call.  qld_last_error()
+ *     gives a thread-local message for the most recent failure.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef QLD_H
+#define QLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same type as hipStream_t, declared here so the header needs no HIP include. */
+typedef struct ihipStream_t *qld_hip_stream;
+
+typedef enum {
+    QLD_OK = 0,
+    QLD_E_INVAL = 1,     /* null pointer, negative count, bad enum */
+    QLD_E_DTYPE = 2,     /* dtype/bits combination not supported */
+    QLD_E_SHAPE = 3,     /* H, W, pitches or frame count inconsistent */
+    QLD_E_ALIGN = 4,     /* alignment required by this entry point not met */
+    QLD_E_OVERFLOW = 5,  /* int32 accumulators could overflow for this input */
+    QLD_E_NOMEM = 6,     /* device or pinned host allocation failed */
+    QLD_E_BUDGET = 7,    /* request can never fit in the server's HBM budget */
+    QLD_E_AGAIN = 8,     /* not now: queued for admission, or no slot free yet */
+    QLD_E_STATE = 9,     /* call not valid in the handle's current state */
+    QLD_E_GAP = 10,      /* frame index skipped: the window was reset */
+    QLD_E_DEVICE = 11,   /* HIP runtime or kernel failure */
+    QLD_E_IO = 12        /* checkpoint file could not be read or written */
+} qld_status;
+
+typedef enum { QLD_U8 = 1, QLD_U16 = 2 } qld_dtype;
+
+/* Geometry and sample format of one frame (and of a stack of frames). */
+typedef struct {
+    int32_t H, W;            /* rows, columns (>= 0) */
+    int64_t row_pitch;       /* elements between rows, >= W */
+    int64_t frame_stride;    /* elements between frames, >= (H-1)*row_pitch + W */
+    qld_dtype dtype;         /* QLD_U8 or QLD_U16 */
+    int32_t bits;            /* significant bits per sample: 1..8 (U8) or 1..16 (U16) */
+} qld_frame_desc;
+
+/* ------------------------------------------------------------------------ */
+/* Batch lock-in                                                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * qld_accumulate -- quadrature sums of a frame stack (Methods, R(j,k);
+ * Supplementary, each frame multiplied by sin and cos and accumulated into
+ * two 2-D arrays).
+ *
+ *   frames     device, [n_frames][H][W] in the layout of `d`
+ *   n_frames   >= 0; frame t has phase (phase0 + t) mod 4, phase0 any int
+ *   I, Q       device int32 [H][W] (dense, row pitch W).  ACCUMULATED: the
+ *              call adds this stack's sums to the values already there, so a
+ *              stack can be fed in chunks (pass phase0 + frames done so far)
+ *   frame_sum  device uint64 [n_frames] or NULL: frame_sum[t] += sum of frame t
+ *   frame_sat  device uint32 [n_frames] or NULL: frame_sat[t] += number of
+ *              samples equal to 2^bits - 1 (clipped pixels break the exact
+ *              cancellation of the unmodulated light)
+ * Errors: QLD_E_OVERFLOW if ceil(n_frames/4) * (2^bits - 1) >= 2^31 (the
+ * caller must split longer stacks into separate accumulators).  Inputs need
+ * no particular alignment; 16-byte aligned base and pitches take the fast
+ * path.  Integer arithmetic throughout: the result is exact.
+ */
+qld_status qld_accumulate(const void *frames, const qld_frame_desc *d, int32_t n_frames,
+                          int32_t phase0, int32_t *I, int32_t *Q, uint64_t *frame_sum,
+                          uint32_t *frame_sat, qld_hip_stream stream);
+
+/*
+ * qld_amplitude -- R = (I^2 + Q^2)^(1/2) (Methods, R(j,k)).
+ *   I, Q       device int32 [n_pixels];  amp  device float [n_pixels] (overwritten)
+ * I^2 + Q^2 is formed exactly in 64-bit integers, its square root taken in
+ * double precision and rounded once to float.
+ */
+qld_status qld_amplitude(const int32_t *I, const int32_t *Q, int64_t n_pixels, float *amp,
+                         qld_hip_stream stream);
+
+/*
+ * dft_bin_baseline -- the Fourier alternative at one frequency (Methods,
+ * Fourier map |F(omega)|^2 of each pixel's series):
+ *     X_k = sum_{n < N} S_n exp(-2 pi i ((k n) mod N) / N),   N = n_frames
+ *   re, im     device float [H][W] (dense, overwritten)
+ * Twiddles are a float table built in double from the exact integer angle
+ * (k n) mod N; accumulation is float.  At k = N/4 with N = 4M, X = I - iQ up
+ * to rounding.  Reports QLD_E_SHAPE for n_frames < 1.
+ */
+qld_status dft_bin_baseline(const void *frames, const qld_frame_desc *d, int32_t n_frames,
+                            int32_t k_bin, float *re, float *im, qld_hip_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Sliding window (Supplementary: sliding sequence of N frames, buffer N n^2) */
+/* ------------------------------------------------------------------------ */
+
+typedef struct qld_window qld_window;
+
+/* Device bytes a window of M_cycles cycles needs for frames described by d:
+ * ring of per-cycle differences (4 B/px per cycle for bits <= 15, 8 B/px for
+ * 16-bit data) + I/Q state (8 B/px).  0 for invalid arguments. */
+size_t qld_window_bytes(const qld_frame_desc *d, int32_t M_cycles);
+
+/* Create a window on the current device.  M_cycles >= 1 and
+ * M_cycles * (2^bits - 1) < 2^31. */
+qld_status qld_window_create(const qld_frame_desc *d, int32_t M_cycles, qld_window **out);
+
+/*
+ * Feed one cycle (four frames, phases 0..3, in the layout of d starting at
+ * cycle_frames) and refresh the window:
+ *     D = (S0 - S2, S1 - S3);   (I, Q) += D - D_oldest  (once M cycles are in)
+ * I_out, Q_out (int32 [H][W]) and amp_out (float [H][W]) are device, each may
+ * be NULL.  warm_out (host, may be NULL) receives 1 once the window holds M
+ * cycles (0 before: the image then covers the cycles received so far).
+ */
+qld_status qld_window_update(qld_window *w, const void *cycle_frames, int32_t *I_out,
+                             int32_t *Q_out, float *amp_out, int32_t *warm_out,
+                             qld_hip_stream stream);
+
+/* Forget every cycle (the next update starts a new window).  Enqueued on the
+ * window's last stream. */
+qld_status qld_window_reset(qld_window *w);
+qld_status qld_window_destroy(qld_window *w);
+/* Cycles currently in the window (0..M) and cycles fed since creation/reset. */
+qld_status qld_window_info(const qld_window *w, int32_t *n_in_window, int64_t *n_cycles);
+/* Checkpoint: ring, I/Q state and counters to a file; load restores them into
+ * a window created with the same desc and M (QLD_E_STATE otherwise).  Both
+ * synchronise with the device. */
+qld_status qld_window_save(const qld_window *w, const char *path);
+qld_status qld_window_load(qld_window *w, const char *path);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: many camera streams, one GPU, continuous batching               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct qld_server qld_server;
+
+typedef enum { QLD_MODE_PLAIN = 0 } qld_mode;
+
+/* Server flags. */
+enum { QLD_SERVER_KEEP_IQ = 1 };   /* also keep per-cycle I/Q output slots */
+
+typedef enum {
+    QLD_STREAM_PENDING = 1,   /* waiting for HBM budget */
+    QLD_STREAM_ACTIVE = 2,
+    QLD_STREAM_CLOSED = 3
+} qld_stream_state_t;
+
+/* One processed image (one per complete cycle of a stream). */
+typedef struct {
+    int32_t stream_id;
+    int32_t warm;              /* 1 once the window holds M cycles */
+    int64_t cycle;             /* camera cycle index: frame_index / 4 of its frames */
+    uint64_t t_arrival_ns;     /* arrival time of the cycle's last frame (caller's clock) */
+    uint64_t t_done_ns;        /* CLOCK_MONOTONIC when the image was complete on the device */
+    const float *amp;          /* device [H][W]; valid until out_slots more cycles of
+                                  the stream complete, or the stream closes */
+    int32_t H, W;
+} qld_result;
+
+/*
+ * Create a server on the current device.
+ *   hbm_budget_bytes  device memory the server may hold for stream state
+ *                     (window ring + I/Q state + frame staging + output slots)
+ *   out_slots         images kept per stream (ring of output slots), 1..1024
+ *   flags             QLD_SERVER_KEEP_IQ to also keep per-cycle I/Q
+ * Starts a scheduler thread (batches every ready cycle of every stream into
+ * one launch) and a completion thread (stamps t_done_ns, publishes results).
+ */
+qld_status qld_server_create(size_t hbm_budget_bytes, int32_t out_slots, int32_t flags,
+                             qld_server **out);
+
+/* Device bytes one stream of this shape and window costs under the server's
+ * policy (what admission charges against the budget). */
+size_t qld_server_stream_bytes(const qld_server *s, const qld_frame_desc *d, int32_t M_cycles,
+                               int32_t M_short);
+
+/* Open a stream of dense host frames (d->row_pitch/frame_stride are ignored)
+ * with a window of M_cycles cycles and optionally a short window of M_short
+ * (0 = none) cycles sharing the same ring.  QLD_OK: admitted now.
+ * QLD_E_AGAIN: queued (state PENDING); admitted in FIFO order once closes
+ * free enough budget.  QLD_E_BUDGET: can never fit.  *stream_id is set in
+ * the first two cases. */
+qld_status qld_stream_open(qld_server *s, const qld_frame_desc *d, int32_t M_cycles,
+                           int32_t M_short, int32_t mode, int32_t *stream_id);
+
+qld_status qld_stream_state(qld_server *s, int32_t stream_id, int32_t *state);
+
+/*
+ * Submit one frame (host pointer, dense [H][W] of the stream's dtype).  Frame
+ * index f has lock-in phase f mod 4; a cycle is the four frames 4m..4m+3.
+ * The frame is copied into pinned staging before the call returns, so the
+ * caller may reuse its buffer at once.  frame_index must be the previous
+ * index + 1: a larger index resets the window (the partial cycle is dropped,
+ * frames are skipped until the next index that is a multiple of 4) and the
+ * call returns QLD_E_GAP; a smaller one is rejected (QLD_E_INVAL).  A pending
+ * stream returns QLD_E_AGAIN.  Blocks while all staging slots of the stream
+ * are in flight (back-pressure).  Thread-safe: one submitting thread per stream.
+ */
+qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const void *host_frame,
+                             int64_t frame_index, uint64_t t_arrival_ns);
+
+/* Completed images, oldest first, at most max; *n_out set.  Non-blocking.
+ * Returns QLD_E_DEVICE if a launch has failed. */
+qld_status qld_stream_poll(qld_server *s, qld_result *out, int32_t max, int32_t *n_out);
+
+/* Device I/Q (and short-window I/Q, NULL without a short window) of a polled
+ * result; needs QLD_SERVER_KEEP_IQ.  Same lifetime as res->amp. */
+qld_status qld_stream_result_iq(qld_server *s, const qld_result *res, const int32_t **I,
+                                const int32_t **Q, const int32_t **Is, const int32_t **Qs);
+
+/* Block until every submitted complete cycle has been processed. */
+qld_status qld_server_drain(qld_server *s);
+
+/* Close a stream: its pending cycles are finished, its unpolled results
+ * dropped, its memory released, and queued streams admitted if they now fit. */
+qld_status qld_stream_close(qld_server *s, int32_t stream_id);
+qld_status qld_server_destroy(qld_server *s);
+
+/* Counters: launches, cycles processed, most streams in one launch, budget bytes in use. */
+qld_status qld_server_stats(const qld_server *s, int64_t *batches, int64_t *cycles,
+                            int32_t *max_streams_in_batch, size_t *bytes_in_use);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                              */
+/* ------------------------------------------------------------------------ */
+const char *qld_status_str(qld_status st);
+const char *qld_last_error(void);
+/* Device timing of the main kernel alone: start_event / stop_event are
+ * hipEvent_t handles created by the caller.  The next qld_accumulate or
+ * dft_bin_baseline call made by this thread records start_event on its
+ * stream right before its main kernel (qld_accum_kernel / dft_bin_kernel) and
+ * stop_event right after it, excluding the helper kernels (statistics
+ * reduction, twiddle table, chunk reduction).  Both NULL cancels. */
+qld_status qld_time_next_kernel(void *start_event, void *stop_event);
+/* Library build string (compiler, target). */
+const char *qld_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QLD_H */

@@ -1,0 +1,355 @@
+"""MI355X (gfx950) quadrature lock-in discrimination: Python binding of libqld.
+
+Thin ctypes layer over the C ABI declared in ``include/qld.h``.  It only
+marshals arguments (torch tensors -> device pointers, the current torch
+stream -> hipStream_t); every step of the computation runs in the HIP
+kernels of ``libqld.so``.  There is no fallback: if the library is missing
+or fails to load, importing this package raises.
+
+Build the library with ``python -m paper_1511_03390_amd._build`` (or
+``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqld.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libqld.so is not built (%s); run python -m paper_1511_03390_amd._build" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+# Status codes (qld_status).
+OK, E_INVAL, E_DTYPE, E_SHAPE, E_ALIGN, E_OVERFLOW, E_NOMEM, E_BUDGET, E_AGAIN, E_STATE, E_GAP, E_DEVICE, E_IO = range(13)
+U8, U16 = 1, 2
+STREAM_PENDING, STREAM_ACTIVE, STREAM_CLOSED = 1, 2, 3
+SERVER_KEEP_IQ = 1
+
+# Every entry point the header declares (checked by the tests).
+EXPORTS = (
+    "qld_accumulate", "qld_amplitude", "dft_bin_baseline",
+    "qld_window_bytes", "qld_window_create", "qld_window_update", "qld_window_reset",
+    "qld_window_destroy", "qld_window_info", "qld_window_save", "qld_window_load",
+    "qld_server_create", "qld_server_stream_bytes", "qld_stream_open", "qld_stream_state",
+    "qld_stream_submit", "qld_stream_poll", "qld_stream_result_iq", "qld_server_drain",
+    "qld_stream_close", "qld_server_destroy", "qld_server_stats",
+    "qld_status_str", "qld_last_error", "qld_version", "qld_time_next_kernel",
+)
+
+
+class QldError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.qld_last_error().decode(errors="replace")
+        super().__init__("%s: %s (%s)" % (where, _lib.qld_status_str(status).decode(), msg))
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("row_pitch", ctypes.c_int64),
+                ("frame_stride", ctypes.c_int64), ("dtype", ctypes.c_int), ("bits", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("stream_id", ctypes.c_int32), ("warm", ctypes.c_int32), ("cycle", ctypes.c_int64),
+                ("t_arrival_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
+                ("amp", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+_vp, _i32, _i64, _u64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+_dp = ctypes.POINTER(FrameDesc)
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("qld_accumulate", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp, _vp, _vp)
+_sig("qld_amplitude", ctypes.c_int, _vp, _vp, _i64, _vp, _vp)
+_sig("dft_bin_baseline", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp)
+_sig("qld_window_bytes", _sz, _dp, _i32)
+_sig("qld_window_create", ctypes.c_int, _dp, _i32, ctypes.POINTER(_vp))
+_sig("qld_window_update", ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _vp)
+_sig("qld_window_reset", ctypes.c_int, _vp)
+_sig("qld_window_destroy", ctypes.c_int, _vp)
+_sig("qld_window_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64))
+_sig("qld_window_save", ctypes.c_int, _vp, ctypes.c_char_p)
+_sig("qld_window_load", ctypes.c_int, _vp, ctypes.c_char_p)
+_sig("qld_server_create", ctypes.c_int, _sz, _i32, _i32, ctypes.POINTER(_vp))
+_sig("qld_server_stream_bytes", _sz, _vp, _dp, _i32, _i32)
+_sig("qld_stream_open", ctypes.c_int, _vp, _dp, _i32, _i32, _i32, ctypes.POINTER(_i32))
+_sig("qld_stream_state", ctypes.c_int, _vp, _i32, ctypes.POINTER(_i32))
+_sig("qld_stream_submit", ctypes.c_int, _vp, _i32, _vp, _i64, _u64)
+_sig("qld_stream_poll", ctypes.c_int, _vp, ctypes.POINTER(Result), _i32, ctypes.POINTER(_i32))
+_sig("qld_stream_result_iq", ctypes.c_int, _vp, ctypes.POINTER(Result), ctypes.POINTER(_vp),
+     ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp))
+_sig("qld_server_drain", ctypes.c_int, _vp)
+_sig("qld_stream_close", ctypes.c_int, _vp, _i32)
+_sig("qld_server_destroy", ctypes.c_int, _vp)
+_sig("qld_server_stats", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+     ctypes.POINTER(_i32), ctypes.POINTER(_sz))
+_sig("qld_status_str", ctypes.c_char_p, ctypes.c_int)
+_sig("qld_last_error", ctypes.c_char_p)
+_sig("qld_version", ctypes.c_char_p)
+_sig("qld_time_next_kernel", ctypes.c_int, _vp, _vp)
+
+lib = _lib
+
+
+class KernelTimer:
+    """HIP events (from the HIP runtime, on the launch stream) around the main
+    kernel of the next qld_accumulate / dft_bin_baseline call of this thread."""
+
+    _hip = None
+
+    def __init__(self):
+        if KernelTimer._hip is None:
+            h = ctypes.CDLL("libamdhip64.so")
+            h.hipEventCreate.argtypes = [ctypes.POINTER(_vp)]
+            h.hipEventDestroy.argtypes = [_vp]
+            h.hipEventSynchronize.argtypes = [_vp]
+            h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), _vp, _vp]
+            KernelTimer._hip = h
+        self.start, self.stop = _vp(), _vp()
+        if self._hip.hipEventCreate(ctypes.byref(self.start)) or self._hip.hipEventCreate(ctypes.byref(self.stop)):
+            raise RuntimeError("hipEventCreate failed")
+
+    def arm(self):
+        _check(_lib.qld_time_next_kernel(self.start, self.stop), "qld_time_next_kernel")
+
+    def ms(self):
+        if self._hip.hipEventSynchronize(self.stop):
+            raise RuntimeError("hipEventSynchronize failed")
+        out = ctypes.c_float()
+        if self._hip.hipEventElapsedTime(ctypes.byref(out), self.start, self.stop):
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(out.value)
+
+    def __del__(self):
+        try:
+            self._hip.hipEventDestroy(self.start)
+            self._hip.hipEventDestroy(self.stop)
+        except Exception:
+            pass
+
+
+def _check(st, where, ok=(OK,)):
+    if st not in ok:
+        raise QldError(st, where)
+    return st
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+_DT = {torch.uint8: (U8, 8), torch.int16: (U16, 16), torch.uint16: (U16, 16)}
+
+
+def frame_desc(frames: torch.Tensor, bits: int | None = None) -> FrameDesc:
+    """Descriptor of a [T][H][W] (or [H][W]) frame tensor; innermost stride must be 1."""
+    if frames.dtype not in _DT:
+        raise TypeError("frames must be uint8, int16 or uint16 (16-bit samples), got %s" % frames.dtype)
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    if frames.dim() != 3:
+        raise ValueError("frames must be [T][H][W]")
+    T, H, W = frames.shape
+    if W > 1 and frames.stride(2) != 1:
+        raise ValueError("frames must be contiguous along W")
+    dt, nbits = _DT[frames.dtype]
+    rp = frames.stride(1) if H > 1 else W
+    fs = frames.stride(0) if T > 1 else H * rp
+    return FrameDesc(int(H), int(W), int(rp), int(fs), dt, int(bits or nbits))
+
+
+def accumulate(frames, I, Q, phase0=0, bits=None, frame_sum=None, frame_sat=None, stream=None):
+    """I += sum over cycles (S0 - S2), Q += sum (S1 - S3) of a [T][H][W] device stack."""
+    d = frame_desc(frames, bits)
+    n = frames.shape[0] if frames.dim() == 3 else 1
+    _check(_lib.qld_accumulate(_ptr(frames), ctypes.byref(d), int(n), int(phase0), _ptr(I), _ptr(Q),
+                               _ptr(frame_sum), _ptr(frame_sat), _stream(stream)), "qld_accumulate")
+
+
+def amplitude(I, Q, amp, stream=None):
+    _check(_lib.qld_amplitude(_ptr(I), _ptr(Q), int(I.numel()), _ptr(amp), _stream(stream)), "qld_amplitude")
+
+
+def dft_bin_baseline(frames, k, re, im, bits=None, stream=None):
+    d = frame_desc(frames, bits)
+    n = frames.shape[0] if frames.dim() == 3 else 1
+    _check(_lib.dft_bin_baseline(_ptr(frames), ctypes.byref(d), int(n), int(k), _ptr(re), _ptr(im),
+                                 _stream(stream)), "dft_bin_baseline")
+
+
+def lockin(frames, phase0=0, bits=None, stats=False, stream=None):
+    """Convenience: fresh I, Q, amplitude (and per-frame stats) of a device stack."""
+    T, H, W = frames.shape
+    dev = frames.device
+    I = torch.zeros((H, W), dtype=torch.int32, device=dev)
+    Q = torch.zeros((H, W), dtype=torch.int32, device=dev)
+    fsum = torch.zeros(T, dtype=torch.int64, device=dev) if stats else None
+    fsat = torch.zeros(T, dtype=torch.int32, device=dev) if stats else None
+    accumulate(frames, I, Q, phase0, bits, fsum, fsat, stream)
+    amp = torch.empty((H, W), dtype=torch.float32, device=dev)
+    amplitude(I, Q, amp, stream)
+    return (I, Q, amp, fsum, fsat) if stats else (I, Q, amp)
+
+
+class Window:
+    """Sliding window of M cycles over frames of a fixed shape (device state)."""
+
+    def __init__(self, H, W, M, dtype=torch.int16, bits=None):
+        dt, nbits = _DT[dtype]
+        self.desc = FrameDesc(int(H), int(W), int(W), int(H) * int(W), dt, int(bits or nbits))
+        self.M = M
+        self.H, self.W = H, W
+        h = _vp()
+        _check(_lib.qld_window_create(ctypes.byref(self.desc), int(M), ctypes.byref(h)), "qld_window_create")
+        self._h = h
+
+    @staticmethod
+    def bytes(H, W, M, dtype=torch.int16, bits=None):
+        dt, nbits = _DT[dtype]
+        d = FrameDesc(int(H), int(W), int(W), int(H) * int(W), dt, int(bits or nbits))
+        return int(_lib.qld_window_bytes(ctypes.byref(d), int(M)))
+
+    def update(self, cycle_frames, I_out=None, Q_out=None, amp_out=None, stream=None):
+        """Feed one cycle ([4][H][W] device tensor); returns warm (1 once M cycles are in)."""
+        d = frame_desc(cycle_frames, self.desc.bits)
+        if (d.H, d.W) != (self.H, self.W) or cycle_frames.shape[0] != 4:
+            raise ValueError("cycle must be [4][%d][%d]" % (self.H, self.W))
+        self.desc.row_pitch, self.desc.frame_stride = d.row_pitch, d.frame_stride
+        warm = _i32()
+        _check(_lib.qld_window_update(self._h, _ptr(cycle_frames), _ptr(I_out), _ptr(Q_out), _ptr(amp_out),
+                                      ctypes.byref(warm), _stream(stream)), "qld_window_update")
+        return warm.value
+
+    def reset(self):
+        _check(_lib.qld_window_reset(self._h), "qld_window_reset")
+
+    def info(self):
+        n, c = _i32(), _i64()
+        _check(_lib.qld_window_info(self._h, ctypes.byref(n), ctypes.byref(c)), "qld_window_info")
+        return n.value, c.value
+
+    def save(self, path):
+        _check(_lib.qld_window_save(self._h, str(path).encode()), "qld_window_save")
+
+    def load(self, path):
+        _check(_lib.qld_window_load(self._h, str(path).encode()), "qld_window_load")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.qld_window_destroy(self._h), "qld_window_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server for many camera streams (see qld_server_* in qld.h)."""
+
+    def __init__(self, hbm_budget_bytes, out_slots=8, keep_iq=False):
+        h = _vp()
+        _check(_lib.qld_server_create(int(hbm_budget_bytes), int(out_slots), SERVER_KEEP_IQ if keep_iq else 0,
+                                      ctypes.byref(h)), "qld_server_create")
+        self._h = h
+        self.shapes = {}
+
+    def stream_bytes(self, H, W, M, M_short=0, dtype=torch.int16, bits=None):
+        dt, nbits = _DT[dtype]
+        d = FrameDesc(int(H), int(W), int(W), int(H) * int(W), dt, int(bits or nbits))
+        return int(_lib.qld_server_stream_bytes(self._h, ctypes.byref(d), int(M), int(M_short)))
+
+    def open(self, H, W, M, M_short=0, dtype=torch.int16, bits=None):
+        """Returns (stream_id, admitted_now)."""
+        dt, nbits = _DT[dtype]
+        d = FrameDesc(int(H), int(W), int(W), int(H) * int(W), dt, int(bits or nbits))
+        sid = _i32()
+        st = _check(_lib.qld_stream_open(self._h, ctypes.byref(d), int(M), int(M_short), 0, ctypes.byref(sid)),
+                    "qld_stream_open", ok=(OK, E_AGAIN))
+        self.shapes[sid.value] = (H, W)
+        return sid.value, st == OK
+
+    def state(self, sid):
+        s = _i32()
+        _check(_lib.qld_stream_state(self._h, int(sid), ctypes.byref(s)), "qld_stream_state")
+        return s.value
+
+    def submit(self, sid, frame, index, t_arrival_ns):
+        """frame: host numpy array [H][W] (uint8 / uint16), C-contiguous.  Returns the status."""
+        if not frame.flags["C_CONTIGUOUS"]:
+            raise ValueError("frame must be C-contiguous")
+        return _check(_lib.qld_stream_submit(self._h, int(sid), ctypes.c_void_p(frame.ctypes.data), int(index),
+                                             int(t_arrival_ns)), "qld_stream_submit", ok=(OK, E_GAP, E_AGAIN))
+
+    def poll(self, max_results=256):
+        buf = (Result * max_results)()
+        n = _i32()
+        _check(_lib.qld_stream_poll(self._h, buf, int(max_results), ctypes.byref(n)), "qld_stream_poll")
+        return [buf[i] for i in range(n.value)]
+
+    def result_iq(self, res):
+        ptrs = [_vp() for _ in range(4)]
+        _check(_lib.qld_stream_result_iq(self._h, ctypes.byref(res), *[ctypes.byref(p) for p in ptrs]),
+               "qld_stream_result_iq")
+        return [p.value for p in ptrs]
+
+    def drain(self):
+        _check(_lib.qld_server_drain(self._h), "qld_server_drain")
+
+    def close_stream(self, sid):
+        _check(_lib.qld_stream_close(self._h, int(sid)), "qld_stream_close")
+
+    def stats(self):
+        b, c, m, u = _i64(), _i64(), _i32(), _sz()
+        _check(_lib.qld_server_stats(self._h, ctypes.byref(b), ctypes.byref(c), ctypes.byref(m), ctypes.byref(u)),
+               "qld_server_stats")
+        return dict(batches=b.value, cycles=c.value, max_streams_in_batch=m.value, bytes_in_use=u.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.qld_server_destroy(self._h), "qld_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceArray:
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(int(s) for s in shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2, "strides": None}
+
+
+def device_view(ptr, shape, dtype, device=None):
+    """Wrap a device pointer owned by libqld as a torch tensor (no copy, no ownership)."""
+    typestr = {torch.float32: "<f4", torch.int32: "<i4"}[dtype]
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    return torch.as_tensor(_DeviceArray(ptr, shape, typestr), device=dev)
+
+
+def version():
+    return _lib.qld_version().decode()

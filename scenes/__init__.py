@@ -185,11 +185,16 @@ class CameraStream:
         self.radius, self.amplitude = radius, amplitude
         self.noise = np.rint(background + rng.normal(0.0, sigma, size=(bank, H, W))).astype(np.int32)
         self.static = []
+
+        def centre(n):
+            # Keep the disk inside when the frame is large enough; otherwise anywhere.
+            return int(rng.integers(radius, n - radius)) if n > 2 * radius else int(rng.integers(0, n))
+
         for _ in range(n_static):
-            cy = int(rng.integers(radius, H - radius))
-            cx = int(rng.integers(radius, W - radius))
+            cy = centre(H)
+            cx = centre(W)
             self.static.append((cy, cx, float(rng.uniform(0, 2 * math.pi))))
-        self.mover_y = int(rng.integers(radius, H - radius))
+        self.mover_y = centre(H)
         self.mover_x0 = int(rng.integers(0, W))
         self.mover_phi = float(rng.uniform(0, 2 * math.pi))
         self.maxv = (1 << bits) - 1

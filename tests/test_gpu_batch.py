@@ -1,0 +1,200 @@
+"""GPU parity of the batch path (qld_accumulate with per-frame statistics,
+qld_amplitude, dft_bin_baseline) against the CPU oracle, through the C ABI.
+
+Bar: I/Q and the statistics bit-exact; amplitude within 2 ulp of float32 of
+the double-precision oracle; the DFT within (N + 2) 2^-24 sum|x| per component.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1511_03390_amd as qld
+import scenes
+from tests.gpu_util import amp_ulps, need_gpu, say, to_dev, to_host_u16
+
+pytestmark = pytest.mark.gpu
+
+
+def run_lockin(frames_np, phase0=0, bits=None, pitch_view=None):
+    dev = to_dev(frames_np)
+    if pitch_view is not None:
+        dev = pitch_view(dev)
+    I, Q, amp, fsum, fsat = qld.lockin(dev, phase0=phase0, bits=bits, stats=True)
+    torch.cuda.synchronize()
+    return I.cpu().numpy(), Q.cpu().numpy(), amp.cpu().numpy(), fsum.cpu().numpy(), fsat.cpu().numpy()
+
+
+def check_against_oracle(frames_host_view, I, Q, amp, fsum, fsat, phase0, bits):
+    oI, oQ = oracle.qld(frames_host_view, phase0)
+    assert np.array_equal(I.astype(np.int64), oI), "I differs"
+    assert np.array_equal(Q.astype(np.int64), oQ), "Q differs"
+    s, n = oracle.frame_stats(frames_host_view, bits)
+    assert np.array_equal(fsum.astype(np.uint64), s), "frame sums differ"
+    assert np.array_equal(fsat.astype(np.uint32), n), "saturation counts differ"
+    oa = oracle.amplitude(oI, oQ)
+    u = amp_ulps(amp, oa)
+    assert u.max() <= 2.0, u.max()
+    return float(u.max())
+
+
+def test_small_disk_scene_u8():
+    need_gpu()
+    st = scenes.disk_scene_u8()
+    say("disk scene u8", st.frames.shape)
+    I, Q, amp, fsum, fsat = run_lockin(st.frames, bits=8)
+    check_against_oracle(st.frames, I, Q, amp, fsum, fsat, 0, 8)
+    # The modulated disk stands out: square-wave closed form 2 sqrt(2) M A = 181.02 minus noise.
+    m = st.meta["mask"]
+    assert amp[m].mean() > 3 * amp[~m].mean()
+
+
+CASES = [
+    # (dtype, T, H, W, pitch_extra, phase0, bits, misalign)
+    (np.uint16, 64, 17, 33, 0, 0, 12, 0),
+    (np.uint16, 67, 5, 8, 8, 1, 12, 0),
+    (np.uint16, 5, 3, 1000, 24, 3, 16, 0),
+    (np.uint16, 1, 1, 1, 0, 0, 16, 0),
+    (np.uint16, 2, 9, 7, 0, 2, 16, 1),
+    (np.uint16, 3, 300, 257, 0, 7, 12, 0),
+    (np.uint16, 4096, 16, 16, 0, 0, 12, 0),      # frame axis split over many work-groups
+    (np.uint16, 1029, 40, 64, 0, -1, 12, 0),
+    (np.uint8, 64, 64, 64, 0, 0, 8, 0),
+    (np.uint8, 33, 7, 31, 1, 1, 8, 0),
+    (np.uint8, 2000, 8, 48, 16, 2, 8, 0),
+    (np.uint8, 9, 13, 17, 0, 0, 8, 3),
+]
+
+
+@pytest.mark.parametrize("dt,T,H,W,pextra,phase0,bits,mis", CASES)
+def test_random_shapes(dt, T, H, W, pextra, phase0, bits, mis):
+    need_gpu()
+    rng = np.random.default_rng(1000 + T * 7 + W)
+    say("shape case", dt.__name__, T, H, W, pextra, phase0, bits, mis)
+    pitch = W + pextra + mis
+    buf, _ = scenes.random_stack(rng, T, H, pitch, dt, bits=bits)
+    # Include saturated samples so the count is exercised.
+    buf[:, ::3, ::5] = (1 << bits) - 1
+    view_host = buf[:, :, mis:mis + W]
+    dev_full = to_dev(buf)
+    dev = dev_full[:, :, mis:mis + W]
+    I, Q, amp, fsum, fsat = qld.lockin(dev, phase0=phase0, bits=bits, stats=True)
+    torch.cuda.synchronize()
+    check_against_oracle(view_host, I.cpu().numpy(), Q.cpu().numpy(), amp.cpu().numpy(), fsum.cpu().numpy(),
+                         fsat.cpu().numpy(), phase0, bits)
+
+
+def test_chunked_accumulation_equals_whole():
+    need_gpu()
+    rng = np.random.default_rng(3)
+    f = rng.integers(0, 4096, size=(150, 21, 40)).astype(np.uint16)
+    dev = to_dev(f)
+    I = torch.zeros((21, 40), dtype=torch.int32, device="cuda")
+    Q = torch.zeros_like(I)
+    done = 0
+    for n in (1, 6, 37, 50, 56):
+        qld.accumulate(dev[done:done + n], I, Q, phase0=done, bits=12)
+        done += n
+    torch.cuda.synchronize()
+    oI, oQ = oracle.qld(f)
+    assert np.array_equal(I.cpu().numpy(), oI) and np.array_equal(Q.cpu().numpy(), oQ)
+
+
+def test_full_range_16bit_and_overflow_edge():
+    need_gpu()
+    M = 32768
+    f = np.zeros((4 * M, 1, 8), dtype=np.uint16)
+    f[0::4] = 65535
+    f[1::4, :, ::2] = 65535
+    dev = to_dev(f)
+    I, Q, amp = qld.lockin(dev, bits=16)
+    torch.cuda.synchronize()
+    assert (I.cpu().numpy() == 65535 * M).all()
+    assert (Q.cpu().numpy()[0, ::2] == 65535 * M).all() and (Q.cpu().numpy()[0, 1::2] == 0).all()
+    with pytest.raises(qld.QldError) as e:
+        qld.lockin(to_dev(np.zeros((4 * M + 1, 1, 8), np.uint16)), bits=16)
+    assert e.value.status == qld.E_OVERFLOW
+
+
+def test_amplitude_extremes():
+    need_gpu()
+    rng = np.random.default_rng(4)
+    I = np.concatenate([np.array([0, 1, -1, 3, 2 ** 31 - 1, -(2 ** 31 - 1), 46341, 2 ** 30, 5], np.int32),
+                        rng.integers(-2 ** 31 + 1, 2 ** 31 - 1, 100000, dtype=np.int64).astype(np.int32)])
+    Q = np.concatenate([np.array([0, 0, 1, 4, 2 ** 31 - 1, 2 ** 31 - 1, 46341, -2 ** 30, 12], np.int32),
+                        rng.integers(-2 ** 31 + 1, 2 ** 31 - 1, 100000, dtype=np.int64).astype(np.int32)])
+    dI, dQ = torch.from_numpy(I).cuda(), torch.from_numpy(Q).cuda()
+    amp = torch.empty(len(I), dtype=torch.float32, device="cuda")
+    qld.amplitude(dI, dQ, amp)
+    a = amp.cpu().numpy()
+    oa = oracle.amplitude(I.astype(np.int64), Q.astype(np.int64))
+    u = amp_ulps(a, oa)
+    say("amplitude max ulp", u.max())
+    assert u.max() <= 2.0
+    assert a[0] == 0 and a[1] == 1 and a[3] == 5 and a[8] == 13
+
+
+def dft_bound(frames_host, N):
+    x = frames_host.astype(np.float64)
+    return (N + 2) * 2.0 ** -24 * np.abs(x).sum(axis=0)
+
+
+@pytest.mark.parametrize("T,H,W,k,dt", [(64, 33, 40, 16, np.uint16), (1024, 16, 64, 256, np.uint16),
+                                        (37, 5, 9, 3, np.uint8), (256, 8, 8, 7, np.uint16),
+                                        (300, 4, 24, -5, np.uint8)])
+def test_dft_bin_baseline(T, H, W, k, dt):
+    need_gpu()
+    rng = np.random.default_rng(T + W)
+    bits = 12 if dt == np.uint16 else 8
+    f = rng.integers(0, (1 << bits), size=(T, H, W)).astype(dt)
+    dev = to_dev(f)
+    re = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    im = torch.empty_like(re)
+    qld.dft_bin_baseline(dev, k, re, im, bits=bits)
+    torch.cuda.synchronize()
+    X = oracle.dft_bin(f, k)
+    bound = dft_bound(f, T)
+    err_r = np.abs(re.cpu().numpy() - X.real)
+    err_i = np.abs(im.cpu().numpy() - X.imag)
+    say("dft max err", err_r.max(), err_i.max(), "bound", bound.min())
+    assert (err_r <= bound).all() and (err_i <= bound).all()
+    if k % T == T // 4 and T % 4 == 0:
+        oI, oQ = oracle.qld(f)
+        assert np.abs(re.cpu().numpy() - oI).max() <= bound.max()
+        assert np.abs(im.cpu().numpy() + oQ).max() <= bound.max()
+
+
+def test_full_size_diffuse_scene_sampled():
+    """1024 x 1024 uint16 (12-bit), 1024 frames: the benchmark's launch, sampled
+    pixels checked by the oracle one by one; statistics against torch's sums."""
+    need_gpu()
+    st = scenes.diffuse_scene_u16(device="cuda")
+    frames = st.frames
+    say("full-size stack", tuple(frames.shape))
+    I, Q, amp, fsum, fsat = qld.lockin(frames, bits=12, stats=True)
+    re = torch.empty((1024, 1024), dtype=torch.float32, device="cuda")
+    im = torch.empty_like(re)
+    qld.dft_bin_baseline(frames, 256, re, im, bits=12)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    ys = np.concatenate([[0, 1023, 511], rng.integers(0, 1024, 61)])
+    xs = np.concatenate([[0, 1023, 512], rng.integers(0, 1024, 61)])
+    sub = frames[:, torch.from_numpy(ys).cuda(), :][:, :, torch.from_numpy(xs).cuda()]
+    sub_h = to_host_u16(sub)                 # [T][64][64], the sampled pixels' series
+    oI, oQ = oracle.qld(sub_h)
+    Ih, Qh, ah = I.cpu().numpy(), Q.cpu().numpy(), amp.cpu().numpy()
+    assert np.array_equal(Ih[np.ix_(ys, xs)], oI) and np.array_equal(Qh[np.ix_(ys, xs)], oQ)
+    assert amp_ulps(ah[np.ix_(ys, xs)], oracle.amplitude(oI, oQ)).max() <= 2.0
+    X = oracle.dft_bin(sub_h, 256)
+    bound = dft_bound(sub_h, 1024)
+    assert (np.abs(re.cpu().numpy()[np.ix_(ys, xs)] - X.real) <= bound).all()
+    assert (np.abs(im.cpu().numpy()[np.ix_(ys, xs)] - X.imag) <= bound).all()
+    # Per-frame statistics of the whole stack against torch's own reductions.
+    ref_sum = frames.to(torch.int64).sum(dim=(1, 2))
+    ref_sat = (frames == 4095).sum(dim=(1, 2))
+    assert torch.equal(fsum, ref_sum) and torch.equal(fsat.to(torch.int64), ref_sat.to(torch.int64))
+    # Drift closed form: the linear ambient ramp leaves I = Q = -2 b M on average
+    # (b = 100/1023 per frame, M = 256) -- about -50 outside the modulated mask.
+    mask = torch.from_numpy(st.meta["mask"]).cuda()
+    mI = I[~mask].double().mean().item()
+    assert abs(mI - (-2 * (100 / 1023) * 256)) < 6.0   # ~5 sigma of the mean of ~1e6 noisy pixels

@@ -1,0 +1,203 @@
+"""GPU parity of the sliding window and of the serving loop against the oracle's
+brute-force window (which re-sums the stored history and never subtracts).
+
+Bar: I/Q bit-exact after every cycle, amplitude within 2 ulp; each stream's
+results in a mixed, continuously batched run identical to the same stream
+run alone.
+"""
+import os
+import tempfile
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1511_03390_amd as qld
+import scenes
+from tests.gpu_util import amp_ulps, need_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("H,W,M,bits,dt,n", [(9, 13, 5, 12, np.uint16, 13), (32, 64, 16, 16, np.uint16, 40),
+                                             (7, 40, 3, 8, np.uint8, 10), (1, 1, 1, 12, np.uint16, 4)])
+def test_window_matches_brute_force_every_cycle(H, W, M, bits, dt, n):
+    need_gpu()
+    rng = np.random.default_rng(H * W + M)
+    say("window", H, W, M, bits, n)
+    cycles = [rng.integers(0, 1 << bits, size=(4, H, W)).astype(dt) for _ in range(n)]
+    win = qld.Window(H, W, M, dtype=torch.uint8 if dt == np.uint8 else torch.int16, bits=bits)
+    I = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    Q = torch.empty_like(I)
+    amp = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    for c, (oI, oQ, nin) in enumerate(oracle.window_series(cycles, M)):
+        warm = win.update(to_dev(cycles[c]), I, Q, amp)
+        torch.cuda.synchronize()
+        assert warm == (1 if c + 1 >= M else 0)
+        assert np.array_equal(I.cpu().numpy(), oI) and np.array_equal(Q.cpu().numpy(), oQ), c
+        assert amp_ulps(amp.cpu().numpy(), oracle.amplitude(oI, oQ)).max() <= 2.0
+    assert win.info() == (min(n, M), n)
+    win.close()
+
+
+def test_window_reset_and_checkpoint_resume():
+    need_gpu()
+    H, W, M = 12, 20, 6
+    rng = np.random.default_rng(5)
+    cycles = [rng.integers(0, 4096, size=(4, H, W)).astype(np.uint16) for _ in range(20)]
+    ref = list(oracle.window_series(cycles, M, resets=[8]))
+    win = qld.Window(H, W, M, bits=12)
+    I = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    Q = torch.empty_like(I)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "w.ckpt")
+        for c in range(20):
+            if c == 8:
+                win.reset()
+            if c == 14:
+                win.save(path)
+                win.close()
+                win = qld.Window(H, W, M, bits=12)
+                win.load(path)
+            win.update(to_dev(cycles[c]), I, Q)
+            torch.cuda.synchronize()
+            assert np.array_equal(I.cpu().numpy(), ref[c][0]) and np.array_equal(Q.cpu().numpy(), ref[c][1]), c
+        other = qld.Window(H, W + 1, M, bits=12)
+        with pytest.raises(qld.QldError) as e:
+            other.load(path)
+        assert e.value.status == qld.E_STATE
+    win.close()
+
+
+def test_window_sinusoid_closed_form():
+    need_gpu()
+    a, b, c0 = 3, -4, 50
+    cyc = np.broadcast_to(np.array([c0 + a, c0 + b, c0 - a, c0 - b], dtype=np.uint16)[:, None, None],
+                          (4, 3, 16)).copy()
+    win = qld.Window(3, 16, 7, bits=12)
+    I = torch.empty((3, 16), dtype=torch.int32, device="cuda")
+    Q = torch.empty_like(I)
+    amp = torch.empty((3, 16), dtype=torch.float32, device="cuda")
+    for k in range(12):
+        win.update(to_dev(cyc), I, Q, amp)
+        torch.cuda.synchronize()
+        n = min(k + 1, 7)
+        assert (I.cpu().numpy() == 2 * n * a).all() and (Q.cpu().numpy() == 2 * n * b).all()
+        assert (amp.cpu().numpy() == 2 * n * 5).all()
+
+
+# ---------------------------------------------------------------------------
+# Serving: alone vs in the mix, admission by budget, gaps.
+# ---------------------------------------------------------------------------
+
+def run_server(streams, n_cycles, M, budget=None, interleave=True, Ms=0):
+    """Submit ``n_cycles`` cycles of each (H, W, seed) stream; return per-stream
+    {cycle: (I, Q, amp[, Is, Qs])} read back right after each poll."""
+    need = 0
+    srv = qld.Server(budget or (1 << 34), out_slots=64, keep_iq=True)
+    ids = []
+    cams = []
+    for (H, W, seed) in streams:
+        sid, ok = srv.open(H, W, M, M_short=Ms, bits=16)
+        assert ok
+        ids.append(sid)
+        cams.append(scenes.CameraStream(H, W, seed, bits=16, bank=4))
+    out = {sid: {} for sid in ids}
+
+    def collect():
+        for r in srv.poll():
+            H, W = r.H, r.W
+            amp = qld.device_view(r.amp, (H, W), torch.float32).cpu().numpy().copy()
+            pI, pQ, pIs, pQs = srv.result_iq(r)
+            I = qld.device_view(pI, (H, W), torch.int32).cpu().numpy().copy()
+            Q = qld.device_view(pQ, (H, W), torch.int32).cpu().numpy().copy()
+            extra = ()
+            if Ms:
+                extra = (qld.device_view(pIs, (H, W), torch.int32).cpu().numpy().copy(),
+                         qld.device_view(pQs, (H, W), torch.int32).cpu().numpy().copy())
+            out[r.stream_id][r.cycle] = (I, Q, amp) + extra
+
+    frames = [[cam.cycle(c) for c in range(n_cycles)] for cam in cams]
+    order = [(c, j, s) for c in range(n_cycles) for j in range(4) for s in range(len(ids))] if interleave else \
+        [(c, j, s) for s in range(len(ids)) for c in range(n_cycles) for j in range(4)]
+    for (c, j, s) in order:
+        srv.submit(ids[s], frames[s][c][j], 4 * c + j, time.monotonic_ns())
+        if j == 3 and c % 8 == 7:
+            collect()
+    srv.drain()
+    collect()
+    st = srv.stats()
+    srv.close()
+    return [out[sid] for sid in ids], frames, st
+
+
+def test_server_alone_vs_mix_and_oracle():
+    need_gpu()
+    shapes = [(48, 80, 11), (96, 64, 12), (40, 136, 13)]
+    M, n = 6, 16
+    mixed, frames, st = run_server(shapes, n, M)
+    say("server stats", st)
+    assert st["cycles"] == 3 * n
+    for k, shp in enumerate(shapes):
+        alone, _, _ = run_server([shp], n, M)
+        for c in range(n):
+            for a, b in zip(alone[0][c], mixed[k][c]):
+                assert np.array_equal(a, b), (shp, c)
+        ref = list(oracle.window_series(frames[k], M))
+        for c in range(n):
+            I, Q, amp = mixed[k][c]
+            assert np.array_equal(I, ref[c][0]) and np.array_equal(Q, ref[c][1]), (shp, c)
+            assert amp_ulps(amp, oracle.amplitude(ref[c][0], ref[c][1])).max() <= 2.0
+
+
+def test_server_short_window_shares_ring():
+    need_gpu()
+    M, Ms, n = 8, 3, 14
+    res, frames, _ = run_server([(24, 40, 21)], n, M, Ms=Ms)
+    longw = list(oracle.window_series(frames[0], M))
+    shortw = list(oracle.window_series(frames[0], Ms))
+    for c in range(n):
+        I, Q, amp, Is, Qs = res[0][c]
+        assert np.array_equal(I, longw[c][0]) and np.array_equal(Is, shortw[c][0])
+        assert np.array_equal(Q, longw[c][1]) and np.array_equal(Qs, shortw[c][1])
+
+
+def test_server_admission_by_budget_and_gap_reset():
+    need_gpu()
+    srv = qld.Server(1 << 40, out_slots=4, keep_iq=True)
+    b_small = srv.stream_bytes(64, 64, 8, bits=16)
+    b_big = srv.stream_bytes(128, 128, 8, bits=16)
+    srv.close()
+    srv = qld.Server(b_big + b_small, out_slots=4, keep_iq=True)
+    s1, ok1 = srv.open(128, 128, 8, bits=16)
+    s2, ok2 = srv.open(64, 64, 8, bits=16)
+    s3, ok3 = srv.open(64, 64, 8, bits=16)
+    assert ok1 and ok2 and not ok3
+    assert srv.state(s3) == qld.STREAM_PENDING
+    cam = scenes.CameraStream(64, 64, 5, bits=16, bank=4)
+    assert srv.submit(s3, cam.cycle(0)[0], 0, 0) == qld.E_AGAIN
+    with pytest.raises(qld.QldError) as e:
+        qld.Server(1 << 20).open(4096, 4096, 64, bits=16)
+    assert e.value.status == qld.E_BUDGET
+    srv.close_stream(s1)
+    assert srv.state(s3) == qld.STREAM_ACTIVE
+    # Gap: frames 0..5 then 9.. -> the window restarts at cycle 3 (frame 12).
+    frames = [cam.cycle(c) for c in range(6)]
+    for f in range(6):
+        srv.submit(s3, frames[f // 4][f % 4], f, 0)
+    assert srv.submit(s3, frames[2][1], 9, 0) == qld.E_GAP
+    for f in range(10, 24):
+        srv.submit(s3, frames[f // 4][f % 4], f, 0)
+    srv.drain()
+    got = {}
+    for r in srv.poll():
+        pI, pQ, _, _ = srv.result_iq(r)
+        got[r.cycle] = qld.device_view(pI, (64, 64), torch.int32).cpu().numpy().copy()
+    assert sorted(got) == [0, 3, 4, 5]
+    ref = list(oracle.window_series([frames[3], frames[4], frames[5]], 8))
+    for k, c in enumerate((3, 4, 5)):
+        assert np.array_equal(got[c], ref[k][0])
+    assert np.array_equal(got[0], oracle.qld(frames[0])[0])
+    srv.close()

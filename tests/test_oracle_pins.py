@@ -156,8 +156,8 @@ def test_split_over_frames_and_phase_rotation():
 
 
 def test_overflow_edge_u16():
-    # Largest window an int32 accumulator holds for 16-bit data: M = 32767.
-    M = 32767
+    # Largest window an int32 accumulator holds for 16-bit data: 32768 * 65535 < 2^31 <= 32769 * 65535.
+    M = 32768
     series = np.tile(np.array([65535, 0, 0, 0], dtype=np.int64), M)
     I, Q = oracle.qld(stack_from_series(series))
     assert I[0, 0] == 65535 * M and I[0, 0] < 2 ** 31 and Q[0, 0] == 0
