@@ -9,19 +9,27 @@
 // I += S0 - S2 and Q += S1 - S3 per cycle: exact integer adds, no multiplies.
 //
 // Layout and mapping (gfx950, wave64):
-//   * one lane owns VPX adjacent pixels of one row: 16 uint8 or 8 uint16, read
-//     with one 16-byte load per frame (global_load_dwordx4), so a wave reads
-//     1 KiB per frame, fully coalesced;
-//   * int32 accumulators stay in VGPRs across the whole frame loop;
-//   * the frame axis can be split into chunks handled by different work-groups
-//     (for small images); chunk partials are combined with int32 atomics,
-//     which are exact and order-free.  The chunks of one pixel tile are placed
-//     on the same XCD (work-group ids are dealt round-robin over the 8 XCDs),
-//     so their atomics meet in one L2;
-//   * per-frame statistics (sum, saturated count) are reduced across the wave
-//     with DPP row shifts/broadcasts and a ballot popcount, buffered one value
-//     per lane for 64 frames, and written as per-wave partials that a second
-//     small kernel folds into frame_sum / frame_sat.
+//   * vector kernel: one lane owns 16 bytes of one row (8 uint16 or 16 uint8
+//     pixels) and reads them with one global_load_dwordx4 per frame, so a wave
+//     reads 1 KiB per frame, fully coalesced; rows are covered by whole 16-byte
+//     lanes only, and the ragged end of each row (W mod lane width pixels) goes
+//     to a scalar kernel (one lane per pixel), as do unaligned stacks;
+//   * the inner loop is branch-free; the I/Q differences are accumulated in
+//     packed 16-bit halves (v_pk_sub/v_pk_add) for up to 8 cycles of 12-bit
+//     data (128 cycles of 8-bit data) and then folded into int32 registers,
+//     which stay in VGPRs across the whole frame loop;
+//   * when the image alone does not fill the GPU, the cycles are dealt
+//     round-robin to S work-groups per pixel tile (cycle c to split c mod S),
+//     so the whole grid still sweeps the stack as one front; their partials
+//     are combined with int32 atomics (exact, order-free).  The splits of one
+//     tile sit on the same XCD (work-group ids are dealt round-robin over the
+//     8 XCDs), so their atomics meet in one L2;
+//   * per-frame statistics: the lane sum (v_dot2_u32_u16 / v_sad_u8) is reduced
+//     across the wave with DPP row shifts and row broadcasts, and written into
+//     lane `slot` of a buffer register that is stored every 64
+//     frames as per-wave partials; a small kernel folds them into frame_sum.
+//     Clipped samples are rare: a packed max per frame detects whether any
+//     sample reaches 2^bits - 1 and only then are they counted with ballots.
 #include "qld_internal.hpp"
 
 namespace qld {
@@ -31,61 +39,34 @@ constexpr int kBlock = 256;            // lanes per work-group (4 waves)
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kXcds = 8;
 
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
+// Reinterpret a 32-bit word as two 16-bit halves.  Takes the word by value:
+// a bit_cast applied directly to an element of a vector lvalue reads element
+// 0 with this compiler.
+__device__ __forceinline__ u16x2 h2(uint32_t w) { return __builtin_bit_cast(u16x2, w); }
+
 struct AccumArgs {
     const uint8_t *frames;
     int64_t rp_b;          // row pitch, bytes
     int64_t fs_b;          // frame stride, bytes
     int32_t H, W;
     int32_t n_frames;
-    int32_t chunk;         // frames per split (multiple of 4)
-    int32_t n_split;
+    int32_t n_split;       // work-groups per pixel tile; split s takes cycles s, s+n_split, ...
     int32_t rot;           // phase of frame 0, mod 4
-    int32_t nvx;           // lane vectors per row
-    int32_t n_tiles;       // work-group tiles over pixels
+    int32_t x_begin;       // first column this kernel covers
+    int32_t ncols;         // columns it covers (vector kernel: whole lanes only)
+    int32_t n_tiles;       // work-group tiles over its lanes
+    int32_t wave_base;     // first stats-partial row of this kernel
     uint32_t top;          // 2^bits - 1
     int32_t *I;
     int32_t *Q;
-    uint32_t *part_sum;    // [n_tiles * 4 waves][n_frames]
+    uint32_t *part_sum;    // [waves][n_frames]
     uint32_t *part_sat;
 };
 
-template <int ELEM, int VPX, bool VEC>
-__device__ __forceinline__ void load_px(const uint8_t *p, bool full, int nvalid, uint32_t (&v)[VPX]) {
-    if constexpr (VEC) {
-        if (full) {
-            const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-            const uint32_t w[4] = {q[0], q[1], q[2], q[3]};
-            if constexpr (ELEM == 2) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    v[2 * k] = w[k] & 0xffffu;
-                    v[2 * k + 1] = w[k] >> 16;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    v[4 * k] = w[k] & 0xffu;
-                    v[4 * k + 1] = (w[k] >> 8) & 0xffu;
-                    v[4 * k + 2] = (w[k] >> 16) & 0xffu;
-                    v[4 * k + 3] = w[k] >> 24;
-                }
-            }
-            return;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < VPX; ++k) {
-        if (k < nvalid) {
-            if constexpr (ELEM == 2) v[k] = reinterpret_cast<const uint16_t *>(p)[k];
-            else v[k] = p[k];
-        } else {
-            v[k] = 0;
-        }
-    }
-}
-
-// Sum of a 32-bit value over the 64 lanes of the wave, valid in lane 63.
-// Inclusive shifts inside each 16-lane row, then row broadcasts 15 and 31.
+// Sum of a 32-bit value over the 64 lanes of the wave, valid in lane 63:
+// inclusive shifts inside each 16-lane row, then row broadcasts 15 and 31.
 __device__ __forceinline__ uint32_t wave_sum_lane63(uint32_t v) {
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);  // row_shr:1
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);  // row_shr:2
@@ -96,126 +77,363 @@ __device__ __forceinline__ uint32_t wave_sum_lane63(uint32_t v) {
     return v;
 }
 
-template <int VPX>
-struct FrameStats {
-    uint32_t buf_sum = 0, buf_sat = 0;   // lane j holds the value of frame (group base + j)
-    int slot = 0;                        // frames buffered in the current 64-frame group
-    int64_t base = 0;                    // chunk-relative index of the group's first frame
+// Per-wave, per-frame statistics buffered one frame per lane.
+struct Stats {
+    uint32_t buf_sum = 0, buf_sat = 0;   // lane j: values of the j-th buffered frame
+    uint32_t buf_t = 0;                  // lane j: that frame's index
+    int slot = 0;                        // frames buffered (uniform)
+    int64_t row;                         // partial index of frame 0 for this wave
 
-    __device__ __forceinline__ void add(const uint32_t (&v)[VPX], uint32_t top, int lane) {
-        uint32_t s = 0, c = 0;
-#pragma unroll
-        for (int k = 0; k < VPX; ++k) {
-            s += v[k];
-            c += (uint32_t)__popcll(__ballot(v[k] == top));
-        }
-        uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_sum_lane63(s), 63);
-        if (lane == slot) {
-            buf_sum = tot;
-            buf_sat = c;
-        }
-        ++slot;
+    __device__ __forceinline__ void put(uint32_t lane_sum, uint32_t wave_sat, uint32_t t) {
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_sum_lane63(lane_sum), 63);
+        // Lane `slot` of the buffer registers takes the (uniform) values.
+        const bool mine = (int)(threadIdx.x & 63) == slot;
+        buf_sum = mine ? tot : buf_sum;
+        buf_sat = mine ? wave_sat : buf_sat;
+        buf_t = mine ? t : buf_t;
+        if (++slot == 64) flush();
     }
 
-    __device__ __forceinline__ void flush(uint32_t *ps, uint32_t *pc, int64_t row, int lane) {
+    __device__ __forceinline__ void flush() {
+        const int lane = (int)(threadIdx.x & 63);
         if (lane < slot) {
-            ps[row + base + lane] = buf_sum;
-            pc[row + base + lane] = buf_sat;
+            part_sum[row + buf_t] = buf_sum;
+            part_sat[row + buf_t] = buf_sat;
         }
-        base += slot;
         slot = 0;
+    }
+
+    uint32_t *part_sum, *part_sat;
+};
+
+// ---------------------------------------------------------------------------
+// Vector kernel: 16 bytes per lane.
+// ---------------------------------------------------------------------------
+template <int ELEM>
+struct Lane16 {
+    static constexpr int kPx = 16 / ELEM;
+};
+
+// Counts samples equal to top in one 16-byte group (exact; wave total).
+template <int ELEM>
+__device__ __forceinline__ uint32_t count_top(const u32x4 &d, uint32_t top) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if constexpr (ELEM == 2) {
+            c += (uint32_t)__popcll(__ballot((d[k] & 0xffffu) == top));
+            c += (uint32_t)__popcll(__ballot((d[k] >> 16) == top));
+        } else {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) c += (uint32_t)__popcll(__ballot(((d[k] >> (8 * b)) & 0xffu) == top));
+        }
+    }
+    return c;
+}
+
+template <int ELEM, bool STATS>
+__device__ __forceinline__ void frame_stats(const u32x4 &d, uint32_t top, Stats &st, uint32_t t) {
+    uint32_t s;
+    uint32_t m;
+    if constexpr (ELEM == 2) {
+        const u16x2 one = {1, 1};
+        s = __builtin_amdgcn_udot2(h2(d[0]), one, 0u, false);
+        s = __builtin_amdgcn_udot2(h2(d[1]), one, s, false);
+        s = __builtin_amdgcn_udot2(h2(d[2]), one, s, false);
+        s = __builtin_amdgcn_udot2(h2(d[3]), one, s, false);
+        u16x2 mx = __builtin_elementwise_max(__builtin_elementwise_max(h2(d[0]),
+                                                                       h2(d[1])),
+                                             __builtin_elementwise_max(h2(d[2]),
+                                                                       h2(d[3])));
+        m = max((uint32_t)mx[0], (uint32_t)mx[1]);
+    } else {
+        s = __builtin_amdgcn_sad_u8(d[0], 0u, 0u);
+        s = __builtin_amdgcn_sad_u8(d[1], 0u, s);
+        s = __builtin_amdgcn_sad_u8(d[2], 0u, s);
+        s = __builtin_amdgcn_sad_u8(d[3], 0u, s);
+        // Largest byte: even and odd bytes widened to 16-bit halves, packed max.
+        const uint32_t b = 0x00ff00ffu;
+        u16x2 mx = h2(d[0] & b);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k) mx = __builtin_elementwise_max(mx, h2(d[k] & b));
+            mx = __builtin_elementwise_max(mx, h2((d[k] >> 8) & b));
+        }
+        m = max((uint32_t)mx[0], (uint32_t)mx[1]);
+    }
+    uint32_t c = 0;
+    if (__ballot(m >= top)) c = count_top<ELEM>(d, top);   // rare: clipped samples present
+    st.put(s, c, t);
+}
+
+// Accumulators of one lane: int32 I/Q per pixel plus packed 16-bit partials.
+template <int ELEM>
+struct Acc {
+    static constexpr int kPx = 16 / ELEM;
+    int32_t I[kPx], Q[kPx];
+    // ELEM == 2: 4 words, word k = pixels (2k, 2k+1).
+    // ELEM == 1: 8 words, word k<4 = pixels (4k, 4k+2), word 4+k = (4k+1, 4k+3).
+    u16x2 pi[ELEM == 2 ? 4 : 8], pq[ELEM == 2 ? 4 : 8];
+
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < kPx; ++k) I[k] = Q[k] = 0;
+        clear_packed();
+    }
+    __device__ __forceinline__ void clear_packed() {
+#pragma unroll
+        for (int k = 0; k < (ELEM == 2 ? 4 : 8); ++k) pi[k] = pq[k] = u16x2{0, 0};
+    }
+    // Fold the packed 16-bit partials (two's complement) into int32.
+    __device__ __forceinline__ void fold() {
+#pragma unroll
+        for (int k = 0; k < (ELEM == 2 ? 4 : 8); ++k) {
+            const int32_t i0 = (int16_t)pi[k][0], i1 = (int16_t)pi[k][1];
+            const int32_t q0 = (int16_t)pq[k][0], q1 = (int16_t)pq[k][1];
+            int a, b;
+            if constexpr (ELEM == 2) {
+                a = 2 * k;
+                b = 2 * k + 1;
+            } else {
+                a = k < 4 ? 4 * k : 4 * (k - 4) + 1;
+                b = a + 2;
+            }
+            I[a] += i0;
+            I[b] += i1;
+            Q[a] += q0;
+            Q[b] += q1;
+        }
+        clear_packed();
+    }
+    // One cycle S0..S3 of packed words: I += S0 - S2, Q += S1 - S3 (mod 2^16 per half).
+    __device__ __forceinline__ void cycle(const u32x4 &s0, const u32x4 &s1, const u32x4 &s2, const u32x4 &s3) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if constexpr (ELEM == 2) {
+                pi[k] += h2(s0[k]) - h2(s2[k]);
+                pq[k] += h2(s1[k]) - h2(s3[k]);
+            } else {
+                const uint32_t m = 0x00ff00ffu;
+                pi[k] += h2(s0[k] & m) - h2(s2[k] & m);
+                pq[k] += h2(s1[k] & m) - h2(s3[k] & m);
+                pi[4 + k] += h2((s0[k] >> 8) & m) - h2((s2[k] >> 8) & m);
+                pq[4 + k] += h2((s1[k] >> 8) & m) - h2((s3[k] >> 8) & m);
+            }
+        }
+    }
+    // Unpacked update of one frame with coefficient +1 into I (ci=1), Q (cq=1), or -1.
+    __device__ __forceinline__ void frame32(const u32x4 &d, int ci, int cq) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if constexpr (ELEM == 2) {
+                const int32_t lo = (int32_t)(d[k] & 0xffffu), hi = (int32_t)(d[k] >> 16);
+                I[2 * k] += ci * lo;
+                I[2 * k + 1] += ci * hi;
+                Q[2 * k] += cq * lo;
+                Q[2 * k + 1] += cq * hi;
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int32_t v = (int32_t)((d[k] >> (8 * b)) & 0xffu);
+                    I[4 * k + b] += ci * v;
+                    Q[4 * k + b] += cq * v;
+                }
+            }
+        }
     }
 };
 
-template <int ELEM, int VPX, bool VEC, bool STATS>
-__global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
+__device__ __forceinline__ u32x4 ld16(const uint8_t *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+}
+
+// PACKED: 16-bit partials hold `fold_every` cycles without overflow
+// (fold_every * (2^bits - 1) <= 32767); otherwise every cycle goes to int32.
+// MASKED: some lanes of this work-group are past the last vector; they read
+// a valid address and zero what they read.
+template <int ELEM, bool STATS, bool PACKED, bool MASKED>
+__device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split) {
+    constexpr int kPx = 16 / ELEM;
+    const int nvx = a.ncols / kPx;
+    const int64_t n_vec = (int64_t)nvx * a.H;
+    const int64_t g = (int64_t)tile * kBlock + threadIdx.x;
+    const bool valid = !MASKED || g < n_vec;
+    const int64_t gc = valid ? g : (int64_t)tile * kBlock;     // lane 0 of the tile is always valid
+    const int64_t y = gc / nvx;
+    const int x0 = a.x_begin + (int)(gc % nvx) * kPx;
+    const uint32_t vmask = valid ? 0xffffffffu : 0u;
+
+    // This work-group owns cycles split, split + S, split + 2S, ... (S = n_split),
+    // so all work-groups sweep the stack together.
+    const int64_t S = a.n_split;
+    const int64_t n_cyc_all = a.n_frames >> 2;
+    const int64_t my = split < n_cyc_all ? (n_cyc_all - split + S - 1) / S : 0;
+    const int64_t fs = a.fs_b;
+    const int64_t step = 4 * S * fs;
+    const uint8_t *p = a.frames + y * a.rp_b + (int64_t)x0 * ELEM + 4 * (int64_t)split * fs;
+
+    Acc<ELEM> acc;
+    acc.zero();
+    Stats st;
+    if constexpr (STATS) {
+        st.part_sum = a.part_sum;
+        st.part_sat = a.part_sat;
+        st.row = ((int64_t)a.wave_base + (int64_t)tile * kWavesPerBlock + (threadIdx.x >> 6)) * a.n_frames;
+    }
+    auto load = [&](const uint8_t *q) {
+        u32x4 d = ld16(q);
+        if constexpr (MASKED) d &= vmask;
+        return d;
+    };
+    const int fold_every = ELEM == 2 ? (int)(32767u / max(a.top, 1u)) : 128;
+
+    int since_fold = 0;
+    auto process = [&](const u32x4 &s0, const u32x4 &s1, const u32x4 &s2, const u32x4 &s3, int64_t k) {
+        if constexpr (PACKED) {
+            acc.cycle(s0, s1, s2, s3);
+            if (++since_fold == fold_every) {
+                acc.fold();
+                since_fold = 0;
+            }
+        } else {
+            acc.frame32(s0, 1, 0);
+            acc.frame32(s1, 0, 1);
+            acc.frame32(s2, -1, 0);
+            acc.frame32(s3, 0, -1);
+        }
+        if constexpr (STATS) {
+            const uint32_t t = (uint32_t)(4 * (split + k * S));
+            frame_stats<ELEM, STATS>(s0, a.top, st, t);
+            frame_stats<ELEM, STATS>(s1, a.top, st, t + 1);
+            frame_stats<ELEM, STATS>(s2, a.top, st, t + 2);
+            frame_stats<ELEM, STATS>(s3, a.top, st, t + 3);
+        }
+    };
+    // One cycle (four frames, 4 x 16 B per lane) per iteration.  Measured on
+    // MI355X: keeping only four frames in flight per wave streams faster than
+    // deeper unrolling or register double-buffering (fewer DRAM pages open).
+    for (int64_t k = 0; k < my; ++k) {
+        const u32x4 s0 = load(p), s1 = load(p + fs), s2 = load(p + 2 * fs), s3 = load(p + 3 * fs);
+        p += step;
+        process(s0, s1, s2, s3, k);
+    }
+    if constexpr (PACKED) acc.fold();
+    // Partial cycle at the end of the stack: taken by the split next in turn.
+    const int rem = (int)(a.n_frames & 3);
+    if (rem && split == (int)(n_cyc_all % S)) {
+        const uint8_t *q = a.frames + y * a.rp_b + (int64_t)x0 * ELEM + 4 * n_cyc_all * fs;
+        for (int j = 0; j < rem; ++j) {
+            const u32x4 s = load(q + j * fs);
+            acc.frame32(s, j == 0 ? 1 : (j == 2 ? -1 : 0), j == 1 ? 1 : 0);
+            if constexpr (STATS) frame_stats<ELEM, STATS>(s, a.top, st, (uint32_t)(4 * n_cyc_all + j));
+        }
+    }
+    if constexpr (STATS) {
+        if (st.slot) st.flush();
+    }
+
+    if (!valid) return;
+    int32_t *Ip = a.I + y * a.W + x0;
+    int32_t *Qp = a.Q + y * a.W + x0;
+#pragma unroll
+    for (int k = 0; k < kPx; ++k) {
+        int32_t oi, oq;
+        rotate_iq(a.rot, acc.I[k], acc.Q[k], oi, oq);
+        if (a.n_split > 1) {
+            atomicAdd(Ip + k, oi);
+            atomicAdd(Qp + k, oq);
+        } else {
+            Ip[k] += oi;
+            Qp[k] += oq;
+        }
+    }
+}
+
+__device__ __forceinline__ void tile_and_split(const AccumArgs &a, int &tile, int &split) {
     // Work-group id -> (pixel tile, frame chunk), chunks of a tile on one XCD.
     const int b = blockIdx.x;
     const int xcd = b % kXcds;
     const int q = b / kXcds;
-    const int split = q % a.n_split;
-    const int tile = (q / a.n_split) * kXcds + xcd;
+    split = q % a.n_split;
+    tile = (q / a.n_split) * kXcds + xcd;
+}
+
+template <int ELEM, bool STATS, bool PACKED>
+__global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
+    int tile, split;
+    tile_and_split(a, tile, split);
     if (tile >= a.n_tiles) return;
+    const int64_t n_vec = (int64_t)(a.ncols / (16 / ELEM)) * a.H;
+    if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split);
+    else vec_body<ELEM, STATS, PACKED, true>(a, tile, split);
+}
 
-    const int lane = threadIdx.x & 63;
+// ---------------------------------------------------------------------------
+// Scalar kernel: one pixel per lane (row tails and unaligned stacks).
+// ---------------------------------------------------------------------------
+template <int ELEM, bool STATS>
+__global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
+    int tile, split;
+    tile_and_split(a, tile, split);
+    if (tile >= a.n_tiles) return;
+    const int64_t n_px = (int64_t)a.ncols * a.H;
     const int64_t g = (int64_t)tile * kBlock + threadIdx.x;
-    const int64_t y = g / a.nvx;
-    const int x0 = (int)(g % a.nvx) * VPX;
-    const bool row_ok = y < a.H;
-    const int nvalid = row_ok ? min(VPX, a.W - x0) : 0;
-    const bool full = nvalid == VPX;
-
-    const int64_t t0 = (int64_t)split * a.chunk;
-    const int64_t t1 = min((int64_t)a.n_frames, t0 + a.chunk);
-    const int64_t len = t1 - t0;
-    const uint8_t *p = a.frames + (row_ok ? (y * a.rp_b + (int64_t)x0 * ELEM + t0 * a.fs_b) : 0);
+    const bool valid = g < n_px;
+    const int64_t gc = valid ? g : 0;
+    const int64_t y = gc / a.ncols;
+    const int x = a.x_begin + (int)(gc % a.ncols);
+    const int64_t S = a.n_split;
+    const int64_t n_cyc_all = a.n_frames >> 2;
     const int64_t fs = a.fs_b;
+    const uint8_t *base = a.frames + y * a.rp_b + (int64_t)x * ELEM;
+    const uint32_t vmask = valid ? 0xffffffffu : 0u;
+    auto load = [&](int64_t t) {
+        const uint8_t *q = base + t * fs;
+        return (ELEM == 2 ? (uint32_t)*reinterpret_cast<const uint16_t *>(q) : (uint32_t)*q) & vmask;
+    };
 
-    int32_t accI[VPX], accQ[VPX];
-#pragma unroll
-    for (int k = 0; k < VPX; ++k) accI[k] = accQ[k] = 0;
-
-    FrameStats<VPX> st;
-    const int64_t wave_row = ((int64_t)tile * kWavesPerBlock + (threadIdx.x >> 6)) * a.n_frames + t0;
-
-    const int64_t n_cyc = len >> 2;
-    for (int64_t c = 0; c < n_cyc; ++c) {
-        uint32_t s0[VPX], s1[VPX], s2[VPX], s3[VPX];
-        load_px<ELEM, VPX, VEC>(p, full, nvalid, s0);
-        load_px<ELEM, VPX, VEC>(p + fs, full, nvalid, s1);
-        load_px<ELEM, VPX, VEC>(p + 2 * fs, full, nvalid, s2);
-        load_px<ELEM, VPX, VEC>(p + 3 * fs, full, nvalid, s3);
-        p += 4 * fs;
-#pragma unroll
-        for (int k = 0; k < VPX; ++k) {
-            accI[k] += (int32_t)s0[k] - (int32_t)s2[k];
-            accQ[k] += (int32_t)s1[k] - (int32_t)s3[k];
-        }
+    Stats st;
+    if constexpr (STATS) {
+        st.part_sum = a.part_sum;
+        st.part_sat = a.part_sat;
+        st.row = ((int64_t)a.wave_base + (int64_t)tile * kWavesPerBlock + (threadIdx.x >> 6)) * a.n_frames;
+    }
+    int32_t I = 0, Q = 0;
+    // Cycles split, split + S, ... (all work-groups sweep the stack together).
+    for (int64_t c = split; c < n_cyc_all; c += S) {
+        const uint32_t v0 = load(4 * c), v1 = load(4 * c + 1), v2 = load(4 * c + 2), v3 = load(4 * c + 3);
+        I += (int32_t)v0 - (int32_t)v2;
+        Q += (int32_t)v1 - (int32_t)v3;
         if constexpr (STATS) {
-            st.add(s0, a.top, lane);
-            st.add(s1, a.top, lane);
-            st.add(s2, a.top, lane);
-            st.add(s3, a.top, lane);
-            if (st.slot == 64) st.flush(a.part_sum, a.part_sat, wave_row, lane);
+            st.put(v0, (uint32_t)__popcll(__ballot(valid && v0 == a.top)), (uint32_t)(4 * c));
+            st.put(v1, (uint32_t)__popcll(__ballot(valid && v1 == a.top)), (uint32_t)(4 * c + 1));
+            st.put(v2, (uint32_t)__popcll(__ballot(valid && v2 == a.top)), (uint32_t)(4 * c + 2));
+            st.put(v3, (uint32_t)__popcll(__ballot(valid && v3 == a.top)), (uint32_t)(4 * c + 3));
         }
     }
-    // Partial cycle at the end of the stack (only the last chunk has one).
-    const int rem = (int)(len & 3);
-    for (int j = 0; j < rem; ++j) {
-        uint32_t s[VPX];
-        load_px<ELEM, VPX, VEC>(p, full, nvalid, s);
-        p += fs;
-#pragma unroll
-        for (int k = 0; k < VPX; ++k) {
-            if (j == 0) accI[k] += (int32_t)s[k];
-            else if (j == 1) accQ[k] += (int32_t)s[k];
-            else accI[k] -= (int32_t)s[k];
-        }
-        if constexpr (STATS) {
-            st.add(s, a.top, lane);
-            if (st.slot == 64) st.flush(a.part_sum, a.part_sat, wave_row, lane);
+    const int rem = (int)(a.n_frames & 3);
+    if (rem && split == (int)(n_cyc_all % S)) {
+        for (int j = 0; j < rem; ++j) {
+            const int64_t t = 4 * n_cyc_all + j;
+            const uint32_t v = load(t);
+            if (j == 0) I += (int32_t)v;
+            else if (j == 1) Q += (int32_t)v;
+            else I -= (int32_t)v;
+            if constexpr (STATS) st.put(v, (uint32_t)__popcll(__ballot(valid && v == a.top)), (uint32_t)t);
         }
     }
     if constexpr (STATS) {
-        if (st.slot) st.flush(a.part_sum, a.part_sat, wave_row, lane);
+        if (st.slot) st.flush();
     }
-
-    if (!row_ok) return;
-    int32_t *Ip = a.I + y * a.W + x0;
-    int32_t *Qp = a.Q + y * a.W + x0;
-#pragma unroll
-    for (int k = 0; k < VPX; ++k) {
-        if (k < nvalid) {
-            int32_t oi, oq;
-            rotate_iq(a.rot, accI[k], accQ[k], oi, oq);
-            if (a.n_split > 1) {
-                atomicAdd(Ip + k, oi);
-                atomicAdd(Qp + k, oq);
-            } else {
-                Ip[k] += oi;
-                Qp[k] += oq;
-            }
-        }
+    if (!valid) return;
+    int32_t oi, oq;
+    rotate_iq(a.rot, I, Q, oi, oq);
+    if (a.n_split > 1) {
+        atomicAdd(a.I + y * a.W + x, oi);
+        atomicAdd(a.Q + y * a.W + x, oq);
+    } else {
+        a.I[y * a.W + x] += oi;
+        a.Q[y * a.W + x] += oq;
     }
 }
 
@@ -251,10 +469,32 @@ __global__ __launch_bounds__(256) void qld_amplitude_kernel(const int32_t *__res
     }
 }
 
-template <int ELEM, int VPX, bool VEC, bool STATS>
-hipError_t launch_accum(const AccumArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((qld_accum_kernel<ELEM, VPX, VEC, STATS>), dim3(grid), dim3(kBlock), 0, s, a);
+template <int ELEM, bool STATS>
+hipError_t launch_vec(const AccumArgs &a, bool packed, int grid, hipStream_t s) {
+    if (packed) hipLaunchKernelGGL((qld_accum_kernel<ELEM, STATS, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((qld_accum_kernel<ELEM, STATS, false>), dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
+}
+
+template <int ELEM, bool STATS>
+hipError_t launch_scalar(const AccumArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((qld_accum_scalar_kernel<ELEM, STATS>), dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// Frame-axis split: only until the grid holds QLD_ACCUM_BLOCKS_PER_CU
+// work-groups per CU, with at least 16 cycles per work-group.  Measured on
+// MI355X with 2 MiB frames: one pass over the frames at 1-2 work-groups per CU
+// streams fastest (the whole grid sweeps the stack as one front).
+#ifndef QLD_ACCUM_BLOCKS_PER_CU
+#define QLD_ACCUM_BLOCKS_PER_CU 2
+#endif
+int32_t choose_split(int64_t n_tiles, int32_t n_frames) {
+    const int64_t want_blocks = (int64_t)QLD_ACCUM_BLOCKS_PER_CU * device_cu_count();
+    int64_t ns = 1;
+    if (n_tiles < want_blocks) ns = ceil_div(want_blocks, n_tiles);
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, (n_frames / 4) / 16));
+    return (int32_t)ns;
 }
 
 }  // namespace
@@ -288,7 +528,9 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
     const uintptr_t base = reinterpret_cast<uintptr_t>(frames);
     const int64_t rp_b = d->row_pitch * eb, fs_b = d->frame_stride * eb;
     const bool vec = (base % 16 == 0) && (rp_b % 16 == 0) && (fs_b % 16 == 0);
-    const int vpx = vec ? 16 / eb : 1;
+    const int lw = 16 / eb;                                 // pixels per vector lane
+    const int vcols = vec ? (d->W / lw) * lw : 0;           // columns of the vector kernel
+    const int scols = d->W - vcols;                         // columns of the scalar kernel
 
     AccumArgs a{};
     a.frames = static_cast<const uint8_t *>(frames);
@@ -298,40 +540,47 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
     a.W = d->W;
     a.n_frames = n_frames;
     a.rot = ((phase0 % 4) + 4) % 4;
-    a.nvx = (int32_t)ceil_div(d->W, vpx);
-    const int64_t n_vec = (int64_t)a.nvx * d->H;
-    const int64_t n_tiles = ceil_div(n_vec, kBlock);
-    if (n_tiles > (1ll << 24)) {
-        set_error("image too large (%lld tiles)", (long long)n_tiles);
-        return QLD_E_SHAPE;
-    }
-    a.n_tiles = (int32_t)n_tiles;
     a.top = (uint32_t)top;
     a.I = I;
     a.Q = Q;
 
-    // Split the frame axis until the grid holds ~8 work-groups per CU, keeping
-    // chunks of at least 64 frames.
-    const int64_t want_blocks = 8ll * device_cu_count();
-    int64_t n_split = 1;
-    if (n_tiles < want_blocks) n_split = ceil_div(want_blocks, n_tiles);
-    n_split = std::max<int64_t>(1, std::min<int64_t>(n_split, n_frames / 64));
-    int64_t chunk = ceil_div(ceil_div(n_frames, n_split), 4) * 4;
-    n_split = ceil_div(n_frames, chunk);
-    a.chunk = (int32_t)chunk;
-    a.n_split = (int32_t)n_split;
+    AccumArgs av = a, as = a;
+    const int64_t vt = vcols ? ceil_div((int64_t)(vcols / lw) * d->H, kBlock) : 0;
+    const int64_t st = scols ? ceil_div((int64_t)scols * d->H, kBlock) : 0;
+    if (vt > (1ll << 24) || st > (1ll << 24)) {
+        set_error("image too large");
+        return QLD_E_SHAPE;
+    }
+    av.x_begin = 0;
+    av.ncols = vcols;
+    av.n_tiles = (int32_t)vt;
+    av.wave_base = 0;
+    as.x_begin = vcols;
+    as.ncols = scols;
+    as.n_tiles = (int32_t)st;
+    as.wave_base = (int32_t)(vt * kWavesPerBlock);
+    av.n_split = choose_split(vt + st, n_frames);
+    as.n_split = av.n_split;
+    if (av.n_split > 1) {
+        // Chunks accumulate with atomics; other callers' I/Q contents are kept (+=).
+    }
 
     const bool stats = frame_sum || frame_sat;
-    const int64_t n_waves = n_tiles * kWavesPerBlock;
+    const int64_t n_waves = (vt + st) * kWavesPerBlock;
     if (stats) {
         size_t need = sizeof(uint32_t) * 2 * (size_t)n_waves * (size_t)n_frames;
         void *ws = stream_workspace(s, need);
         if (!ws) return QLD_E_NOMEM;
-        a.part_sum = static_cast<uint32_t *>(ws);
-        a.part_sat = a.part_sum + (size_t)n_waves * n_frames;
+        uint32_t *ps = static_cast<uint32_t *>(ws);
+        uint32_t *pc = ps + (size_t)n_waves * n_frames;
+        av.part_sum = as.part_sum = ps;
+        av.part_sat = as.part_sat = pc;
     }
-    const int64_t grid = ceil_div(n_tiles, kXcds) * kXcds * n_split;
-    if (grid > 0x7fffffff) {
+    // 16-bit partial sums hold at least two cycles for data of up to 14 bits.
+    const bool packed = eb == 1 || top <= 16383;
+    const int64_t gv = ceil_div(vt, kXcds) * kXcds * av.n_split;
+    const int64_t gs = ceil_div(st, kXcds) * kXcds * as.n_split;
+    if (gv > 0x7fffffff || gs > 0x7fffffff) {
         set_error("grid too large");
         return QLD_E_SHAPE;
     }
@@ -339,19 +588,21 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
     hipEvent_t ev0, ev1;
     take_kernel_timer(&ev0, &ev1);
     if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
-    hipError_t e;
-    if (eb == 2) {
-        if (vec) e = stats ? launch_accum<2, 8, true, true>(a, (int)grid, s) : launch_accum<2, 8, true, false>(a, (int)grid, s);
-        else e = stats ? launch_accum<2, 1, false, true>(a, (int)grid, s) : launch_accum<2, 1, false, false>(a, (int)grid, s);
-    } else {
-        if (vec) e = stats ? launch_accum<1, 16, true, true>(a, (int)grid, s) : launch_accum<1, 16, true, false>(a, (int)grid, s);
-        else e = stats ? launch_accum<1, 1, false, true>(a, (int)grid, s) : launch_accum<1, 1, false, false>(a, (int)grid, s);
+    hipError_t e = hipSuccess;
+    if (vt > 0) {
+        if (eb == 2) e = stats ? launch_vec<2, true>(av, packed, (int)gv, s) : launch_vec<2, false>(av, packed, (int)gv, s);
+        else e = stats ? launch_vec<1, true>(av, packed, (int)gv, s) : launch_vec<1, false>(av, packed, (int)gv, s);
+        QLD_TRY(check_hip(e, "qld_accum_kernel launch"));
     }
-    QLD_TRY(check_hip(e, "qld_accum_kernel launch"));
     if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
+    if (st > 0) {
+        if (eb == 2) e = stats ? launch_scalar<2, true>(as, (int)gs, s) : launch_scalar<2, false>(as, (int)gs, s);
+        else e = stats ? launch_scalar<1, true>(as, (int)gs, s) : launch_scalar<1, false>(as, (int)gs, s);
+        QLD_TRY(check_hip(e, "qld_accum_scalar_kernel launch"));
+    }
     if (stats) {
         dim3 g2((unsigned)ceil_div(n_frames, 64), (unsigned)ceil_div(n_waves, kRowsPerBlock));
-        hipLaunchKernelGGL(qld_stats_reduce_kernel, g2, dim3(64), 0, s, a.part_sum, a.part_sat, n_waves,
+        hipLaunchKernelGGL(qld_stats_reduce_kernel, g2, dim3(64), 0, s, av.part_sum, av.part_sat, n_waves,
                            n_frames, frame_sum, frame_sat);
         QLD_TRY(check_hip(hipGetLastError(), "qld_stats_reduce_kernel launch"));
     }

@@ -19,6 +19,9 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;
+#ifndef QLD_DFT_BLOCKS_PER_CU
+#define QLD_DFT_BLOCKS_PER_CU 2
+#endif
 
 struct DftArgs {
     const uint8_t *frames;
@@ -208,7 +211,9 @@ extern "C" qld_status dft_bin_baseline(const void *frames, const qld_frame_desc 
         return QLD_E_SHAPE;
     }
     a.n_tiles = (int32_t)n_tiles;
-    const int64_t want_blocks = 8ll * device_cu_count();
+    // Same grid policy as the lock-in accumulation: split the frame axis only
+    // until the grid holds QLD_DFT_BLOCKS_PER_CU work-groups per CU.
+    const int64_t want_blocks = (int64_t)QLD_DFT_BLOCKS_PER_CU * device_cu_count();
     int64_t n_split = 1;
     if (n_tiles < want_blocks) n_split = ceil_div(want_blocks, n_tiles);
     n_split = std::max<int64_t>(1, std::min<int64_t>(n_split, n_frames / 64));
