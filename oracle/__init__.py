@@ -4,9 +4,11 @@ TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
 with the HIP library in ``paper_1511_03390_amd`` and never imports it.
 
-The arithmetic lives in ``qld_oracle.c`` (plain C, built with gcc -O2, no
-fast-math); this module loads it with ctypes and adds the brute-force sliding
-window, which re-sums the stored history of frames at every step.
+The arithmetic lives in ``qld_oracle.c`` and ``gen_oracle.c`` (plain C, built
+with gcc -O2, no fast-math); this module loads them with ctypes and adds the
+brute-force sliding window, which re-sums the stored history of frames at
+every step.  ``oracle.learned`` holds the training-pair generator and the
+denoiser (numpy, double precision).
 
 Functions:
     qld(frames, phase0=0)            -> (I, Q) int64       (Methods, R(j,k))
@@ -24,7 +26,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "qld_oracle.c")
+_SRCS = [os.path.join(_HERE, "qld_oracle.c"), os.path.join(_HERE, "gen_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -35,11 +37,11 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 
 
 def build(force: bool = False) -> str:
-    """Compile qld_oracle.c into liboracle.so with gcc (always when force)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the oracle's C sources into liboracle.so with gcc (always when force)."""
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
+               "-ffp-contract=off", "-fno-fast-math", *_SRCS, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -62,6 +64,18 @@ def _load():
                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                        _f64p, _f64p, ctypes.c_int]
         lib.oracle_reference_tables.argtypes = [_i64p, _i64p]
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        lib.oracle_philox4x32.argtypes = [u32p, u32p, ctypes.c_int, u32p]
+        lib.oracle_philox4x32.restype = None
+        lib.oracle_poisson_bounds.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]
+        lib.oracle_poisson_table.argtypes = [ctypes.c_double, u32p, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32)]
+        lib.oracle_poisson_invert.argtypes = [u32p, ctypes.c_int, ctypes.c_int32, ctypes.c_uint32]
+        lib.oracle_poisson_invert.restype = ctypes.c_int32
+        lib.oracle_gen_frames.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
         _lib = lib
     return _lib
 
