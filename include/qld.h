@@ -253,6 +253,101 @@ qld_status qld_server_stats(const qld_server *s, int64_t *batches, int64_t *cycl
                             int32_t *max_streams_in_batch, size_t *bytes_in_use);
 
 /* ------------------------------------------------------------------------ */
+/* Learned short-window path (not in the paper): training pairs, denoiser,  */
+/* gate, judges.  Plain QLD is the fallback and the judge.                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * qld_gen_pairs -- training pairs generated by the lock-in itself.  Tile i is
+ * a synthetic stack of Poisson frames (four samples per modulation period)
+ * that is never stored: sample (t, y, x) = min(X_lambda(u), 2^bits - 1) with
+ * lambda = rates_host[i][mask(y,x)][t mod 4] and u = word (t mod 4) of
+ * Philox4x32-10(counter = (y*W + x, t / 4, tile0 + i, 0), key = seed), X the
+ * Poisson inversion defined in the library source.  The lock-in sums of its
+ * first M_short cycles go to I_S, Q_S and of its first M_long cycles to
+ * I_L, Q_L (Methods, R(j,k)); sum_S / sum_L receive the tile's sample sums
+ * over the same windows.
+ *   mask       device uint8 [n_tiles][H][W] (0 or 1)
+ *   rates_host HOST double [n_tiles][2][4], each in (0, 6000]
+ *   outputs    device int32 [n_tiles][H][W]; uint64 [n_tiles] (overwritten)
+ * QLD_E_OVERFLOW if M_long * 4 * (2^bits - 1) >= 2^32.
+ */
+qld_status qld_gen_pairs(const uint8_t *mask, const double *rates_host, int32_t n_tiles, int32_t H,
+                         int32_t W, int32_t M_short, int32_t M_long, uint32_t tile0, uint64_t seed,
+                         int32_t bits, int32_t *I_S, int32_t *Q_S, int32_t *I_L, int32_t *Q_L,
+                         uint64_t *sum_S, uint64_t *sum_L, qld_hip_stream stream);
+
+/*
+ * Network input of the denoiser from a short window: x = (I, Q) / (sigma sqrt(M)),
+ * sigma^2 = 2 b, b = sum / (H W 4 M) the mean sample level (the Poisson noise
+ * of one quadrature per cycle has variance 2 b); scale[i] = sigma / sqrt(M)
+ * converts the network output to counts per cycle.
+ *   I_S, Q_S device int32 [B][H][W]; sum_S device uint64 [B];
+ *   x device float [B][H][W][2]; scale device float [B]  (overwritten)
+ */
+qld_status qld_denoise_prepare(const int32_t *I_S, const int32_t *Q_S, const uint64_t *sum_S,
+                               int32_t M_S, int32_t B, int32_t H, int32_t W, float *x, float *scale,
+                               qld_hip_stream stream);
+
+/* Training target: long-window amplitude per cycle with its noise power
+ * removed, in network units: t = sqrt(max(I^2 + Q^2 - 4 M b, 0)) / M / scale.
+ *   t device float [B][H][W] (overwritten) */
+qld_status qld_denoise_target(const int32_t *I_L, const int32_t *Q_L, const uint64_t *sum_L,
+                              int32_t M_L, const float *scale, int32_t B, int32_t H, int32_t W,
+                              float *t, qld_hip_stream stream);
+
+/* Per-cycle lock-in amplitude of the noise-free rates of each tile,
+ * |(lambda_0 - lambda_2, lambda_1 - lambda_3)|: the reference of the NRMSE judge.
+ *   mask device uint8 [B][H][W]; rates_host HOST double [B][2][4]; a device float [B][H][W] */
+qld_status qld_clean_amplitude(const uint8_t *mask, const double *rates_host, int32_t B, int32_t H,
+                               int32_t W, float *a, qld_hip_stream stream);
+
+/* Judges, per tile, double-precision fixed-order reductions:
+ *   qld_judge_nrmse: out[b] = RMS(x[b]*scale[b] - ref[b]) / RMS(ref[b]); scale may be NULL (1).
+ *   qld_judge_cnr:   Eq. CNR of the paper (Methods): labels 1 = source, 2 = surround,
+ *                    out[b] = (mean_src - mean_surr) / RMS(surr - mean_surr).
+ * x, ref, img device float [B][n]; labels device uint8 [B][n]; out device float [B]. */
+qld_status qld_judge_nrmse(const float *x, const float *scale, const float *ref, int32_t B, int64_t n,
+                           float *out, qld_hip_stream stream);
+qld_status qld_judge_cnr(const float *img, const uint8_t *labels, int32_t B, int64_t n, float *out,
+                         qld_hip_stream stream);
+
+/*
+ * The denoiser: 3x3 convolutions 2 -> 32 -> 32 -> 32 -> 1 with bias, ReLU
+ * between layers and zero "same" padding, NHWC bfloat16 activations, fp32
+ * accumulation (matrix cores), fp32 master weights; plus a gate
+ * gate[b] = mean_pixels(a3[b]) . Wg + bg predicting the tile's excess error.
+ * Parameters (qld_denoiser_param_count() = 19426 floats, in this order):
+ * W1[3][3][2][32] b1[32] W2[3][3][32][32] b2[32] W3[3][3][32][32] b3[32]
+ * W4[3][3][32][1] b4[1] Wg[32] bg[1].  Work is enqueued on `stream`; the
+ * object keeps the activations of its last forward for the backward.
+ */
+typedef struct qld_denoiser qld_denoiser;
+int32_t qld_denoiser_param_count(void);
+qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batch, qld_denoiser **out);
+qld_status qld_denoiser_destroy(qld_denoiser *d);
+/* Host copies (synchronous).  set_params also resets the optimizer state. */
+qld_status qld_denoiser_set_params(qld_denoiser *d, const float *host, int32_t n);
+qld_status qld_denoiser_get_params(qld_denoiser *d, float *host, int32_t n);
+qld_status qld_denoiser_get_grads(qld_denoiser *d, float *host, int32_t n);
+/* Device pointer to an internal tensor (0 x0 bf16 [B][H][W][2], 1..3 a1..a3
+ * bf16 [B][H][W][32], 4 y f32, 5 dz3, 6 dz2, 10 dz1 (bf16 [B][H][W][32], the
+ * ReLU-masked gradients of the hidden pre-activations), 7 pool f32 [B][32],
+ * 8 gate f32 [B], 9 loss f32 [2]); sized for max_batch. */
+qld_status qld_denoiser_tensor(qld_denoiser *d, int32_t which, void **ptr, int64_t *count);
+/* x device float [B][H][W][2]; y_out device float [B][H][W] or NULL; gate_out device float [B] or NULL. */
+qld_status qld_denoiser_forward(qld_denoiser *d, const float *x, int32_t B, float *y_out,
+                                float *gate_out, qld_hip_stream stream);
+/* Gradients of mean (y - t)^2 (weights W1..b4) and of the gate's own loss
+ * gate_weight * mean (gate - (e_a - e_b))^2 (Wg, bg only; e_a NULL: none;
+ * e_b may be NULL).  loss_out device float [2] or NULL. */
+qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, const float *e_a, const float *e_b,
+                                 float gate_weight, int32_t B, float *loss_out, qld_hip_stream stream);
+/* One Adam step (Kingma and Ba, 2015, bias-corrected) on all parameters. */
+qld_status qld_denoiser_adam(qld_denoiser *d, float lr, float beta1, float beta2, float eps,
+                             qld_hip_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Diagnostics                                                              */
 /* ------------------------------------------------------------------------ */
 const char *qld_status_str(qld_status st);

@@ -150,3 +150,39 @@ int oracle_gen_frames(const uint8_t *mask, const double *rates, int n_tiles, int
     }
     return 0;
 }
+
+/*
+ * Series of selected pixels of one tile (same definition as above): for each
+ * k, pixel index pix[k] = y*W + x of a tile of width W, mask state mk[k];
+ * writes series[k][t] for t < 4*n_cycles.
+ */
+int oracle_gen_pixels(const int64_t *pix, const uint8_t *mk, int n_px, const double *rates, int n_cycles,
+                      uint32_t tile, uint32_t seed_lo, uint32_t seed_hi, int bits, uint16_t *series) {
+    const int32_t top = (1 << bits) - 1;
+    uint32_t *thr[8];
+    int nthr[8];
+    int32_t lo[8], hi[8];
+    for (int s = 0; s < 8; ++s) {
+        int32_t l, h;
+        oracle_poisson_bounds(rates[s], &l, &h);
+        thr[s] = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(h - l + 1));
+        if (!thr[s]) return 1;
+        nthr[s] = oracle_poisson_table(rates[s], thr[s], &lo[s], &hi[s]);
+    }
+    for (int k = 0; k < n_px; ++k) {
+        for (int c = 0; c < n_cycles; ++c) {
+            uint32_t ctr[4] = {(uint32_t)pix[k], (uint32_t)c, tile, 0u};
+            uint32_t key[2] = {seed_lo, seed_hi};
+            uint32_t r[4];
+            oracle_philox4x32(ctr, key, 10, r);
+            for (int j = 0; j < 4; ++j) {
+                int s = (mk[k] ? 1 : 0) * 4 + j;
+                int32_t v = oracle_poisson_invert(thr[s], nthr[s], lo[s], r[j]);
+                if (v > top) v = top;
+                series[(size_t)k * 4 * n_cycles + (size_t)(4 * c + j)] = (uint16_t)v;
+            }
+        }
+    }
+    for (int s = 0; s < 8; ++s) free(thr[s]);
+    return 0;
+}

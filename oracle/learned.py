@@ -72,6 +72,20 @@ def gen_frames(mask, rates, n_cycles, tile0, seed, bits=12):
     return out
 
 
+def gen_pixel_series(pix, mk, rates_tile, n_cycles, tile, seed, bits=12):
+    """Series [k][4*n_cycles] uint16 of selected pixels (index y*W + x, mask state mk) of one tile."""
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    mk = np.ascontiguousarray(mk, dtype=np.uint8)
+    r = np.ascontiguousarray(rates_tile, dtype=np.float64).reshape(8)
+    out = np.zeros((len(pix), 4 * n_cycles), dtype=np.uint16)
+    rc = _o._load().oracle_gen_pixels(pix.ctypes.data, mk.ctypes.data, len(pix), r.ctypes.data, n_cycles,
+                                      int(tile) & 0xFFFFFFFF, int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF,
+                                      bits, out.ctypes.data)
+    if rc:
+        raise RuntimeError("oracle_gen_pixels failed")
+    return out
+
+
 def gen_pairs(mask, rates, M_S, M_L, tile0, seed, bits=12):
     """Quadrature sums of the short (first M_S cycles) and long (first M_L
     cycles) windows of the generated stack, by the lock-in oracle, plus the

@@ -38,6 +38,10 @@ EXPORTS = (
     "qld_stream_submit", "qld_stream_poll", "qld_stream_result_iq", "qld_server_drain",
     "qld_stream_close", "qld_server_destroy", "qld_server_stats",
     "qld_status_str", "qld_last_error", "qld_version", "qld_time_next_kernel",
+    "qld_gen_pairs", "qld_denoise_prepare", "qld_denoise_target", "qld_clean_amplitude",
+    "qld_judge_nrmse", "qld_judge_cnr", "qld_denoiser_param_count", "qld_denoiser_create",
+    "qld_denoiser_destroy", "qld_denoiser_set_params", "qld_denoiser_get_params", "qld_denoiser_get_grads",
+    "qld_denoiser_tensor", "qld_denoiser_forward", "qld_denoiser_backward", "qld_denoiser_adam",
 )
 
 
@@ -98,6 +102,24 @@ _sig("qld_status_str", ctypes.c_char_p, ctypes.c_int)
 _sig("qld_last_error", ctypes.c_char_p)
 _sig("qld_version", ctypes.c_char_p)
 _sig("qld_time_next_kernel", ctypes.c_int, _vp, _vp)
+_fp = ctypes.POINTER(ctypes.c_float)
+_sig("qld_gen_pairs", ctypes.c_int, _vp, _vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_uint32, ctypes.c_uint64, _i32,
+     _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("qld_denoise_prepare", ctypes.c_int, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp)
+_sig("qld_denoise_target", ctypes.c_int, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _vp, _vp)
+_sig("qld_clean_amplitude", ctypes.c_int, _vp, _vp, _i32, _i32, _i32, _vp, _vp)
+_sig("qld_judge_nrmse", ctypes.c_int, _vp, _vp, _vp, _i32, _i64, _vp, _vp)
+_sig("qld_judge_cnr", ctypes.c_int, _vp, _vp, _i32, _i64, _vp, _vp)
+_sig("qld_denoiser_param_count", _i32)
+_sig("qld_denoiser_create", ctypes.c_int, _i32, _i32, _i32, ctypes.POINTER(_vp))
+_sig("qld_denoiser_destroy", ctypes.c_int, _vp)
+_sig("qld_denoiser_set_params", ctypes.c_int, _vp, _fp, _i32)
+_sig("qld_denoiser_get_params", ctypes.c_int, _vp, _fp, _i32)
+_sig("qld_denoiser_get_grads", ctypes.c_int, _vp, _fp, _i32)
+_sig("qld_denoiser_tensor", ctypes.c_int, _vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_i64))
+_sig("qld_denoiser_forward", ctypes.c_int, _vp, _vp, _i32, _vp, _vp, _vp)
+_sig("qld_denoiser_backward", ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_float, _i32, _vp, _vp)
+_sig("qld_denoiser_adam", ctypes.c_int, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp)
 
 lib = _lib
 
@@ -349,6 +371,140 @@ def device_view(ptr, shape, dtype, device=None):
     typestr = {torch.float32: "<f4", torch.int32: "<i4"}[dtype]
     dev = device or torch.device("cuda", torch.cuda.current_device())
     return torch.as_tensor(_DeviceArray(ptr, shape, typestr), device=dev)
+
+
+# ---------------------------------------------------------------------------
+# Learned short-window path
+# ---------------------------------------------------------------------------
+
+def _host_f64(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, ctypes.c_void_p(a.ctypes.data)
+
+
+def gen_pairs(mask, rates, M_short, M_long, tile0, seed, bits=12, stream=None):
+    """Training pairs of n tiles: mask device uint8 [n][H][W], rates host [n][2][4].
+    Returns device tensors (I_S, Q_S, I_L, Q_L, sum_S, sum_L)."""
+    n, H, W = mask.shape
+    dev = mask.device
+    outs = [torch.empty((n, H, W), dtype=torch.int32, device=dev) for _ in range(4)]
+    sums = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(2)]
+    keep, rp = _host_f64(rates)
+    _check(_lib.qld_gen_pairs(_ptr(mask), rp, int(n), int(H), int(W), int(M_short), int(M_long), int(tile0),
+                              int(seed), int(bits), *[_ptr(o) for o in outs], _ptr(sums[0]), _ptr(sums[1]),
+                              _stream(stream)), "qld_gen_pairs")
+    return (*outs, *sums)
+
+
+def denoise_prepare(I_S, Q_S, sum_S, M_S, stream=None):
+    B, H, W = I_S.shape
+    x = torch.empty((B, H, W, 2), dtype=torch.float32, device=I_S.device)
+    scale = torch.empty(B, dtype=torch.float32, device=I_S.device)
+    _check(_lib.qld_denoise_prepare(_ptr(I_S), _ptr(Q_S), _ptr(sum_S), int(M_S), int(B), int(H), int(W), _ptr(x),
+                                    _ptr(scale), _stream(stream)), "qld_denoise_prepare")
+    return x, scale
+
+
+def denoise_target(I_L, Q_L, sum_L, M_L, scale, stream=None):
+    B, H, W = I_L.shape
+    t = torch.empty((B, H, W), dtype=torch.float32, device=I_L.device)
+    _check(_lib.qld_denoise_target(_ptr(I_L), _ptr(Q_L), _ptr(sum_L), int(M_L), _ptr(scale), int(B), int(H), int(W),
+                                   _ptr(t), _stream(stream)), "qld_denoise_target")
+    return t
+
+
+def clean_amplitude(mask, rates, stream=None):
+    B, H, W = mask.shape
+    a = torch.empty((B, H, W), dtype=torch.float32, device=mask.device)
+    keep, rp = _host_f64(rates)
+    _check(_lib.qld_clean_amplitude(_ptr(mask), rp, int(B), int(H), int(W), _ptr(a), _stream(stream)),
+           "qld_clean_amplitude")
+    return a
+
+
+def judge_nrmse(x, ref, scale=None, stream=None):
+    B = x.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=x.device)
+    _check(_lib.qld_judge_nrmse(_ptr(x), _ptr(scale), _ptr(ref), int(B), int(x[0].numel()), _ptr(out),
+                                _stream(stream)), "qld_judge_nrmse")
+    return out
+
+
+def judge_cnr(img, labels, stream=None):
+    B = img.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=img.device)
+    _check(_lib.qld_judge_cnr(_ptr(img), _ptr(labels), int(B), int(img[0].numel()), _ptr(out), _stream(stream)),
+           "qld_judge_cnr")
+    return out
+
+
+TENSORS = {"x0": 0, "a1": 1, "a2": 2, "a3": 3, "y": 4, "dz3": 5, "dz2": 6, "pool": 7, "gate": 8, "loss": 9, "dz1": 10}
+
+
+class Denoiser:
+    """The learned short-window denoiser (device weights, Adam state, activations)."""
+
+    def __init__(self, H, W, max_batch):
+        h = _vp()
+        _check(_lib.qld_denoiser_create(int(H), int(W), int(max_batch), ctypes.byref(h)), "qld_denoiser_create")
+        self._h, self.H, self.W, self.max_batch = h, H, W, max_batch
+        self.n_params = int(_lib.qld_denoiser_param_count())
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(_lib.qld_denoiser_set_params(self._h, a.ctypes.data_as(_fp), int(a.size)), "qld_denoiser_set_params")
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib.qld_denoiser_get_params(self._h, a.ctypes.data_as(_fp), int(a.size)), "qld_denoiser_get_params")
+        return a
+
+    def get_grads(self):
+        import numpy as np
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib.qld_denoiser_get_grads(self._h, a.ctypes.data_as(_fp), int(a.size)), "qld_denoiser_get_grads")
+        return a
+
+    def tensor(self, name):
+        p, n = _vp(), _i64()
+        _check(_lib.qld_denoiser_tensor(self._h, TENSORS[name], ctypes.byref(p), ctypes.byref(n)), "qld_denoiser_tensor")
+        return p.value, n.value
+
+    def forward(self, x, y=None, gate=None, stream=None):
+        _check(_lib.qld_denoiser_forward(self._h, _ptr(x), int(x.shape[0]), _ptr(y), _ptr(gate), _stream(stream)),
+               "qld_denoiser_forward")
+
+    def backward(self, t, e_a=None, e_b=None, gate_weight=1.0, loss=None, stream=None):
+        _check(_lib.qld_denoiser_backward(self._h, _ptr(t), _ptr(e_a), _ptr(e_b), float(gate_weight),
+                                          int(t.shape[0]), _ptr(loss), _stream(stream)), "qld_denoiser_backward")
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_lib.qld_denoiser_adam(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream(stream)),
+               "qld_denoiser_adam")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.qld_denoiser_destroy(self._h), "qld_denoiser_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bf16_view(ptr, count, device=None):
+    """float32 copy of a libqld bfloat16 device buffer (bits widened by 16)."""
+    raw = device_view(ptr, ((count + 1) // 2,), torch.int32, device)
+    lo = raw & 0xFFFF
+    hi = (raw >> 16) & 0xFFFF
+    words = torch.stack([lo, hi], dim=-1).reshape(-1)[:count]
+    return (words << 16).view(torch.float32)
 
 
 def version():

@@ -1,0 +1,729 @@
+// Learned short-window denoiser: 4 conv3x3 layers (2 -> 32 -> 32 -> 32 -> 1),
+// bias and ReLU between layers, zero "same" padding, trained on pairs the
+// lock-in itself generates (short-window I/Q in, long-window amplitude out).
+// Not in the paper: it lets fewer frames reach the image quality of a longer
+// plain lock-in, with plain QLD as its fallback (gate) and its judge.
+//
+// Layout: activations NHWC bfloat16 [B][H][W][32]; weights fp32 master copy in
+// a canonical order, packed to bfloat16 operand layouts after every update.
+// The 32-channel layers are implicit GEMMs on the matrix cores:
+// v_mfma_f32_16x16x32_bf16 with A = 16 pixels x 32 input channels (one 16-byte
+// load per lane from NHWC), B = 32 input x 16 output channels, fp32
+// accumulation; one MFMA per tap and 16x16 output block.  The same kernel,
+// with the tap offsets negated and the weights transposed, computes the
+// gradient with respect to the input.  Weight gradients are MFMA reductions
+// over pixels (K = 32 pixels per step) into per-work-group partials that a
+// second kernel sums in a fixed order, so training is deterministic.  The
+// 2-channel input layer packs its 18 (tap, channel) products into one K = 32
+// MFMA; the 1-channel output layer and the small reductions use the VALU.
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "qld_internal.hpp"
+
+namespace qld {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Canonical parameter order (fp32): W[3][3][Cin][Cout] then b[Cout], per layer; then the gate.
+constexpr int64_t OFF_W1 = 0, OFF_B1 = 576, OFF_W2 = 608, OFF_B2 = 9824, OFF_W3 = 9856, OFF_B3 = 19072,
+                  OFF_W4 = 19104, OFF_B4 = 19392, OFF_WG = 19393, OFF_BG = 19425, N_ALL = 19426;
+
+constexpr int kRows = 4;        // output rows per work-group (one per wave)
+constexpr int kCols = 64;       // output pixels per row and work-group
+
+__device__ __forceinline__ int tap_dy(int t) { return t / 3 - 1; }
+__device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
+
+__device__ __forceinline__ f32x4 mfma16(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+    return z;
+}
+
+// ---------------------------------------------------------------------------
+// Weight packing: fp32 canonical -> bf16 operand layouts.
+//   w1f [32 co][32 k], k = tap*2 + ch (k < 18), zero elsewhere
+//   wNf [9][32 co][32 ci]   forward B operand (K = ci contiguous)
+//   wNb [9][32 ci][32 co]   input-gradient B operand (K = co contiguous)
+//   w4  [9][32]
+// ---------------------------------------------------------------------------
+__global__ void pack_kernel(const float *__restrict__ p, __bf16 *w1f, __bf16 *w2f, __bf16 *w2b, __bf16 *w3f,
+                            __bf16 *w3b, __bf16 *w4) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 1024) {
+        const int co = i / 32, k = i % 32;
+        w1f[i] = (__bf16)(k < 18 ? p[OFF_W1 + (k / 2 * 2 + k % 2) * 32 + co] : 0.0f);
+    }
+    if (i < 9 * 1024) {
+        const int t = i / 1024, r = i % 1024;
+        const int a = r / 32, b = r % 32;
+        // forward: [t][co = a][ci = b]  <- W[t][ci][co]
+        w2f[i] = (__bf16)p[OFF_W2 + (t * 32 + b) * 32 + a];
+        w3f[i] = (__bf16)p[OFF_W3 + (t * 32 + b) * 32 + a];
+        // input gradient: [t][ci = a][co = b] <- W[t][ci][co]
+        w2b[i] = (__bf16)p[OFF_W2 + (t * 32 + a) * 32 + b];
+        w3b[i] = (__bf16)p[OFF_W3 + (t * 32 + a) * 32 + b];
+    }
+    if (i < 288) w4[i] = (__bf16)p[OFF_W4 + i];
+}
+
+__global__ void to_bf16_kernel(const float *__restrict__ x, __bf16 *__restrict__ y, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = (__bf16)x[i];
+}
+
+// Work-group tile -> (image, first row, first column).
+__device__ __forceinline__ bool tile_of(int H, int W, int &b, int &y, int &x0) {
+    const int tx = (W + kCols - 1) / kCols, ty = (H + kRows - 1) / kRows;
+    int id = blockIdx.x;
+    x0 = (id % tx) * kCols;
+    id /= tx;
+    y = (id % ty) * kRows + (int)(threadIdx.x >> 6);
+    b = id / ty;
+    return y < H;
+}
+
+// ---------------------------------------------------------------------------
+// 32 -> 32 convolution on the matrix cores.
+// MODE 0 (forward):        out = bf16(relu(sum_tap in[p + tap] W[tap] + bias))
+// MODE 1 (input gradient): out = bf16((sum_tap in[p - tap] W^T[tap]) * (act[p] > 0))
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void conv32_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
+                                                     const float *__restrict__ bias, const __bf16 *__restrict__ act,
+                                                     __bf16 *__restrict__ out, int H, int W) {
+    int b, y, x0;
+    if (!tile_of(H, W, b, y, x0)) return;
+    const int lane = threadIdx.x & 63, m = lane & 15, kb = lane >> 4;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[g][0] = acc[g][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int64_t img = (int64_t)b * H;
+#pragma unroll 1
+    for (int t = 0; t < 9; ++t) {
+        const int sy = MODE == 0 ? tap_dy(t) : -tap_dy(t);
+        const int sx = MODE == 0 ? tap_dx(t) : -tap_dx(t);
+        const bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(wt + ((t * 32 + m) * 32 + kb * 8));
+        const bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(wt + ((t * 32 + 16 + m) * 32 + kb * 8));
+        const int iy = y + sy;
+        const bool row_ok = iy >= 0 && iy < H;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int ix = x0 + 16 * g + m + sx;
+            bf16x8 a = zero8();
+            if (row_ok && ix >= 0 && ix < W) a = *reinterpret_cast<const bf16x8 *>(in + ((img + iy) * W + ix) * 32 + kb * 8);
+            acc[g][0] = mfma16(a, w0, acc[g][0]);
+            acc[g][1] = mfma16(a, w1, acc[g][1]);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = x0 + 16 * g + 4 * kb + i;
+                if (px >= W) continue;
+                const int co = 16 * cb + m;
+                const int64_t idx = ((img + y) * W + px) * 32 + co;
+                float v = acc[g][cb][i];
+                if (MODE == 0) v = fmaxf(v + bias[co], 0.0f);
+                else v = (float)act[idx] > 0.0f ? v : 0.0f;
+                out[idx] = (__bf16)v;
+            }
+}
+
+// 2 -> 32 input layer: the 18 (tap, channel) products form one K = 32 MFMA.
+__global__ __launch_bounds__(256) void conv1_kernel(const __bf16 *__restrict__ x0, const __bf16 *__restrict__ w1f,
+                                                    const float *__restrict__ bias, __bf16 *__restrict__ out, int H,
+                                                    int W) {
+    int b, y, xs;
+    if (!tile_of(H, W, b, y, xs)) return;
+    const int lane = threadIdx.x & 63, m = lane & 15, kb = lane >> 4;
+    const int64_t img = (int64_t)b * H;
+    const bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(w1f + (m * 32 + kb * 8));
+    const bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(w1f + ((16 + m) * 32 + kb * 8));
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int px = xs + 16 * g + m;
+        bf16x8 a = zero8();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {          // k = 8 kb + 2 e + ch: tap 4 kb + e
+            const int t = 4 * kb + e;
+            if (t < 9) {
+                const int iy = y + tap_dy(t), ix = px + tap_dx(t);
+                if (iy >= 0 && iy < H && ix >= 0 && ix < W) {
+                    const int64_t o = ((img + iy) * W + ix) * 2;
+                    a[2 * e] = x0[o];
+                    a[2 * e + 1] = x0[o + 1];
+                }
+            }
+        }
+        acc[g][0] = mfma16(a, w0, f32x4{0.f, 0.f, 0.f, 0.f});
+        acc[g][1] = mfma16(a, w1, f32x4{0.f, 0.f, 0.f, 0.f});
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = xs + 16 * g + 4 * kb + i;
+                if (px >= W) continue;
+                const int co = 16 * cb + m;
+                out[((img + y) * W + px) * 32 + co] = (__bf16)fmaxf(acc[g][cb][i] + bias[co], 0.0f);
+            }
+}
+
+// 32 -> 1 output layer (VALU): y[p] = b4 + sum_tap sum_c a3[p + tap][c] w4[tap][c].
+__global__ __launch_bounds__(256) void conv_out_kernel(const __bf16 *__restrict__ a3, const __bf16 *__restrict__ w4,
+                                                       const float *__restrict__ b4, float *__restrict__ yout, int B,
+                                                       int H, int W) {
+    const int64_t n = (int64_t)B * H * W;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int x = (int)(p % W), y = (int)((p / W) % H);
+    const int64_t b = p / ((int64_t)H * W);
+    float acc = b4[0];
+    for (int t = 0; t < 9; ++t) {
+        const int iy = y + tap_dy(t), ix = x + tap_dx(t);
+        if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
+        const __bf16 *src = a3 + ((b * H + iy) * W + ix) * 32;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc = fmaf((float)src[c], (float)w4[t * 32 + c], acc);
+    }
+    yout[p] = acc;
+}
+
+// dy = 2 (y - t) / N; per-block partial sums of (y - t)^2.
+__global__ __launch_bounds__(256) void loss_kernel(const float *__restrict__ y, const float *__restrict__ t,
+                                                   float *__restrict__ dy, int64_t n, double *__restrict__ part) {
+    __shared__ double red[256];
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const float sc = (float)(2.0 / (double)n);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float d = y[i] - t[i];
+        dy[i] = sc * d;
+        s += (double)d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Gradient of the output layer with respect to a3, masked by ReLU, in bf16:
+// dz3[q][c] = bf16((sum_tap dy[q - tap] w4[tap][c]) * (a3[q][c] > 0)).
+__global__ __launch_bounds__(256) void out_back_kernel(const float *__restrict__ dy, const __bf16 *__restrict__ w4,
+                                                       const __bf16 *__restrict__ a3, __bf16 *__restrict__ dz, int B,
+                                                       int H, int W) {
+    const int64_t n = (int64_t)B * H * W;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int x = (int)(p % W), y = (int)((p / W) % H);
+    const int64_t b = p / ((int64_t)H * W);
+    float acc[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc[c] = 0.f;
+    for (int t = 0; t < 9; ++t) {
+        const int iy = y - tap_dy(t), ix = x - tap_dx(t);
+        if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
+        const float g = dy[(b * H + iy) * W + ix];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc[c] = fmaf(g, (float)w4[t * 32 + c], acc[c]);
+    }
+    const __bf16 *ap = a3 + p * 32;
+    __bf16 *dp = dz + p * 32;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) dp[c] = (__bf16)((float)ap[c] > 0.f ? acc[c] : 0.f);
+}
+
+// Small weight / bias gradients on the VALU.  Output o = (tap, ci, co) over
+// n_taps taps; partial[block][o] = sum over this block's pixels of
+// X[p + tap][ci] * D[p][co]  (X == NULL: X = 1, a bias gradient).
+template <typename XT, typename DT>
+__global__ __launch_bounds__(640) void small_grad_kernel(const XT *__restrict__ X, const DT *__restrict__ D, int CI,
+                                                         int CO, int n_taps, int B, int H, int W, int64_t per_block,
+                                                         float *__restrict__ part) {
+    const int n_out = n_taps * CI * CO;
+    const int o = threadIdx.x;
+    const int64_t n = (int64_t)B * H * W;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block, p1 = min(n, p0 + per_block);
+    if (o >= n_out) return;
+    const int co = o % CO, ci = (o / CO) % CI, t = o / (CO * CI);
+    const int dy = n_taps == 9 ? tap_dy(t) : 0, dx = n_taps == 9 ? tap_dx(t) : 0;
+    float acc = 0.f;
+    for (int64_t p = p0; p < p1; ++p) {
+        const int x = (int)(p % W), y = (int)((p / W) % H);
+        const int64_t b = p / ((int64_t)H * W);
+        const float d = (float)D[p * CO + co];
+        float xv = 1.0f;
+        if (X) {
+            const int iy = y + dy, ix = x + dx;
+            if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
+            xv = (float)X[((b * H + iy) * W + ix) * CI + ci];
+        }
+        acc = fmaf(xv, d, acc);
+    }
+    part[(int64_t)blockIdx.x * n_out + o] = acc;
+}
+
+// 32x32 weight gradient on the matrix cores: D[co][ci] += sum_px dz[px][co] a[px + tap][ci].
+// A (16 co x 32 px) and B (32 px x 16 ci) gathered per lane (8 pixels of one
+// channel).  Wave w of a work-group owns taps w, w+4, w+8.  Segments of 32
+// pixels of one row are dealt to work-groups; partial[block][tap][ci][co].
+__global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a, const __bf16 *__restrict__ dz, int B,
+                                                   int H, int W, float *__restrict__ part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, m = lane & 15, kb = lane >> 4;
+    const int segs_x = (W + 31) / 32;
+    const int64_t n_seg = (int64_t)B * H * segs_x;
+    f32x4 acc[3][2][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j][0] = acc[i][j][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
+        const int sx = (int)(s % segs_x);
+        const int64_t row = s / segs_x;             // b * H + y
+        const int y = (int)(row % H);
+        const int px0 = sx * 32 + kb * 8;
+        bf16x8 A[2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int px = px0 + e;
+                A[cb][e] = px < W ? dz[(row * W + px) * 32 + 16 * cb + m] : (__bf16)0.0f;
+            }
+#pragma unroll
+        for (int ti = 0; ti < 3; ++ti) {
+            const int t = wave + 4 * ti;
+            if (t >= 9) break;
+            const int iy = y + tap_dy(t), dx = tap_dx(t);
+            const bool row_ok = iy >= 0 && iy < H;
+            const int64_t irow = row - y + iy;
+            bf16x8 Bv[2];
+#pragma unroll
+            for (int cib = 0; cib < 2; ++cib)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int px = px0 + e, ix = px + dx;
+                    Bv[cib][e] = (row_ok && px < W && ix >= 0 && ix < W) ? a[(irow * W + ix) * 32 + 16 * cib + m]
+                                                                          : (__bf16)0.0f;
+                }
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int cib = 0; cib < 2; ++cib) acc[ti][cb][cib] = mfma16(A[cb], Bv[cib], acc[ti][cb][cib]);
+        }
+    }
+    float *pb = part + (int64_t)blockIdx.x * 9 * 1024;
+#pragma unroll
+    for (int ti = 0; ti < 3; ++ti) {
+        const int t = wave + 4 * ti;
+        if (t >= 9) break;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int cib = 0; cib < 2; ++cib)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int co = 16 * cb + 4 * kb + i, ci = 16 * cib + m;
+                    pb[(t * 32 + ci) * 32 + co] = acc[ti][cb][cib][i];
+                }
+    }
+}
+
+// out[i] = sum_b part[b][i] in block order (deterministic).
+__global__ void reduce_kernel(const float *__restrict__ part, int n_blocks, int n, float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int b = 0; b < n_blocks; ++b) s += part[(int64_t)b * n + i];
+    out[i] = s;
+}
+
+// Gate: pool[b][c] = mean_p a3[b][p][c]; gate[b] = pool[b] . Wg + bg.
+__global__ __launch_bounds__(256) void pool_kernel(const __bf16 *__restrict__ a3, int64_t npx, int chunks,
+                                                   float *__restrict__ part) {
+    __shared__ float red[8][32];
+    const int b = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+    const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int64_t per = ceil_div(npx, chunks);
+    const int64_t p0 = ch * per, p1 = min(npx, p0 + per);
+    float s = 0.f;
+    for (int64_t p = p0 + g; p < p1; p += 8) s += (float)a3[((int64_t)b * npx + p) * 32 + c];
+    red[g][c] = s;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float t = 0.f;
+        for (int k = 0; k < 8; ++k) t += red[k][c];
+        part[(int64_t)blockIdx.x * 32 + c] = t;
+    }
+}
+
+__global__ void gate_fwd_kernel(const float *__restrict__ part, int chunks, int64_t npx, const float *__restrict__ p,
+                                float *__restrict__ pool, float *__restrict__ gate, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float g = p[OFF_BG];
+    for (int c = 0; c < 32; ++c) {
+        float s = 0.f;
+        for (int k = 0; k < chunks; ++k) s += part[((int64_t)b * chunks + k) * 32 + c];
+        const float v = s / (float)npx;
+        pool[b * 32 + c] = v;
+        g = fmaf(v, p[OFF_WG + c], g);
+    }
+    gate[b] = g;
+}
+
+// Gate gradient (its own loss, w * mean_b (gate - e)^2; e = ea - eb), one work-group.
+__global__ void gate_back_kernel(const float *__restrict__ pool, const float *__restrict__ gate,
+                                 const float *__restrict__ ea, const float *__restrict__ eb, float w, int B,
+                                 float *__restrict__ grads, float *__restrict__ loss) {
+    const int c = threadIdx.x;
+    float gw = 0.f, gb = 0.f, l = 0.f;
+    for (int b = 0; b < B; ++b) {
+        const float e = ea[b] - (eb ? eb[b] : 0.f);
+        const float d = gate[b] - e;
+        const float de = w * 2.0f / (float)B * d;
+        if (c < 32) gw = fmaf(pool[b * 32 + c], de, gw);
+        gb += de;
+        l += d * d;
+    }
+    if (c < 32) grads[OFF_WG + c] = gw;
+    if (c == 0) {
+        grads[OFF_BG] = gb;
+        if (loss) loss[1] = w * l / (float)B;
+    }
+}
+
+__global__ void loss_finish_kernel(const double *__restrict__ part, int n_blocks, int64_t n, float *__restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < n_blocks; ++b) s += part[b];
+    loss[0] = (float)(s / (double)n);
+}
+
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void zero_f32_kernel(float *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+}  // namespace
+}  // namespace qld
+
+// ---------------------------------------------------------------------------
+// Object and entry points
+// ---------------------------------------------------------------------------
+struct qld_denoiser {
+    int H, W, max_batch;
+    int64_t step;
+    float *params, *grads, *m, *v;
+    __bf16 *w1f, *w2f, *w2b, *w3f, *w3b, *w4;
+    __bf16 *x0, *a1, *a2, *a3, *dzA, *dzB, *dzC;   // dz3, dz2, dz1
+    float *y, *dy, *pool, *gate, *part, *loss;
+    double *lpart;
+    int64_t part_floats;
+    int last_B;
+    std::vector<void *> allocs;
+};
+
+namespace qld {
+namespace {
+
+constexpr int kGradBlocks = 256;     // work-groups of the weight-gradient reductions
+constexpr int kPoolChunks = 64;
+constexpr int kLossBlocks = 256;
+
+template <typename T>
+qld_status dalloc(qld_denoiser *d, T **p, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, count * sizeof(T) + 64) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("denoiser allocation of %zu bytes failed", count * sizeof(T));
+        return QLD_E_NOMEM;
+    }
+    d->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return QLD_OK;
+}
+
+int conv_grid(int B, int H, int W) {
+    return (int)((int64_t)B * ceil_div(H, kRows) * ceil_div(W, kCols));
+}
+
+qld_status pack(qld_denoiser *d, hipStream_t s) {
+    hipLaunchKernelGGL(pack_kernel, dim3(36), dim3(256), 0, s, d->params, d->w1f, d->w2f, d->w2b, d->w3f, d->w3b,
+                       d->w4);
+    return check_hip(hipGetLastError(), "pack_kernel launch");
+}
+
+// partial sums over kGradBlocks pixel ranges, reduced into grads + off
+template <typename XT, typename DT>
+qld_status small_grad(qld_denoiser *d, const XT *X, const DT *D, int CI, int CO, int n_taps, int B, int64_t off,
+                      hipStream_t s) {
+    const int64_t n = (int64_t)B * d->H * d->W;
+    const int64_t per = ceil_div(n, kGradBlocks);
+    const int n_out = n_taps * CI * CO;
+    hipLaunchKernelGGL((small_grad_kernel<XT, DT>), dim3(kGradBlocks), dim3(640), 0, s, X, D, CI, CO, n_taps, B,
+                       d->H, d->W, per, d->part);
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)ceil_div(n_out, 256)), dim3(256), 0, s, d->part, kGradBlocks,
+                       n_out, d->grads + off);
+    return check_hip(hipGetLastError(), "small_grad launch");
+}
+
+qld_status dw32(qld_denoiser *d, const __bf16 *a, const __bf16 *dz, int B, int64_t off, hipStream_t s) {
+    hipLaunchKernelGGL(dw32_kernel, dim3(kGradBlocks), dim3(256), 0, s, a, dz, B, d->H, d->W, d->part);
+    hipLaunchKernelGGL(reduce_kernel, dim3(36), dim3(256), 0, s, d->part, kGradBlocks, 9 * 1024, d->grads + off);
+    return check_hip(hipGetLastError(), "dw32 launch");
+}
+
+}  // namespace
+}  // namespace qld
+
+using namespace qld;
+
+extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batch, qld_denoiser **out) {
+    clear_error();
+    if (!out || H < 1 || W < 1 || max_batch < 1) {
+        set_error("invalid denoiser shape %dx%d, batch %d", H, W, max_batch);
+        return QLD_E_INVAL;
+    }
+    auto *d = new (std::nothrow) qld_denoiser();
+    if (!d) return QLD_E_NOMEM;
+    d->H = H;
+    d->W = W;
+    d->max_batch = max_batch;
+    const size_t npx = (size_t)max_batch * H * W;
+    d->part_floats = std::max<int64_t>((int64_t)kGradBlocks * 9 * 1024, (int64_t)max_batch * kPoolChunks * 32);
+    qld_status st = QLD_OK;
+    if (st == QLD_OK) st = dalloc(d, &d->params, N_ALL);
+    if (st == QLD_OK) st = dalloc(d, &d->grads, N_ALL);
+    if (st == QLD_OK) st = dalloc(d, &d->m, N_ALL);
+    if (st == QLD_OK) st = dalloc(d, &d->v, N_ALL);
+    if (st == QLD_OK) st = dalloc(d, &d->w1f, 1024);
+    if (st == QLD_OK) st = dalloc(d, &d->w2f, 9 * 1024);
+    if (st == QLD_OK) st = dalloc(d, &d->w2b, 9 * 1024);
+    if (st == QLD_OK) st = dalloc(d, &d->w3f, 9 * 1024);
+    if (st == QLD_OK) st = dalloc(d, &d->w3b, 9 * 1024);
+    if (st == QLD_OK) st = dalloc(d, &d->w4, 288);
+    if (st == QLD_OK) st = dalloc(d, &d->x0, npx * 2);
+    if (st == QLD_OK) st = dalloc(d, &d->a1, npx * 32);
+    if (st == QLD_OK) st = dalloc(d, &d->a2, npx * 32);
+    if (st == QLD_OK) st = dalloc(d, &d->a3, npx * 32);
+    if (st == QLD_OK) st = dalloc(d, &d->dzA, npx * 32);
+    if (st == QLD_OK) st = dalloc(d, &d->dzB, npx * 32);
+    if (st == QLD_OK) st = dalloc(d, &d->dzC, npx * 32);
+    if (st == QLD_OK) st = dalloc(d, &d->y, npx);
+    if (st == QLD_OK) st = dalloc(d, &d->dy, npx);
+    if (st == QLD_OK) st = dalloc(d, &d->pool, (size_t)max_batch * 32);
+    if (st == QLD_OK) st = dalloc(d, &d->gate, (size_t)max_batch);
+    if (st == QLD_OK) st = dalloc(d, &d->part, (size_t)d->part_floats);
+    if (st == QLD_OK) st = dalloc(d, &d->loss, 2);
+    if (st == QLD_OK) st = dalloc(d, &d->lpart, kLossBlocks);
+    if (st == QLD_OK) {
+        for (void *p : d->allocs)
+            if (hipMemset(p, 0, 64) != hipSuccess) st = QLD_E_DEVICE;
+        const size_t zero_n = N_ALL * sizeof(float);
+        if (hipMemset(d->params, 0, zero_n) != hipSuccess || hipMemset(d->grads, 0, zero_n) != hipSuccess ||
+            hipMemset(d->m, 0, zero_n) != hipSuccess || hipMemset(d->v, 0, zero_n) != hipSuccess ||
+            hipMemset(d->loss, 0, 8) != hipSuccess)
+            st = QLD_E_DEVICE;
+    }
+    if (st != QLD_OK) {
+        for (void *p : d->allocs) (void)hipFree(p);
+        delete d;
+        return st;
+    }
+    d->step = 0;
+    d->last_B = 0;
+    *out = d;
+    return QLD_OK;
+}
+
+extern "C" qld_status qld_denoiser_destroy(qld_denoiser *d) {
+    clear_error();
+    if (!d) return QLD_OK;
+    (void)hipDeviceSynchronize();
+    for (void *p : d->allocs) (void)hipFree(p);
+    delete d;
+    return QLD_OK;
+}
+
+extern "C" int32_t qld_denoiser_param_count(void) { return (int32_t)N_ALL; }
+
+extern "C" qld_status qld_denoiser_set_params(qld_denoiser *d, const float *host, int32_t n) {
+    clear_error();
+    if (!d || !host || n != N_ALL) {
+        set_error("set_params needs %lld floats", (long long)N_ALL);
+        return QLD_E_INVAL;
+    }
+    QLD_TRY(check_hip(hipDeviceSynchronize(), "sync"));
+    QLD_TRY(check_hip(hipMemcpy(d->params, host, N_ALL * sizeof(float), hipMemcpyHostToDevice), "params upload"));
+    QLD_TRY(check_hip(hipMemset(d->m, 0, N_ALL * sizeof(float)), "adam reset"));
+    QLD_TRY(check_hip(hipMemset(d->v, 0, N_ALL * sizeof(float)), "adam reset"));
+    d->step = 0;
+    QLD_TRY(pack(d, nullptr));
+    return check_hip(hipDeviceSynchronize(), "pack sync");
+}
+
+extern "C" qld_status qld_denoiser_get_params(qld_denoiser *d, float *host, int32_t n) {
+    clear_error();
+    if (!d || !host || n != N_ALL) return QLD_E_INVAL;
+    QLD_TRY(check_hip(hipDeviceSynchronize(), "sync"));
+    return check_hip(hipMemcpy(host, d->params, N_ALL * sizeof(float), hipMemcpyDeviceToHost), "params download");
+}
+
+extern "C" qld_status qld_denoiser_get_grads(qld_denoiser *d, float *host, int32_t n) {
+    clear_error();
+    if (!d || !host || n != N_ALL) return QLD_E_INVAL;
+    QLD_TRY(check_hip(hipDeviceSynchronize(), "sync"));
+    return check_hip(hipMemcpy(host, d->grads, N_ALL * sizeof(float), hipMemcpyDeviceToHost), "grads download");
+}
+
+extern "C" qld_status qld_denoiser_tensor(qld_denoiser *d, int32_t which, void **ptr, int64_t *count) {
+    clear_error();
+    if (!d || !ptr) return QLD_E_INVAL;
+    const int64_t npx = (int64_t)d->max_batch * d->H * d->W;
+    void *p = nullptr;
+    int64_t c = 0;
+    switch (which) {
+        case 0: p = d->x0; c = npx * 2; break;     // bf16 input
+        case 1: p = d->a1; c = npx * 32; break;    // bf16 activations
+        case 2: p = d->a2; c = npx * 32; break;
+        case 3: p = d->a3; c = npx * 32; break;
+        case 4: p = d->y; c = npx; break;          // f32 output
+        case 5: p = d->dzA; c = npx * 32; break;   // bf16 gradient dz3
+        case 6: p = d->dzB; c = npx * 32; break;   // bf16 gradient dz2
+        case 7: p = d->pool; c = (int64_t)d->max_batch * 32; break;
+        case 8: p = d->gate; c = d->max_batch; break;
+        case 9: p = d->loss; c = 2; break;
+        case 10: p = d->dzC; c = npx * 32; break;  // bf16 gradient dz1
+        default: set_error("unknown tensor %d", which); return QLD_E_INVAL;
+    }
+    *ptr = p;
+    if (count) *count = c;
+    return QLD_OK;
+}
+
+extern "C" qld_status qld_denoiser_forward(qld_denoiser *d, const float *x, int32_t B, float *y_out,
+                                           float *gate_out, qld_hip_stream stream) {
+    clear_error();
+    if (!d || !x || B < 1 || B > d->max_batch) {
+        set_error("forward: bad arguments (batch %d, max %d)", B, d ? d->max_batch : 0);
+        return QLD_E_INVAL;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int H = d->H, W = d->W;
+    const int64_t npx = (int64_t)B * H * W;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(npx * 2, 256), 8192)), dim3(256), 0,
+                       s, x, d->x0, npx * 2);
+    const int g = conv_grid(B, H, W);
+    hipEvent_t ev0, ev1;
+    take_kernel_timer(&ev0, &ev1);
+    if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
+    hipLaunchKernelGGL(conv1_kernel, dim3(g), dim3(256), 0, s, d->x0, d->w1f, d->params + OFF_B1, d->a1, H, W);
+    hipLaunchKernelGGL((conv32_kernel<0>), dim3(g), dim3(256), 0, s, d->a1, d->w2f, d->params + OFF_B2, nullptr, d->a2,
+                       H, W);
+    hipLaunchKernelGGL((conv32_kernel<0>), dim3(g), dim3(256), 0, s, d->a2, d->w3f, d->params + OFF_B3, nullptr, d->a3,
+                       H, W);
+    hipLaunchKernelGGL(conv_out_kernel, dim3((unsigned)ceil_div(npx, 256)), dim3(256), 0, s, d->a3, d->w4,
+                       d->params + OFF_B4, d->y, B, H, W);
+    if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
+    hipLaunchKernelGGL(pool_kernel, dim3(B * kPoolChunks), dim3(256), 0, s, d->a3, (int64_t)H * W, kPoolChunks,
+                       d->part);
+    hipLaunchKernelGGL(gate_fwd_kernel, dim3((unsigned)ceil_div(B, 64)), dim3(64), 0, s, d->part, kPoolChunks,
+                       (int64_t)H * W, d->params, d->pool, d->gate, B);
+    QLD_TRY(check_hip(hipGetLastError(), "forward launch"));
+    if (y_out) QLD_TRY(check_hip(hipMemcpyAsync(y_out, d->y, npx * sizeof(float), hipMemcpyDeviceToDevice, s), "y copy"));
+    if (gate_out)
+        QLD_TRY(check_hip(hipMemcpyAsync(gate_out, d->gate, B * sizeof(float), hipMemcpyDeviceToDevice, s), "gate copy"));
+    d->last_B = B;
+    return QLD_OK;
+}
+
+extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, const float *e_a, const float *e_b,
+                                            float gate_weight, int32_t B, float *loss_out, qld_hip_stream stream) {
+    clear_error();
+    if (!d || !t || B < 1 || B != d->last_B) {
+        set_error("backward: bad arguments or no matching forward (batch %d, last forward %d)", B, d ? d->last_B : 0);
+        return QLD_E_INVAL;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int H = d->H, W = d->W;
+    const int64_t npx = (int64_t)B * H * W;
+    hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, s, d->y, t, d->dy, npx, d->lpart);
+    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, d->lpart, kLossBlocks, npx, d->loss);
+    // Output layer: dW4, db4, and dz3 = bf16(d a3 * (a3 > 0)).
+    QLD_TRY(small_grad<__bf16, float>(d, d->a3, d->dy, 32, 1, 9, B, OFF_W4, s));
+    QLD_TRY(small_grad<__bf16, float>(d, nullptr, d->dy, 1, 1, 1, B, OFF_B4, s));
+    hipLaunchKernelGGL(out_back_kernel, dim3((unsigned)ceil_div(npx, 256)), dim3(256), 0, s, d->dy, d->w4, d->a3,
+                       d->dzA, B, H, W);
+    const int g = conv_grid(B, H, W);
+    // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
+    QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));
+    QLD_TRY(small_grad<__bf16, __bf16>(d, nullptr, d->dzA, 1, 32, 1, B, OFF_B3, s));
+    hipLaunchKernelGGL((conv32_kernel<1>), dim3(g), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W);
+    // Layer 2: dW2 from (a1, dz2); dz1 = bf16(conv^T(dz2, W2) * (a1 > 0)).
+    QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));
+    QLD_TRY(small_grad<__bf16, __bf16>(d, nullptr, d->dzB, 1, 32, 1, B, OFF_B2, s));
+    hipLaunchKernelGGL((conv32_kernel<1>), dim3(g), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W);
+    // Layer 1: dW1 from (x0, dz1).
+    QLD_TRY(small_grad<__bf16, __bf16>(d, d->x0, d->dzC, 2, 32, 9, B, OFF_W1, s));
+    QLD_TRY(small_grad<__bf16, __bf16>(d, nullptr, d->dzC, 1, 32, 1, B, OFF_B1, s));
+    // Gate (its own loss; its gradient reaches only Wg, bg).
+    if (e_a) {
+        hipLaunchKernelGGL(gate_back_kernel, dim3(1), dim3(64), 0, s, d->pool, d->gate, e_a, e_b, gate_weight, B,
+                           d->grads, d->loss);
+    } else {
+        hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, s, d->grads + OFF_WG, (int64_t)33);
+    }
+    QLD_TRY(check_hip(hipGetLastError(), "backward launch"));
+    if (loss_out) QLD_TRY(check_hip(hipMemcpyAsync(loss_out, d->loss, 8, hipMemcpyDeviceToDevice, s), "loss copy"));
+    return QLD_OK;
+}
+
+extern "C" qld_status qld_denoiser_adam(qld_denoiser *d, float lr, float beta1, float beta2, float eps,
+                                        qld_hip_stream stream) {
+    clear_error();
+    if (!d || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f)) {
+        set_error("adam: bad hyper-parameters");
+        return QLD_E_INVAL;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    d->step += 1;
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)d->step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)d->step));
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)ceil_div(N_ALL, 256)), dim3(256), 0, s, d->params, d->grads, d->m,
+                       d->v, N_ALL, lr, beta1, beta2, eps, c1, c2);
+    QLD_TRY(check_hip(hipGetLastError(), "adam launch"));
+    return pack(d, s);
+}

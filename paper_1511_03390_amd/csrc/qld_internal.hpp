@@ -37,7 +37,7 @@ int device_cu_count();
 // (with the message set).  elem_bytes receives 1 or 2.
 qld_status check_desc(const qld_frame_desc *d, int *elem_bytes);
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Rotation of the local quadratures by the lock-in phase of the first frame:
 // one step of phase maps (I, Q) to (-Q, I).
@@ -52,8 +52,8 @@ __host__ __device__ inline void rotate_iq(int rot, int32_t i, int32_t q, int32_t
 
 }  // namespace qld
 
-#define QLD_TRY(expr)                              \
+#define QLD_TRY(...)                               \
     do {                                           \
-        qld_status _st = (expr);                   \
+        qld_status _st = (__VA_ARGS__);            \
         if (_st != QLD_OK) return _st;             \
     } while (0)

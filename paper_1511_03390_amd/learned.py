@@ -1,0 +1,124 @@
+"""Training and evaluation loop of the learned short-window path.
+
+Every step runs in libqld's kernels (pair generation, normalisation, target,
+forward, backward, Adam, judges); this module only sequences the calls and
+draws the seeded scene parameters and initial weights on the host (they are
+inputs).  Plain QLD is the fallback and the judge:
+
+* training pairs: short window (M_S cycles) I/Q in, bias-reduced long-window
+  (M_L cycles) amplitude out, of the same generated stack;
+* gate target: the tile's excess error NRMSE(learned) - NRMSE(plain at M_L),
+  both against the per-cycle lock-in amplitude of the noise-free rates;
+* serving rule: learned output when the predicted excess is at most
+  ``gate_threshold``, plain QLD at M_L otherwise.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+import paper_1511_03390_amd as qld
+import scenes
+
+LAYERS = ((2, 32), (32, 32), (32, 32), (32, 1))
+
+
+def he_init(seed):
+    """He-normal weights, zero biases and gate, in the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in LAYERS:
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / (9 * ci)), size=9 * ci * co))
+        parts.append(np.zeros(co))
+    parts.append(np.zeros(33))
+    return np.concatenate(parts).astype(np.float32)
+
+
+class Batch:
+    """Device tensors of one batch of generated tiles."""
+
+    def __init__(self, params, M_S, M_L, tile0, seed, bits=12):
+        self.mask = torch.from_numpy(params["mask"]).cuda()
+        self.rates = params["rates"]
+        self.M_S, self.M_L = M_S, M_L
+        self.I_S, self.Q_S, self.I_L, self.Q_L, self.sum_S, self.sum_L = qld.gen_pairs(
+            self.mask, self.rates, M_S, M_L, tile0, seed, bits)
+        self.x, self.scale = qld.denoise_prepare(self.I_S, self.Q_S, self.sum_S, M_S)
+        self.t = qld.denoise_target(self.I_L, self.Q_L, self.sum_L, M_L, self.scale)
+        self.clean = qld.clean_amplitude(self.mask, self.rates)
+        B, H, W = self.I_S.shape
+        self.B, self.H, self.W = B, H, W
+        self.ampL = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+        qld.amplitude(self.I_L, self.Q_L, self.ampL)
+        self.ampS = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+        qld.amplitude(self.I_S, self.Q_S, self.ampS)
+        self.invL = torch.full((B,), 1.0 / M_L, dtype=torch.float32, device="cuda")
+        self.invS = torch.full((B,), 1.0 / M_S, dtype=torch.float32, device="cuda")
+
+
+def tile_batch(step, batch, H, W, M_S, M_L, seed, ballistic=5e-4, background=2000.0):
+    p = scenes.tile_params(scenes.seed_for(4, step), batch, H=H, W=W, background=background, ballistic=ballistic,
+                           smin=16, smax=256)
+    return Batch(p, M_S, M_L, tile0=step * batch, seed=seed)
+
+
+def train(steps=200, batch=8, H=512, W=512, M_S=8, M_L=512, lr=2e-3, seed=1511033904, gate_weight=0.1,
+          log=None, first_step=0):
+    d = qld.Denoiser(H, W, batch)
+    d.set_params(he_init(seed))
+    y = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(2, dtype=torch.float32, device="cuda")
+    hist = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        b = tile_batch(first_step + s, batch, H, W, M_S, M_L, seed)
+        d.forward(b.x, y)
+        nl = qld.judge_nrmse(y, b.clean, b.scale)
+        npl = qld.judge_nrmse(b.ampL, b.clean, b.invL)
+        d.backward(b.t, nl, npl, gate_weight, loss)
+        d.adam(lr)
+        if log and (s % max(1, steps // 10) == 0 or s == steps - 1):
+            torch.cuda.synchronize()
+            lv = loss.cpu().numpy()
+            hist.append((s, float(lv[0]), float(lv[1])))
+            log("step %d loss %.5f gate %.5f" % (s, lv[0], lv[1]))
+    torch.cuda.synchronize()
+    return d, hist, time.perf_counter() - t0
+
+
+def evaluate(d, n_batches=2, batch=8, H=512, W=512, M_S=8, M_L=512, seed=1511033904, first_step=10 ** 6,
+             gate_threshold=0.05):
+    """NRMSE against the noise-free per-cycle amplitude on held-out tiles."""
+    y = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
+    gate = torch.empty(batch, dtype=torch.float32, device="cuda")
+    acc = {k: [] for k in ("learned", "plain_S", "plain_L", "plain_L_bias_reduced", "served", "gate",
+                           "learned_vs_noisy_L")}
+    for k in range(n_batches):
+        b = tile_batch(first_step + k, batch, H, W, M_S, M_L, seed)
+        d.forward(b.x, y, gate)
+        acc["learned"].append(qld.judge_nrmse(y, b.clean, b.scale).cpu().numpy())
+        acc["plain_S"].append(qld.judge_nrmse(b.ampS, b.clean, b.invS).cpu().numpy())
+        acc["plain_L"].append(qld.judge_nrmse(b.ampL, b.clean, b.invL).cpu().numpy())
+        acc["plain_L_bias_reduced"].append(qld.judge_nrmse(b.t, b.clean, b.scale).cpu().numpy())
+        ampL_pc = b.ampL * b.invL[:, None, None]
+        acc["learned_vs_noisy_L"].append(qld.judge_nrmse(y, ampL_pc, b.scale).cpu().numpy())
+        g = gate.cpu().numpy()
+        acc["gate"].append(g)
+        acc["served"].append(np.where(g > gate_threshold, acc["plain_L"][-1], acc["learned"][-1]))
+    out = {k: float(np.mean(np.concatenate(v))) for k, v in acc.items()}
+    out["fallback_rate"] = float(np.mean(np.concatenate(acc["gate"]) > gate_threshold))
+    out["tiles"] = n_batches * batch
+    return out
+
+
+def flops_per_pixel_step():
+    """Multiply-adds x 2 of one training step per pixel: forward (18x32 + 2 x 288x32
+    + 288 MACs) and backward (input gradients of layers 2-4 and weight
+    gradients of all four layers, each the size of the forward layer)."""
+    fwd = 2 * (18 * 32 + 2 * 288 * 32 + 288)
+    bwd_data = 2 * (2 * 288 * 32 + 288)
+    bwd_weight = fwd
+    return fwd + bwd_data + bwd_weight
