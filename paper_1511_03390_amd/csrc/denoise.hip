@@ -253,33 +253,65 @@ __global__ __launch_bounds__(256) void out_back_kernel(const float *__restrict__
 }
 
 // Small weight / bias gradients on the VALU.  Output o = (tap, ci, co) over
-// n_taps taps; partial[block][o] = sum over this block's pixels of
-// X[p + tap][ci] * D[p][co]  (X == NULL: X = 1, a bias gradient).
-template <typename XT, typename DT>
-__global__ __launch_bounds__(640) void small_grad_kernel(const XT *__restrict__ X, const DT *__restrict__ D, int CI,
-                                                         int CO, int n_taps, int B, int H, int W, int64_t per_block,
-                                                         float *__restrict__ part) {
-    const int n_out = n_taps * CI * CO;
-    const int o = threadIdx.x;
-    const int64_t n = (int64_t)B * H * W;
-    const int64_t p0 = (int64_t)blockIdx.x * per_block, p1 = min(n, p0 + per_block);
-    if (o >= n_out) return;
-    const int co = o % CO, ci = (o / CO) % CI, t = o / (CO * CI);
-    const int dy = n_taps == 9 ? tap_dy(t) : 0, dx = n_taps == 9 ? tap_dx(t) : 0;
-    float acc = 0.f;
-    for (int64_t p = p0; p < p1; ++p) {
-        const int x = (int)(p % W), y = (int)((p / W) % H);
-        const int64_t b = p / ((int64_t)H * W);
-        const float d = (float)D[p * CO + co];
-        float xv = 1.0f;
-        if (X) {
-            const int iy = y + dy, ix = x + dx;
-            if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
-            xv = (float)X[((b * H + iy) * W + ix) * CI + ci];
+// NT taps: sum over pixels of X[p + tap][ci] * D[p][co] (X == NULL: X = 1, a
+// bias gradient).  A work-group stages a 128-pixel row segment of D and the
+// three rows of X around it in LDS, then each thread accumulates its outputs
+// from LDS; segments are dealt round-robin to work-groups, each of which
+// writes one row of partial sums.
+constexpr int kSeg = 128;
+
+template <typename XT, typename DT, int CI, int CO, int NT>
+__global__ __launch_bounds__(256) void small_grad_kernel(const XT *__restrict__ X, const DT *__restrict__ D, int B,
+                                                         int H, int W, float *__restrict__ part) {
+    constexpr int NOUT = NT * CI * CO;
+    constexpr int PER = (NOUT + 255) / 256;
+    __shared__ float xs[3][kSeg + 2][CI];
+    __shared__ float ds[kSeg][CO];
+    float acc[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) acc[j] = 0.f;
+    const int segs_x = (W + kSeg - 1) / kSeg;
+    const int64_t n_seg = (int64_t)B * H * segs_x;
+    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+        const int x0 = (int)(sg % segs_x) * kSeg;
+        const int64_t row = sg / segs_x;           // b * H + y
+        const int y = (int)(row % H);
+        __syncthreads();                           // the previous segment's readers are done
+        for (int i = threadIdx.x; i < kSeg * CO; i += 256) {
+            const int px = i / CO, c = i % CO, x = x0 + px;
+            ds[px][c] = x < W ? (float)D[(row * W + x) * CO + c] : 0.f;
         }
-        acc = fmaf(xv, d, acc);
+        if (X) {
+            for (int i = threadIdx.x; i < 3 * (kSeg + 2) * CI; i += 256) {
+                const int r = i / ((kSeg + 2) * CI), rem = i % ((kSeg + 2) * CI);
+                const int px = rem / CI, c = rem % CI;
+                const int iy = y + r - 1, ix = x0 + px - 1;
+                xs[r][px][c] = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? (float)X[((row - y + iy) * W + ix) * CI + c]
+                                                                         : 0.f;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int o = threadIdx.x + 256 * j;
+            if (o < NOUT) {
+                const int co = o % CO, ci = (o / CO) % CI, t = o / (CO * CI);
+                const int r = NT == 9 ? t / 3 : 1, dx = NT == 9 ? t % 3 : 1;
+                float a = acc[j];
+                if (X) {
+                    for (int px = 0; px < kSeg; ++px) a = fmaf(xs[r][px + dx][ci], ds[px][co], a);
+                } else {
+                    for (int px = 0; px < kSeg; ++px) a += ds[px][co];
+                }
+                acc[j] = a;
+            }
+        }
     }
-    part[(int64_t)blockIdx.x * n_out + o] = acc;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int o = threadIdx.x + 256 * j;
+        if (o < NOUT) part[(int64_t)blockIdx.x * NOUT + o] = acc[j];
+    }
 }
 
 // 32x32 weight gradient on the matrix cores: D[co][ci] += sum_px dz[px][co] a[px + tap][ci].
@@ -348,13 +380,22 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
     }
 }
 
-// out[i] = sum_b part[b][i] in block order (deterministic).
-__global__ void reduce_kernel(const float *__restrict__ part, int n_blocks, int n, float *__restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Column sums of part[R][n] in a fixed order.  Work-group (cx, slab): 64
+// columns x 4 row groups; group g adds rows slab*64 + g, +4, ... ; the four
+// groups are combined in order.  Output row `slab` of out[slabs][n].
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const float *__restrict__ in, int R, int n,
+                                                          float *__restrict__ out) {
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int g = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * 64, r1 = min(R, r0 + 64);
     float s = 0.f;
-    for (int b = 0; b < n_blocks; ++b) s += part[(int64_t)b * n + i];
-    out[i] = s;
+    if (c < n)
+        for (int r = r0 + g; r < r1; r += 4) s += in[(int64_t)r * n + c];
+    red[g][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (g == 0 && c < n) out[(int64_t)blockIdx.y * n + c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                                             red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
 // Gate: pool[b][c] = mean_p a3[b][p][c]; gate[b] = pool[b] . Wg + bg.
@@ -449,7 +490,7 @@ struct qld_denoiser {
     float *params, *grads, *m, *v;
     __bf16 *w1f, *w2f, *w2b, *w3f, *w3b, *w4;
     __bf16 *x0, *a1, *a2, *a3, *dzA, *dzB, *dzC;   // dz3, dz2, dz1
-    float *y, *dy, *pool, *gate, *part, *loss;
+    float *y, *dy, *pool, *gate, *part, *part2, *loss;
     double *lpart;
     int64_t part_floats;
     int last_B;
@@ -459,7 +500,8 @@ struct qld_denoiser {
 namespace qld {
 namespace {
 
-constexpr int kGradBlocks = 256;     // work-groups of the weight-gradient reductions
+constexpr int kGradBlocks = 256;     // work-groups of the MFMA weight-gradient reduction
+constexpr int kSmallBlocks = 1024;   // work-groups of the VALU gradient reductions
 constexpr int kPoolChunks = 64;
 constexpr int kLossBlocks = 256;
 
@@ -486,24 +528,38 @@ qld_status pack(qld_denoiser *d, hipStream_t s) {
     return check_hip(hipGetLastError(), "pack_kernel launch");
 }
 
-// partial sums over kGradBlocks pixel ranges, reduced into grads + off
-template <typename XT, typename DT>
-qld_status small_grad(qld_denoiser *d, const XT *X, const DT *D, int CI, int CO, int n_taps, int B, int64_t off,
-                      hipStream_t s) {
-    const int64_t n = (int64_t)B * d->H * d->W;
-    const int64_t per = ceil_div(n, kGradBlocks);
-    const int n_out = n_taps * CI * CO;
-    hipLaunchKernelGGL((small_grad_kernel<XT, DT>), dim3(kGradBlocks), dim3(640), 0, s, X, D, CI, CO, n_taps, B,
-                       d->H, d->W, per, d->part);
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)ceil_div(n_out, 256)), dim3(256), 0, s, d->part, kGradBlocks,
-                       n_out, d->grads + off);
-    return check_hip(hipGetLastError(), "small_grad launch");
+// Sum the rows of part[R][n] into dst[n] (two stages, fixed order).
+qld_status reduce_rows(qld_denoiser *d, const float *part, int R, int n, float *dst, hipStream_t s) {
+    const float *in = part;
+    while (R > 64) {
+        const int slabs = (int)ceil_div(R, 64);
+        hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)ceil_div(n, 64), (unsigned)slabs), dim3(256), 0, s, in, R,
+                           n, d->part2);
+        in = d->part2;
+        R = slabs;
+        if (R > 64) {
+            set_error("reduction too large");
+            return QLD_E_INVAL;
+        }
+    }
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)ceil_div(n, 64), 1), dim3(256), 0, s, in, R, n, dst);
+    return check_hip(hipGetLastError(), "reduce_rows launch");
+}
+
+template <typename XT, typename DT, int CI, int CO, int NT>
+qld_status small_grad(qld_denoiser *d, const XT *X, const DT *D, int B, int64_t off, hipStream_t s) {
+    const int64_t n_seg = (int64_t)B * d->H * ceil_div(d->W, kSeg);
+    const int blocks = (int)std::min<int64_t>(kSmallBlocks, n_seg);
+    hipLaunchKernelGGL((small_grad_kernel<XT, DT, CI, CO, NT>), dim3(blocks), dim3(256), 0, s, X, D, B, d->H, d->W,
+                       d->part);
+    QLD_TRY(check_hip(hipGetLastError(), "small_grad launch"));
+    return reduce_rows(d, d->part, blocks, NT * CI * CO, d->grads + off, s);
 }
 
 qld_status dw32(qld_denoiser *d, const __bf16 *a, const __bf16 *dz, int B, int64_t off, hipStream_t s) {
     hipLaunchKernelGGL(dw32_kernel, dim3(kGradBlocks), dim3(256), 0, s, a, dz, B, d->H, d->W, d->part);
-    hipLaunchKernelGGL(reduce_kernel, dim3(36), dim3(256), 0, s, d->part, kGradBlocks, 9 * 1024, d->grads + off);
-    return check_hip(hipGetLastError(), "dw32 launch");
+    QLD_TRY(check_hip(hipGetLastError(), "dw32 launch"));
+    return reduce_rows(d, d->part, kGradBlocks, 9 * 1024, d->grads + off, s);
 }
 
 }  // namespace
@@ -547,6 +603,7 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     if (st == QLD_OK) st = dalloc(d, &d->pool, (size_t)max_batch * 32);
     if (st == QLD_OK) st = dalloc(d, &d->gate, (size_t)max_batch);
     if (st == QLD_OK) st = dalloc(d, &d->part, (size_t)d->part_floats);
+    if (st == QLD_OK) st = dalloc(d, &d->part2, (size_t)d->part_floats / 16 + 65536);
     if (st == QLD_OK) st = dalloc(d, &d->loss, 2);
     if (st == QLD_OK) st = dalloc(d, &d->lpart, kLossBlocks);
     if (st == QLD_OK) {
@@ -683,22 +740,22 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, s, d->y, t, d->dy, npx, d->lpart);
     hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, d->lpart, kLossBlocks, npx, d->loss);
     // Output layer: dW4, db4, and dz3 = bf16(d a3 * (a3 > 0)).
-    QLD_TRY(small_grad<__bf16, float>(d, d->a3, d->dy, 32, 1, 9, B, OFF_W4, s));
-    QLD_TRY(small_grad<__bf16, float>(d, nullptr, d->dy, 1, 1, 1, B, OFF_B4, s));
+    QLD_TRY(small_grad<__bf16, float, 32, 1, 9>(d, d->a3, d->dy, B, OFF_W4, s));
+    QLD_TRY(small_grad<__bf16, float, 1, 1, 1>(d, nullptr, d->dy, B, OFF_B4, s));
     hipLaunchKernelGGL(out_back_kernel, dim3((unsigned)ceil_div(npx, 256)), dim3(256), 0, s, d->dy, d->w4, d->a3,
                        d->dzA, B, H, W);
     const int g = conv_grid(B, H, W);
     // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
     QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));
-    QLD_TRY(small_grad<__bf16, __bf16>(d, nullptr, d->dzA, 1, 32, 1, B, OFF_B3, s));
+    QLD_TRY(small_grad<__bf16, __bf16, 1, 32, 1>(d, nullptr, d->dzA, B, OFF_B3, s));
     hipLaunchKernelGGL((conv32_kernel<1>), dim3(g), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W);
     // Layer 2: dW2 from (a1, dz2); dz1 = bf16(conv^T(dz2, W2) * (a1 > 0)).
     QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));
-    QLD_TRY(small_grad<__bf16, __bf16>(d, nullptr, d->dzB, 1, 32, 1, B, OFF_B2, s));
+    QLD_TRY(small_grad<__bf16, __bf16, 1, 32, 1>(d, nullptr, d->dzB, B, OFF_B2, s));
     hipLaunchKernelGGL((conv32_kernel<1>), dim3(g), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W);
     // Layer 1: dW1 from (x0, dz1).
-    QLD_TRY(small_grad<__bf16, __bf16>(d, d->x0, d->dzC, 2, 32, 9, B, OFF_W1, s));
-    QLD_TRY(small_grad<__bf16, __bf16>(d, nullptr, d->dzC, 1, 32, 1, B, OFF_B1, s));
+    QLD_TRY(small_grad<__bf16, __bf16, 2, 32, 9>(d, d->x0, d->dzC, B, OFF_W1, s));
+    QLD_TRY(small_grad<__bf16, __bf16, 1, 32, 1>(d, nullptr, d->dzC, B, OFF_B1, s));
     // Gate (its own loss; its gradient reaches only Wg, bg).
     if (e_a) {
         hipLaunchKernelGGL(gate_back_kernel, dim3(1), dim3(64), 0, s, d->pool, d->gate, e_a, e_b, gate_weight, B,

@@ -17,8 +17,9 @@
 //   w[m] = 1; w[k] = (w[k-1] lambda)/k (k > m); w[k] = (w[k+1] (k+1))/lambda (k < m)
 //   total = sum w (ascending k); thr[k] = min(floor(cum_k/total * 2^32), 2^32-1), k < hi
 //   X(u) = lo + #{k : thr[k] <= u}
-// A 1024-entry guide table (Chen and Asau, 1974) gives the first candidate
-// for each u >> 22, so the search takes about one step.
+// A 1024-entry guide table (Chen and Asau, 1974) brackets the answer for each
+// u >> 22; a binary search inside the bracket finishes it (a few steps at
+// most, one or none in the bulk of the distribution).
 #include "qld_internal.hpp"
 
 namespace qld {
@@ -56,10 +57,14 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     out[3] = c3;
 }
 
-// One thread builds one table: tables[t] for rate rates[t].
-__global__ void build_tables_kernel(const double *__restrict__ rates, int32_t n_rates, Table *__restrict__ tables,
-                                    double *__restrict__ wbuf) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// One work-group builds one table: lane 0 runs the sequential parts exactly
+// in the order the definition fixes (the ratio recurrence and the two
+// ascending sums, in LDS), then all lanes form the thresholds and the guide.
+__global__ __launch_bounds__(64) void build_tables_kernel(const double *__restrict__ rates, int32_t n_rates,
+                                                          Table *__restrict__ tables) {
+    __shared__ double wk[kTableMax + 1];
+    __shared__ double tot;
+    const int t = blockIdx.x;
     if (t >= n_rates) return;
     const double lam = rates[t];
     Table &T = tables[t];
@@ -68,25 +73,38 @@ __global__ void build_tables_kernel(const double *__restrict__ rates, int32_t n_
     const int32_t lo = m - w < 0 ? 0 : m - w;
     const int32_t hi = m + w;
     const int32_t n = hi - lo;                       // thresholds k = lo .. hi-1
-    double *wk = wbuf + (int64_t)t * (kTableMax + 1);
-    wk[m - lo] = 1.0;
-    for (int32_t k = m + 1; k <= hi; ++k) wk[k - lo] = __ddiv_rn(__dmul_rn(wk[k - 1 - lo], lam), (double)k);
-    for (int32_t k = m - 1; k >= lo; --k) wk[k - lo] = __ddiv_rn(__dmul_rn(wk[k + 1 - lo], (double)(k + 1)), lam);
-    double total = 0.0;
-    for (int32_t i = 0; i <= n; ++i) total = __dadd_rn(total, wk[i]);
-    double cum = 0.0;
-    for (int32_t i = 0; i < n; ++i) {
-        cum = __dadd_rn(cum, wk[i]);
-        const double f = floor(__dmul_rn(__ddiv_rn(cum, total), 4294967296.0));
+    if (threadIdx.x == 0) {
+        wk[m - lo] = 1.0;
+        for (int32_t k = m + 1; k <= hi; ++k) wk[k - lo] = __ddiv_rn(__dmul_rn(wk[k - 1 - lo], lam), (double)k);
+        for (int32_t k = m - 1; k >= lo; --k) wk[k - lo] = __ddiv_rn(__dmul_rn(wk[k + 1 - lo], (double)(k + 1)), lam);
+        double total = 0.0;
+        for (int32_t i = 0; i <= n; ++i) total = __dadd_rn(total, wk[i]);
+        double cum = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            cum = __dadd_rn(cum, wk[i]);
+            wk[i] = cum;                              // wk now holds the partial sums
+        }
+        tot = total;
+        T.lo = lo;
+        T.n = n;
+    }
+    __syncthreads();
+    const double total = tot;
+    for (int32_t i = threadIdx.x; i < n; i += 64) {
+        const double f = floor(__dmul_rn(__ddiv_rn(wk[i], total), 4294967296.0));
         T.thr[i] = f >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)f;
     }
-    T.lo = lo;
-    T.n = n;
-    int32_t k = 0;
-    for (int g = 0; g < kGuide; ++g) {
+    __syncthreads();
+    // guide[g] = #{thr <= g * 2^22}: binary search per entry.
+    for (int g = threadIdx.x; g < kGuide; g += 64) {
         const uint32_t u = (uint32_t)g << 22;
-        while (k < n && T.thr[k] <= u) ++k;
-        T.guide[g] = (uint16_t)k;
+        int32_t a = 0, b = n;
+        while (a < b) {
+            const int32_t mid = (a + b) >> 1;
+            if (T.thr[mid] <= u) a = mid + 1;
+            else b = mid;
+        }
+        T.guide[g] = (uint16_t)a;
     }
 }
 
@@ -101,10 +119,20 @@ struct GenArgs {
     unsigned long long *sum_S, *sum_L;
 };
 
+// X(u) = lo + #{k : thr[k] <= u}.  The count lies between the guide entries of
+// u's bucket and of the next bucket (thresholds are non-decreasing); a binary
+// search between them takes at most ~10 steps even in the tails, where one
+// bucket spans hundreds of thresholds.
 __device__ __forceinline__ int32_t invert(const Table *__restrict__ T, uint32_t u) {
-    int32_t k = T->guide[u >> 22];
-    while (k < T->n && T->thr[k] <= u) ++k;
-    return T->lo + k;
+    const uint32_t g = u >> 22;
+    int32_t a = T->guide[g];
+    int32_t b = g + 1 < (uint32_t)kGuide ? (int32_t)T->guide[g + 1] : T->n;
+    while (a < b) {
+        const int32_t mid = (a + b) >> 1;
+        if (T->thr[mid] <= u) a = mid + 1;
+        else b = mid;
+    }
+    return T->lo + a;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -210,16 +238,13 @@ extern "C" qld_status qld_gen_pairs(const uint8_t *mask, const double *rates_hos
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int32_t n_rates = n_tiles * 8;
     const size_t tab_b = ((sizeof(Table) * (size_t)n_rates + 255) / 256) * 256;
-    const size_t w_b = ((sizeof(double) * (size_t)n_rates * (kTableMax + 1) + 255) / 256) * 256;
     const size_t r_b = sizeof(double) * (size_t)n_rates;
-    char *ws = static_cast<char *>(stream_workspace(s, tab_b + w_b + r_b));
+    char *ws = static_cast<char *>(stream_workspace(s, tab_b + r_b));
     if (!ws) return QLD_E_NOMEM;
     Table *tables = reinterpret_cast<Table *>(ws);
-    double *wbuf = reinterpret_cast<double *>(ws + tab_b);
-    double *rates = reinterpret_cast<double *>(ws + tab_b + w_b);
+    double *rates = reinterpret_cast<double *>(ws + tab_b);
     QLD_TRY(check_hip(hipMemcpyAsync(rates, rates_host, r_b, hipMemcpyHostToDevice, s), "rates upload"));
-    hipLaunchKernelGGL(build_tables_kernel, dim3((unsigned)ceil_div(n_rates, 64)), dim3(64), 0, s, rates, n_rates,
-                       tables, wbuf);
+    hipLaunchKernelGGL(build_tables_kernel, dim3((unsigned)n_rates), dim3(64), 0, s, rates, n_rates, tables);
     QLD_TRY(check_hip(hipGetLastError(), "build_tables_kernel launch"));
     hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)ceil_div(n_tiles, 256)), dim3(256), 0, s,
                        reinterpret_cast<unsigned long long *>(sum_S), n_tiles);
