@@ -80,11 +80,11 @@ def train(steps=200, batch=8, H=512, W=512, M_S=8, M_L=512, lr=2e-3, seed=151103
         npl = qld.judge_nrmse(b.ampL, b.clean, b.invL)
         d.backward(b.t, nl, npl, gate_weight, loss)
         d.adam(lr)
-        if log and (s % max(1, steps // 10) == 0 or s == steps - 1):
-            torch.cuda.synchronize()
+        if s % max(1, steps // 10) == 0 or s == steps - 1:
             lv = loss.cpu().numpy()
             hist.append((s, float(lv[0]), float(lv[1])))
-            log("step %d loss %.5f gate %.5f" % (s, lv[0], lv[1]))
+            if log:
+                log("step %d loss %.5f gate %.5f" % (s, lv[0], lv[1]))
     torch.cuda.synchronize()
     return d, hist, time.perf_counter() - t0
 
