@@ -232,6 +232,22 @@ def bench_streaming(qld, torch, seconds, fps, M=64):
             "unpaced_launches": unpaced_batches, "wall_s": round(wall, 2)}
 
 
+def copy_calibration(torch, gib=1):
+    """A plain device copy of known size (torch's elementwise negation of an
+    int32 buffer: 4 B read and 4 B written per element).  Under rocprofv3
+    --pmc its FETCH_SIZE / WRITE_SIZE give the counters' bytes per KiB, which
+    converts the same counters of qld_accum_kernel into HBM bytes."""
+    n = gib << 28
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+    return {"kernel": "torch neg, int32", "launches": 3, "bytes_read": 4 * n, "bytes_written": 4 * n}
+
+
 def bench_learned(qld, torch, steps, eval_batches):
     """Learned short-window path at its tile size: 512 x 512 tiles, M_S = 8
     cycles in, bias-reduced M_L = 512-cycle amplitude out (64x fewer frames)."""
@@ -304,6 +320,8 @@ def main():
     ap.add_argument("--no-streaming", action="store_true")
     ap.add_argument("--learned-steps", type=int, default=150)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; "
@@ -343,6 +361,8 @@ def main():
     dft = {"kernel": "dft_bin_kernel", "k": T // 4, "kernel_ms_avg": round(d_avg, 4),
            "pxf_per_s": round(pxf / (d_avg * 1e-3)), "achieved_gbs": round(kern_bytes / (d_avg * 1e-3) / 1e9, 1),
            "ms_per_call": round(d_el / max(5, args.steps // 2) * 1e3, 4)}
+
+    calib = copy_calibration(torch) if args.copy_calibration else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -386,6 +406,8 @@ def main():
         "learned": learned,
         "library": qld.version(),
     }
+    if calib is not None:
+        out["copy_calibration"] = calib
     print(json.dumps(out), flush=True)
 
 
