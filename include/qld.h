@@ -166,7 +166,12 @@ qld_status qld_window_load(qld_window *w, const char *path);
 
 typedef struct qld_server qld_server;
 
-typedef enum { QLD_MODE_PLAIN = 0 } qld_mode;
+/* PLAIN: the image is the window's amplitude R (Methods, R(j,k)).
+ * LEARNED (not in the paper): every cycle the stream's denoiser maps the
+ * short window's I/Q to a per-cycle amplitude; its gate decides whether that
+ * image or the plain long-window amplitude per cycle is served (see
+ * qld_stream_set_denoiser). */
+typedef enum { QLD_MODE_PLAIN = 0, QLD_MODE_LEARNED = 1 } qld_mode;
 
 /* Server flags. */
 enum { QLD_SERVER_KEEP_IQ = 1 };   /* also keep per-cycle I/Q output slots */
@@ -185,8 +190,15 @@ typedef struct {
     uint64_t t_arrival_ns;     /* arrival time of the cycle's last frame (caller's clock) */
     uint64_t t_done_ns;        /* CLOCK_MONOTONIC when the image was complete on the device */
     const float *amp;          /* device [H][W]; valid until out_slots more cycles of
-                                  the stream complete, or the stream closes */
+                                  the stream complete, or the stream closes.
+                                  PLAIN: R of the window.  LEARNED: the served
+                                  image, amplitude per cycle (counts) */
     int32_t H, W;
+    const float *amp_plain;    /* device [H][W], same lifetime: R of the (long)
+                                  window; equals amp for a PLAIN stream */
+    float gate;                /* LEARNED: the gate's predicted excess NRMSE, NaN
+                                  while the short window is not yet full; PLAIN: 0 */
+    int32_t learned;           /* 1 if amp is the denoiser's output */
 } qld_result;
 
 /*
@@ -201,14 +213,17 @@ typedef struct {
 qld_status qld_server_create(size_t hbm_budget_bytes, int32_t out_slots, int32_t flags,
                              qld_server **out);
 
-/* Device bytes one stream of this shape and window costs under the server's
- * policy (what admission charges against the budget). */
+/* Device bytes one stream of this shape, window and mode costs under the
+ * server's policy (what admission charges against the budget; a LEARNED
+ * stream's denoiser is the caller's and is not counted). */
 size_t qld_server_stream_bytes(const qld_server *s, const qld_frame_desc *d, int32_t M_cycles,
-                               int32_t M_short);
+                               int32_t M_short, int32_t mode);
 
 /* Open a stream of dense host frames (d->row_pitch/frame_stride are ignored)
  * with a window of M_cycles cycles and optionally a short window of M_short
- * (0 = none) cycles sharing the same ring.  QLD_OK: admitted now.
+ * (0 = none) cycles sharing the same ring.  mode: QLD_MODE_PLAIN, or
+ * QLD_MODE_LEARNED (needs 1 <= M_short <= M_cycles, and a denoiser set with
+ * qld_stream_set_denoiser before the first frame).  QLD_OK: admitted now.
  * QLD_E_AGAIN: queued (state PENDING); admitted in FIFO order once closes
  * free enough budget.  QLD_E_BUDGET: can never fit.  *stream_id is set in
  * the first two cases. */
@@ -216,6 +231,24 @@ qld_status qld_stream_open(qld_server *s, const qld_frame_desc *d, int32_t M_cyc
                            int32_t M_short, int32_t mode, int32_t *stream_id);
 
 qld_status qld_stream_state(qld_server *s, int32_t stream_id, int32_t *state);
+
+typedef struct qld_denoiser qld_denoiser;
+
+/*
+ * Denoiser of a LEARNED stream (created by the caller for the stream's H x W,
+ * any max_batch; it must outlive the stream or be replaced after
+ * qld_server_drain, and the caller must not use it while the server may).
+ * For each cycle c of the window (c = 0 after a reset) the server, on its
+ * compute stream after the window update:
+ *   - if c + 1 >= M_short: x = qld_denoise_prepare(short-window I/Q, the
+ *     short window's sample sum), runs the forward (batch 1) and serves
+ *     y * scale when gate <= gate_threshold;
+ *   - otherwise, or when the gate is above the threshold, serves the plain
+ *     long-window amplitude per cycle, R / min(c + 1, M_cycles).
+ * Submissions to a LEARNED stream without a denoiser fail with QLD_E_STATE.
+ * QLD_E_SHAPE if the denoiser's H x W differ from the stream's.
+ */
+qld_status qld_stream_set_denoiser(qld_server *s, int32_t stream_id, qld_denoiser *dn, float gate_threshold);
 
 /*
  * Submit one frame (host pointer, dense [H][W] of the stream's dtype).  Frame
@@ -235,8 +268,10 @@ qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const void *host_
  * Returns QLD_E_DEVICE if a launch has failed. */
 qld_status qld_stream_poll(qld_server *s, qld_result *out, int32_t max, int32_t *n_out);
 
-/* Device I/Q (and short-window I/Q, NULL without a short window) of a polled
- * result; needs QLD_SERVER_KEEP_IQ.  Same lifetime as res->amp. */
+/* Device I/Q and short-window I/Q of a polled result, each NULL when not
+ * kept: the long window's with QLD_SERVER_KEEP_IQ, the short window's with
+ * QLD_SERVER_KEEP_IQ or in a LEARNED stream.  QLD_E_STATE if the stream keeps
+ * neither.  Same lifetime as res->amp. */
 qld_status qld_stream_result_iq(qld_server *s, const qld_result *res, const int32_t **I,
                                 const int32_t **Q, const int32_t **Is, const int32_t **Qs);
 
@@ -322,9 +357,10 @@ qld_status qld_judge_cnr(const float *img, const uint8_t *labels, int32_t B, int
  * W4[3][3][32][1] b4[1] Wg[32] bg[1].  Work is enqueued on `stream`; the
  * object keeps the activations of its last forward for the backward.
  */
-typedef struct qld_denoiser qld_denoiser;
 int32_t qld_denoiser_param_count(void);
 qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batch, qld_denoiser **out);
+/* Shape the denoiser was created for. */
+qld_status qld_denoiser_info(const qld_denoiser *d, int32_t *H, int32_t *W, int32_t *max_batch);
 qld_status qld_denoiser_destroy(qld_denoiser *d);
 /* Host copies (synchronous).  set_params also resets the optimizer state. */
 qld_status qld_denoiser_set_params(qld_denoiser *d, const float *host, int32_t n);

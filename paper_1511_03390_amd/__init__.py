@@ -28,6 +28,7 @@ OK, E_INVAL, E_DTYPE, E_SHAPE, E_ALIGN, E_OVERFLOW, E_NOMEM, E_BUDGET, E_AGAIN, 
 U8, U16 = 1, 2
 STREAM_PENDING, STREAM_ACTIVE, STREAM_CLOSED = 1, 2, 3
 SERVER_KEEP_IQ = 1
+MODE_PLAIN, MODE_LEARNED = 0, 1
 
 # Every entry point the header declares (checked by the tests).
 EXPORTS = (
@@ -35,12 +36,12 @@ EXPORTS = (
     "qld_window_bytes", "qld_window_create", "qld_window_update", "qld_window_reset",
     "qld_window_destroy", "qld_window_info", "qld_window_save", "qld_window_load",
     "qld_server_create", "qld_server_stream_bytes", "qld_stream_open", "qld_stream_state",
-    "qld_stream_submit", "qld_stream_poll", "qld_stream_result_iq", "qld_server_drain",
+    "qld_stream_set_denoiser", "qld_stream_submit", "qld_stream_poll", "qld_stream_result_iq", "qld_server_drain",
     "qld_stream_close", "qld_server_destroy", "qld_server_stats",
     "qld_status_str", "qld_last_error", "qld_version", "qld_time_next_kernel",
     "qld_gen_pairs", "qld_denoise_prepare", "qld_denoise_target", "qld_clean_amplitude",
     "qld_judge_nrmse", "qld_judge_cnr", "qld_denoiser_param_count", "qld_denoiser_create",
-    "qld_denoiser_destroy", "qld_denoiser_set_params", "qld_denoiser_get_params", "qld_denoiser_get_grads",
+    "qld_denoiser_info", "qld_denoiser_destroy", "qld_denoiser_set_params", "qld_denoiser_get_params", "qld_denoiser_get_grads",
     "qld_denoiser_tensor", "qld_denoiser_forward", "qld_denoiser_backward", "qld_denoiser_adam",
 )
 
@@ -60,7 +61,8 @@ class FrameDesc(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("stream_id", ctypes.c_int32), ("warm", ctypes.c_int32), ("cycle", ctypes.c_int64),
                 ("t_arrival_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
-                ("amp", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+                ("amp", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("amp_plain", ctypes.c_void_p), ("gate", ctypes.c_float), ("learned", ctypes.c_int32)]
 
 
 _vp, _i32, _i64, _u64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
@@ -86,7 +88,9 @@ _sig("qld_window_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(
 _sig("qld_window_save", ctypes.c_int, _vp, ctypes.c_char_p)
 _sig("qld_window_load", ctypes.c_int, _vp, ctypes.c_char_p)
 _sig("qld_server_create", ctypes.c_int, _sz, _i32, _i32, ctypes.POINTER(_vp))
-_sig("qld_server_stream_bytes", _sz, _vp, _dp, _i32, _i32)
+_sig("qld_server_stream_bytes", _sz, _vp, _dp, _i32, _i32, _i32)
+_sig("qld_stream_set_denoiser", ctypes.c_int, _vp, _i32, _vp, ctypes.c_float)
+_sig("qld_denoiser_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _sig("qld_stream_open", ctypes.c_int, _vp, _dp, _i32, _i32, _i32, ctypes.POINTER(_i32))
 _sig("qld_stream_state", ctypes.c_int, _vp, _i32, ctypes.POINTER(_i32))
 _sig("qld_stream_submit", ctypes.c_int, _vp, _i32, _vp, _i64, _u64)
@@ -297,20 +301,25 @@ class Server:
         self._h = h
         self.shapes = {}
 
-    def stream_bytes(self, H, W, M, M_short=0, dtype=torch.int16, bits=None):
+    def stream_bytes(self, H, W, M, M_short=0, dtype=torch.int16, bits=None, mode=MODE_PLAIN):
         dt, nbits = _DT[dtype]
         d = FrameDesc(int(H), int(W), int(W), int(H) * int(W), dt, int(bits or nbits))
-        return int(_lib.qld_server_stream_bytes(self._h, ctypes.byref(d), int(M), int(M_short)))
+        return int(_lib.qld_server_stream_bytes(self._h, ctypes.byref(d), int(M), int(M_short), int(mode)))
 
-    def open(self, H, W, M, M_short=0, dtype=torch.int16, bits=None):
+    def open(self, H, W, M, M_short=0, dtype=torch.int16, bits=None, mode=MODE_PLAIN):
         """Returns (stream_id, admitted_now)."""
         dt, nbits = _DT[dtype]
         d = FrameDesc(int(H), int(W), int(W), int(H) * int(W), dt, int(bits or nbits))
         sid = _i32()
-        st = _check(_lib.qld_stream_open(self._h, ctypes.byref(d), int(M), int(M_short), 0, ctypes.byref(sid)),
-                    "qld_stream_open", ok=(OK, E_AGAIN))
+        st = _check(_lib.qld_stream_open(self._h, ctypes.byref(d), int(M), int(M_short), int(mode),
+                                         ctypes.byref(sid)), "qld_stream_open", ok=(OK, E_AGAIN))
         self.shapes[sid.value] = (H, W)
         return sid.value, st == OK
+
+    def set_denoiser(self, sid, denoiser, gate_threshold=0.05):
+        """Attach a Denoiser (same H x W as the stream) to a LEARNED stream."""
+        _check(_lib.qld_stream_set_denoiser(self._h, int(sid), denoiser._h, float(gate_threshold)),
+               "qld_stream_set_denoiser")
 
     def state(self, sid):
         s = _i32()

@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libqld.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("QLD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["capi.cpp", "accumulate.hip", "dft.hip", "window.hip", "server.cpp", "gen.hip", "denoise.hip", "judges.hip"]
+SOURCES = ["capi.cpp", "accumulate.hip", "dft.hip", "window.hip", "server.cpp", "gen.hip", "denoise.hip", "judges.hip",
+           "serve_learned.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

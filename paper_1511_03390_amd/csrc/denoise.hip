@@ -626,6 +626,18 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     return QLD_OK;
 }
 
+extern "C" qld_status qld_denoiser_info(const qld_denoiser *d, int32_t *H, int32_t *W, int32_t *max_batch) {
+    clear_error();
+    if (!d) {
+        set_error("denoiser is NULL");
+        return QLD_E_INVAL;
+    }
+    if (H) *H = d->H;
+    if (W) *W = d->W;
+    if (max_batch) *max_batch = d->max_batch;
+    return QLD_OK;
+}
+
 extern "C" qld_status qld_denoiser_destroy(qld_denoiser *d) {
     clear_error();
     if (!d) return QLD_OK;

@@ -11,6 +11,10 @@
 //     different sizes share the launch), after waiting on the copy events;
 //   * a completion thread: waits for each launch's event, stamps the host
 //     time and publishes the images (qld_stream_poll).
+// A LEARNED stream (not in the paper) also runs its denoiser on the short
+// window after each cycle, on the same compute stream and before the launch's
+// event, and serves either that image or the plain long-window amplitude as
+// its gate decides.
 // HIP stream order and events replace the flags.  Streams are admitted while
 // the sum of their device footprints fits the HBM budget; the rest wait in
 // FIFO order and are admitted as closes free memory.
@@ -27,6 +31,7 @@
 #include <thread>
 #include <vector>
 
+#include "serve_learned.hpp"
 #include "window.hpp"
 
 namespace qld {
@@ -54,7 +59,22 @@ struct StreamRec {
     uint8_t *stage = nullptr;       // [kStageCycles][4][H][Wp] samples
     int64_t rp_b = 0, fs_b = 0, slot_b = 0;
     float *out_amp = nullptr;       // [out_slots][H][W]
-    int32_t *out_iq = nullptr;      // [out_slots][2 or 4][H][W] when the server keeps I/Q
+    int32_t *out_iq = nullptr;      // I/Q output planes, each [out_slots][H][W]:
+    int32_t *Io = nullptr, *Qo = nullptr;     //   long window (server keeps I/Q)
+    int32_t *Iso = nullptr, *Qso = nullptr;   //   short window (keeps I/Q, or LEARNED)
+
+    // LEARNED streams.
+    qld_denoiser *dn = nullptr;
+    float gate_thr = 0.05f;
+    const float *dn_y = nullptr, *dn_gate = nullptr;   // the denoiser's output tensors
+    float *served = nullptr;        // [out_slots][H][W] served images
+    float *x = nullptr;             // [H][W][2] network input
+    float *scale = nullptr;         // [1]
+    uint64_t *sumS = nullptr;       // [1] short-window sample sum
+    uint64_t *csum = nullptr;       // [ring][kCycleSumBlocks] per-cycle partial sums
+    float *gate_dev = nullptr;      // [out_slots]
+    float *gate_host = nullptr;     // pinned [out_slots]
+    int ring = 0;
     uint8_t *pin = nullptr;         // [kPinnedFrames][H][W]
     size_t frame_bytes = 0;
     hipEvent_t pin_ev[kPinnedFrames] = {};
@@ -83,6 +103,17 @@ struct CycleRef {
     uint64_t t_arr;
     int warm;
     int out_slot;
+    float gate_thr;     // LEARNED: threshold the launch used
+};
+
+// The learned work of one job: cycles c0 .. c0+n-1 of a LEARNED stream.
+struct LearnedJob {
+    StreamRec *r;
+    qld_denoiser *dn;
+    const float *y, *gate;
+    float thr;
+    int64_t c0;
+    int n, out0, stage0;
 };
 
 struct Inflight {
@@ -121,7 +152,14 @@ namespace {
 
 int padded_w(int W, int eb) { return (int)(ceil_div(W, window_vpx(eb)) * window_vpx(eb)); }
 
-size_t stream_bytes(const qld_server *s, const qld_frame_desc *d, int M, int Ms) {
+int iq_planes(const qld_server *s, int Ms, int mode) {
+    const bool keep = s->flags & QLD_SERVER_KEEP_IQ;
+    return (keep ? 2 : 0) + ((keep || mode == QLD_MODE_LEARNED) && Ms > 0 ? 2 : 0);
+}
+
+int learned_ring(int Ms) { return Ms + kMaxCyclesPerJob; }
+
+size_t stream_bytes(const qld_server *s, const qld_frame_desc *d, int M, int Ms, int mode) {
     int eb = 0;
     if (check_desc(d, &eb) != QLD_OK) return 0;
     const size_t wb = window_bytes(d, M, Ms);
@@ -129,8 +167,12 @@ size_t stream_bytes(const qld_server *s, const qld_frame_desc *d, int M, int Ms)
     const size_t npx = (size_t)d->H * d->W;
     const size_t stage = (size_t)kStageCycles * 4 * d->H * padded_w(d->W, eb) * eb;
     const size_t out = (size_t)s->out_slots * npx * 4;
-    const size_t iq = (s->flags & 1) ? (size_t)s->out_slots * npx * 4 * (Ms > 0 ? 4 : 2) : 0;
-    return wb + stage + out + iq;
+    const size_t iq = (size_t)s->out_slots * npx * 4 * iq_planes(s, Ms, mode);
+    size_t learned = 0;
+    if (mode == QLD_MODE_LEARNED)
+        learned = (size_t)s->out_slots * npx * 4 + npx * 8 + (size_t)learned_ring(Ms) * kCycleSumBlocks * 8 +
+                  (size_t)s->out_slots * 4 + 64;
+    return wb + stage + out + iq + learned;
 }
 
 void free_stream_mem(StreamRec *r) {
@@ -140,9 +182,15 @@ void free_stream_mem(StreamRec *r) {
     if (r->out_amp) (void)hipFree(r->out_amp);
     if (r->out_iq) (void)hipFree(r->out_iq);
     if (r->pin) (void)hipHostFree(r->pin);
+    if (r->served) (void)hipFree(r->served);
+    if (r->x) (void)hipFree(r->x);
+    if (r->csum) (void)hipFree(r->csum);
+    if (r->gate_host) (void)hipHostFree(r->gate_host);
     r->stage = r->pin = nullptr;
     r->out_amp = nullptr;
-    r->out_iq = nullptr;
+    r->out_iq = r->Io = r->Qo = r->Iso = r->Qso = nullptr;
+    r->served = r->x = r->scale = r->gate_dev = r->gate_host = nullptr;
+    r->csum = r->sumS = nullptr;
     for (auto &e : r->pin_ev)
         if (e) (void)hipEventDestroy(e), e = nullptr;
     for (auto &e : r->slot_ev)
@@ -162,8 +210,37 @@ qld_status alloc_stream(qld_server *srv, StreamRec *r) {
     hipError_t e = hipMalloc(&r->stage, (size_t)kStageCycles * r->slot_b + 16);
     if (e == hipSuccess) e = hipMemset(r->stage, 0, (size_t)kStageCycles * r->slot_b + 16);
     if (e == hipSuccess) e = hipMalloc(&r->out_amp, (size_t)srv->out_slots * npx * 4 + 16);
-    if (e == hipSuccess && (srv->flags & 1))
-        e = hipMalloc(&r->out_iq, (size_t)srv->out_slots * npx * 4 * (r->Ms > 0 ? 4 : 2) + 16);
+    const int planes = iq_planes(srv, r->Ms, r->mode);
+    const size_t plane = (size_t)srv->out_slots * npx;
+    if (e == hipSuccess && planes > 0) e = hipMalloc(&r->out_iq, plane * 4 * planes + 16);
+    if (e == hipSuccess && planes > 0) {
+        int32_t *q = r->out_iq;
+        if (srv->flags & QLD_SERVER_KEEP_IQ) {
+            r->Io = q;
+            r->Qo = q + plane;
+            q += 2 * plane;
+        }
+        if (r->Ms > 0) {
+            r->Iso = q;
+            r->Qso = q + plane;
+        }
+    }
+    if (e == hipSuccess && r->mode == QLD_MODE_LEARNED) {
+        r->ring = learned_ring(r->Ms);
+        e = hipMalloc(&r->served, plane * 4 + 16);
+        // x [H][W][2] floats, then scale, gate slots (256-byte aligned pieces).
+        const size_t xb = (npx * 8 + 255) / 256 * 256, gb = ((size_t)srv->out_slots * 4 + 255) / 256 * 256;
+        if (e == hipSuccess) e = hipMalloc(&r->x, xb + 256 + gb);
+        if (e == hipSuccess) {
+            r->scale = reinterpret_cast<float *>(reinterpret_cast<uint8_t *>(r->x) + xb);
+            r->gate_dev = reinterpret_cast<float *>(reinterpret_cast<uint8_t *>(r->x) + xb + 256);
+            e = hipMalloc(&r->csum, ((size_t)r->ring * kCycleSumBlocks + 8) * 8);
+        }
+        if (e == hipSuccess) {
+            r->sumS = r->csum + (size_t)r->ring * kCycleSumBlocks;
+            e = hipHostMalloc(&r->gate_host, (size_t)srv->out_slots * 4 + 16, hipHostMallocDefault);
+        }
+    }
     if (e == hipSuccess) e = hipHostMalloc(&r->pin, (size_t)kPinnedFrames * r->frame_bytes + 16, hipHostMallocDefault);
     for (int i = 0; e == hipSuccess && i < kPinnedFrames; ++i)
         e = hipEventCreateWithFlags(&r->pin_ev[i], hipEventDisableTiming);
@@ -206,6 +283,38 @@ hipEvent_t take_event(qld_server *srv) {
     return e;
 }
 
+// Learned work of one job, enqueued on the compute stream after the window
+// update that wrote the job's short-window I/Q and plain amplitudes.
+hipError_t run_learned(qld_server *srv, const LearnedJob &L) {
+    StreamRec *r = L.r;
+    hipStream_t s = srv->compute;
+    const int64_t npx = (int64_t)r->d.H * r->d.W;
+    hipError_t e = launch_cycle_sums(r->stage, r->slot_b, kStageCycles, L.stage0, L.n, r->eb, r->csum, r->ring, L.c0,
+                                     kCycleSumBlocks, s);
+    for (int i = 0; i < L.n && e == hipSuccess; ++i) {
+        const int64_t c = L.c0 + i;
+        const int o = (L.out0 + i) % srv->out_slots;
+        const float *plain = r->out_amp + (size_t)o * npx;
+        float *served = r->served + (size_t)o * npx;
+        const float inv_n = 1.0f / (float)std::min<int64_t>(c + 1, r->M);
+        if (c + 1 >= r->Ms) {
+            e = launch_window_sum(r->csum, r->ring, kCycleSumBlocks, c, r->Ms, r->sumS, s);
+            if (e == hipSuccess &&
+                (qld_denoise_prepare(r->Iso + (size_t)o * npx, r->Qso + (size_t)o * npx, r->sumS, r->Ms, 1, r->d.H,
+                                     r->d.W, r->x, r->scale, s) != QLD_OK ||
+                 qld_denoiser_forward(L.dn, r->x, 1, nullptr, nullptr, s) != QLD_OK))
+                e = hipErrorLaunchFailure;
+            if (e == hipSuccess) e = launch_serve(L.y, r->scale, L.gate, plain, npx, L.thr, inv_n, served,
+                                                  r->gate_dev + o, s);
+        } else {
+            e = launch_serve(nullptr, nullptr, nullptr, plain, npx, L.thr, inv_n, served, r->gate_dev + o, s);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->gate_host + o, r->gate_dev + o, sizeof(float), hipMemcpyDeviceToHost, s);
+    }
+    return e;
+}
+
 void scheduler_loop(qld_server *srv) {
     (void)hipSetDevice(srv->device);
     std::unique_lock<std::mutex> lk(srv->mu);
@@ -233,6 +342,7 @@ void scheduler_loop(qld_server *srv) {
         for (auto &g : groups) {
             WinBatch b{};
             std::vector<CycleRef> refs;
+            std::vector<LearnedJob> ljobs;
             std::vector<hipEvent_t> waits;
             int tiles = 0;
             for (StreamRec *r : g.second) {
@@ -241,8 +351,10 @@ void scheduler_loop(qld_server *srv) {
                 const int64_t k0 = r->ready.front();
                 const int slot0 = (int)(k0 % kStageCycles);
                 const bool fresh = r->slot_reset[slot0];
+                // A job's cycles each need their own output slot.
+                const int max_n = std::min(kMaxCyclesPerJob, srv->out_slots);
                 int n = 0;
-                while (n < (int)r->ready.size() && n < kMaxCyclesPerJob) {
+                while (n < (int)r->ready.size() && n < max_n) {
                     const int64_t k = r->ready[n];
                     if (n > 0 && r->slot_reset[k % kStageCycles]) break;   // a reset starts its own job
                     ++n;
@@ -269,18 +381,11 @@ void scheduler_loop(qld_server *srv) {
                 J.Is = r->win->Is;
                 J.Qs = r->win->Qs;
                 J.amp = r->out_amp;
-                if (r->out_iq) {
-                    const int per = r->Ms > 0 ? 4 : 2;
-                    // Slot layout: [out_slots][per][H][W]; the kernel indexes
-                    // slot * npx, so each plane gets its own base and stride.
-                    (void)per;
-                    J.Io = r->out_iq;
-                    J.Qo = r->out_iq + (size_t)srv->out_slots * npx;
-                    if (r->Ms > 0) {
-                        J.Iso = r->out_iq + 2 * (size_t)srv->out_slots * npx;
-                        J.Qso = r->out_iq + 3 * (size_t)srv->out_slots * npx;
-                    }
-                }
+                J.Io = r->Io;
+                J.Qo = r->Qo;
+                J.Iso = r->Iso;
+                J.Qso = r->Qso;
+                (void)npx;
                 J.out_slots = srv->out_slots;
                 J.out0 = (int32_t)(k0 % srv->out_slots);
                 J.tiles = (int32_t)ceil_div((int64_t)r->d.H * (J.Wp / window_vpx(r->eb)), 256);
@@ -294,8 +399,10 @@ void scheduler_loop(qld_server *srv) {
                     waits.push_back(r->slot_ev[sl]);
                     const int64_t c = c0 + i;
                     refs.push_back(CycleRef{r, k, r->slot_cam_cycle[sl], r->slot_tarr[sl], c + 1 >= r->M ? 1 : 0,
-                                            (int)(k % srv->out_slots)});
+                                            (int)(k % srv->out_slots), r->gate_thr});
                 }
+                if (r->mode == QLD_MODE_LEARNED)
+                    ljobs.push_back(LearnedJob{r, r->dn, r->dn_y, r->dn_gate, r->gate_thr, c0, n, J.out0, slot0});
                 r->win_c = c0 + n;
                 r->launched += n;
             }
@@ -310,6 +417,8 @@ void scheduler_loop(qld_server *srv) {
                 if (e == hipSuccess) e = hipStreamWaitEvent(srv->compute, w, 0);
             // Staging rows are padded to 16-byte multiples: the vector path always applies.
             if (e == hipSuccess) e = launch_window_batch(b, eb, wide, true, srv->compute);
+            for (const LearnedJob &L : ljobs)
+                if (e == hipSuccess) e = run_learned(srv, L);
             if (e == hipSuccess && ev) e = hipEventRecord(ev, srv->compute);
             lk.lock();
             if (e != hipSuccess || !ev) {
@@ -353,8 +462,14 @@ void completion_loop(qld_server *srv) {
             res.t_arrival_ns = c.t_arr;
             res.t_done_ns = t;
             res.amp = r->out_amp + (size_t)c.out_slot * r->d.H * r->d.W;
+            res.amp_plain = res.amp;
             res.H = r->d.H;
             res.W = r->d.W;
+            if (r->mode == QLD_MODE_LEARNED) {
+                res.amp = r->served + (size_t)c.out_slot * r->d.H * r->d.W;
+                res.gate = r->gate_host[c.out_slot];
+                res.learned = (res.gate == res.gate && res.gate <= c.gate_thr) ? 1 : 0;
+            }
             srv->results.push_back(res);
             r->done++;
             srv->cycles++;
@@ -403,9 +518,9 @@ extern "C" qld_status qld_server_create(size_t hbm_budget_bytes, int32_t out_slo
 }
 
 extern "C" size_t qld_server_stream_bytes(const qld_server *s, const qld_frame_desc *d, int32_t M_cycles,
-                                          int32_t M_short) {
-    if (!s) return 0;
-    return stream_bytes(s, d, M_cycles, M_short);
+                                          int32_t M_short, int32_t mode) {
+    if (!s || (mode != QLD_MODE_PLAIN && mode != QLD_MODE_LEARNED)) return 0;
+    return stream_bytes(s, d, M_cycles, M_short, mode);
 }
 
 extern "C" qld_status qld_stream_open(qld_server *s, const qld_frame_desc *d, int32_t M_cycles, int32_t M_short,
@@ -421,7 +536,8 @@ extern "C" qld_status qld_stream_open(qld_server *s, const qld_frame_desc *d, in
         set_error("a stream needs frames of at least 1x1 pixels");
         return QLD_E_SHAPE;
     }
-    if (M_cycles < 1 || M_short < 0 || M_short > M_cycles || mode != QLD_MODE_PLAIN) {
+    if (M_cycles < 1 || M_short < 0 || M_short > M_cycles || (mode != QLD_MODE_PLAIN && mode != QLD_MODE_LEARNED) ||
+        (mode == QLD_MODE_LEARNED && M_short < 1)) {
         set_error("invalid window M=%d short=%d mode=%d", M_cycles, M_short, mode);
         return QLD_E_INVAL;
     }
@@ -429,7 +545,7 @@ extern "C" qld_status qld_stream_open(qld_server *s, const qld_frame_desc *d, in
         set_error("M=%d cycles of %d-bit data could overflow int32", M_cycles, d->bits);
         return QLD_E_OVERFLOW;
     }
-    const size_t need = stream_bytes(s, d, M_cycles, M_short);
+    const size_t need = stream_bytes(s, d, M_cycles, M_short, mode);
     if (need == 0 || need > s->budget) {
         set_error("stream needs %zu bytes, budget is %zu", need, s->budget);
         return QLD_E_BUDGET;
@@ -473,6 +589,36 @@ extern "C" qld_status qld_stream_state(qld_server *s, int32_t stream_id, int32_t
     return QLD_OK;
 }
 
+extern "C" qld_status qld_stream_set_denoiser(qld_server *s, int32_t stream_id, qld_denoiser *dn,
+                                             float gate_threshold) {
+    clear_error();
+    if (!s || !dn || gate_threshold != gate_threshold) {
+        set_error("server and denoiser must be non-NULL and the threshold a number");
+        return QLD_E_INVAL;
+    }
+    int32_t H = 0, W = 0, mb = 0;
+    QLD_TRY(qld_denoiser_info(dn, &H, &W, &mb));
+    void *y = nullptr, *g = nullptr;
+    int64_t cnt = 0;
+    QLD_TRY(qld_denoiser_tensor(dn, 4, &y, &cnt));
+    QLD_TRY(qld_denoiser_tensor(dn, 8, &g, &cnt));
+    std::lock_guard<std::mutex> lk(s->mu);
+    StreamRec *r = find_stream(s, stream_id);
+    if (!r || r->state == QLD_STREAM_CLOSED || r->mode != QLD_MODE_LEARNED) {
+        set_error("stream %d is not an open LEARNED stream", stream_id);
+        return r ? QLD_E_STATE : QLD_E_INVAL;
+    }
+    if (H != r->d.H || W != r->d.W) {
+        set_error("denoiser is %dx%d, stream is %dx%d", H, W, r->d.H, r->d.W);
+        return QLD_E_SHAPE;
+    }
+    r->dn = dn;
+    r->dn_y = static_cast<const float *>(y);
+    r->dn_gate = static_cast<const float *>(g);
+    r->gate_thr = gate_threshold;
+    return QLD_OK;
+}
+
 extern "C" qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const void *host_frame,
                                         int64_t frame_index, uint64_t t_arrival_ns) {
     clear_error();
@@ -490,6 +636,10 @@ extern "C" qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const 
     if (r->state == QLD_STREAM_PENDING) {
         set_error("stream %d is waiting for admission", stream_id);
         return QLD_E_AGAIN;
+    }
+    if (r->mode == QLD_MODE_LEARNED && !r->dn) {
+        set_error("stream %d is LEARNED and has no denoiser", stream_id);
+        return QLD_E_STATE;
     }
     if (frame_index < r->next_frame) {
         set_error("frame index %lld < expected %lld", (long long)frame_index, (long long)r->next_frame);
@@ -670,11 +820,14 @@ extern "C" qld_status qld_stream_result_iq(qld_server *s, const qld_result *res,
         return QLD_E_STATE;
     }
     const size_t npx = (size_t)r->d.H * r->d.W;
-    const size_t slot = (size_t)(res->amp - r->out_amp) / npx;
-    const size_t plane = (size_t)s->out_slots * npx;
-    if (I) *I = r->out_iq + slot * npx;
-    if (Q) *Q = r->out_iq + plane + slot * npx;
-    if (Is) *Is = r->Ms > 0 ? r->out_iq + 2 * plane + slot * npx : nullptr;
-    if (Qs) *Qs = r->Ms > 0 ? r->out_iq + 3 * plane + slot * npx : nullptr;
+    const size_t slot = (size_t)(res->amp_plain - r->out_amp) / npx;
+    if (slot >= (size_t)s->out_slots) {
+        set_error("result does not belong to stream %d", res->stream_id);
+        return QLD_E_INVAL;
+    }
+    if (I) *I = r->Io ? r->Io + slot * npx : nullptr;
+    if (Q) *Q = r->Qo ? r->Qo + slot * npx : nullptr;
+    if (Is) *Is = r->Iso ? r->Iso + slot * npx : nullptr;
+    if (Qs) *Qs = r->Qso ? r->Qso + slot * npx : nullptr;
     return QLD_OK;
 }

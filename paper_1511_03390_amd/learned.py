@@ -59,14 +59,19 @@ class Batch:
         self.invS = torch.full((B,), 1.0 / M_S, dtype=torch.float32, device="cuda")
 
 
-def tile_batch(step, batch, H, W, M_S, M_L, seed, ballistic=5e-4, background=2000.0):
-    p = scenes.tile_params(scenes.seed_for(4, step), batch, H=H, W=W, background=background, ballistic=ballistic,
-                           smin=16, smax=256)
+TILES_CONFIG4 = dict(background=2000.0, ballistic=5e-4, smin=16, smax=256, max_rects=5)
+
+
+def tile_batch(step, batch, H, W, M_S, M_L, seed, tiles=None):
+    """Generated batch number ``step``: scene parameters from the tile recipe
+    ``tiles`` (keyword arguments of scenes.tile_params; default: 1-5 rectangles
+    of sides 16-256 at ballistic fraction 5e-4 of a 2000-count background)."""
+    p = scenes.tile_params(scenes.seed_for(4, step), batch, H=H, W=W, **(tiles or TILES_CONFIG4))
     return Batch(p, M_S, M_L, tile0=step * batch, seed=seed)
 
 
 def train(steps=200, batch=8, H=512, W=512, M_S=8, M_L=512, lr=2e-3, seed=1511033904, gate_weight=0.1,
-          log=None, first_step=0):
+          log=None, first_step=0, tiles=None):
     d = qld.Denoiser(H, W, batch)
     d.set_params(he_init(seed))
     y = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
@@ -74,7 +79,7 @@ def train(steps=200, batch=8, H=512, W=512, M_S=8, M_L=512, lr=2e-3, seed=151103
     hist = []
     t0 = time.perf_counter()
     for s in range(steps):
-        b = tile_batch(first_step + s, batch, H, W, M_S, M_L, seed)
+        b = tile_batch(first_step + s, batch, H, W, M_S, M_L, seed, tiles)
         d.forward(b.x, y)
         nl = qld.judge_nrmse(y, b.clean, b.scale)
         npl = qld.judge_nrmse(b.ampL, b.clean, b.invL)
@@ -90,14 +95,14 @@ def train(steps=200, batch=8, H=512, W=512, M_S=8, M_L=512, lr=2e-3, seed=151103
 
 
 def evaluate(d, n_batches=2, batch=8, H=512, W=512, M_S=8, M_L=512, seed=1511033904, first_step=10 ** 6,
-             gate_threshold=0.05):
+             gate_threshold=0.05, tiles=None):
     """NRMSE against the noise-free per-cycle amplitude on held-out tiles."""
     y = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
     gate = torch.empty(batch, dtype=torch.float32, device="cuda")
     acc = {k: [] for k in ("learned", "plain_S", "plain_L", "plain_L_bias_reduced", "served", "gate",
                            "learned_vs_noisy_L")}
     for k in range(n_batches):
-        b = tile_batch(first_step + k, batch, H, W, M_S, M_L, seed)
+        b = tile_batch(first_step + k, batch, H, W, M_S, M_L, seed, tiles)
         d.forward(b.x, y, gate)
         acc["learned"].append(qld.judge_nrmse(y, b.clean, b.scale).cpu().numpy())
         acc["plain_S"].append(qld.judge_nrmse(b.ampS, b.clean, b.invS).cpu().numpy())

@@ -244,20 +244,147 @@ def tile_params(seed, n_tiles, H=512, W=512, background=2000.0, ballistic=5e-4,
     Returns dict with ``mask`` uint8 [n][H][W] and ``rates`` float64 [n][2][4]:
     rates[i][0][j] = background (outside), rates[i][1][j] =
     background + ballistic*background*(1 + cos(pi j / 2 + phi_i)) for phase j.
-    Also ``phi`` [n].
+    Also ``phi`` [n].  ``ballistic`` may be a pair (lo, hi): then each tile
+    draws its fraction log-uniformly from [lo, hi].
     """
     rng = np.random.default_rng(seed)
     masks = np.zeros((n_tiles, H, W), dtype=np.uint8)
     rates = np.zeros((n_tiles, 2, 4), dtype=np.float64)
     phis = np.zeros(n_tiles)
-    A = ballistic * background
     for i in range(n_tiles):
         n = int(rng.integers(1, max_rects + 1))
         m, _ = rect_masks(rng, H, W, n, smin, min(smax, H, W))
         masks[i] = m
         phi = float(rng.uniform(0, 2 * math.pi))
         phis[i] = phi
+        if isinstance(ballistic, (tuple, list)):
+            A = background * math.exp(rng.uniform(math.log(ballistic[0]), math.log(ballistic[1])))
+        else:
+            A = ballistic * background
         for j in range(4):
             rates[i, 0, j] = background
             rates[i, 1, j] = background + A * (1.0 + math.cos(math.pi * j / 2.0 + phi))
     return dict(mask=masks, rates=rates, phi=phis, background=background, ballistic=ballistic)
+
+
+class ClutterMotionScene:
+    """A camera scene with moving sources and clutter, rendered on a device.
+
+    1024 x 1024 frames with 12-bit Poisson samples, four frames per modulation
+    period (frame t has phase t mod 4), of rate
+
+      background 2000
+      + 6 point sources: Gaussian spots (sigma 1.5 px) of ballistic amplitude
+        20 counts, modulated 20 (1 + cos(pi t / 2 + phi_i + 0.01 c)) (a phase
+        drift of 0.01 rad per cycle c = t // 4), moving at U[0, 2] px per cycle
+        in random directions (wrapping at the frame edges)
+      + 2 clutter spots (sigma 4 px) of amplitude 200 modulated at 1.5 times
+        the lock-in frequency, 200 (1 + cos(3 pi t / 4 + psi_j))
+      + 2 steady clutter spots (sigma 4 px) of 200 counts
+      + an extended disk (radius 64) of ballistic fraction 1e-4 (0.2 counts),
+        0.2 (1 + cos(pi t / 2 + phi_d)).
+
+    ``rates(t)`` renders the rate of frame t; ``signal_rates(t)`` only the
+    terms modulated at the lock-in frequency (points and disk), the
+    noise-free signal the images are judged against; ``frames(c0, n)`` draws
+    the Poisson frames of cycles c0 .. c0+n-1 from a seeded device generator.
+    """
+
+    N_POINTS, N_CLUTTER_AC, N_CLUTTER_DC = 6, 2, 2
+
+    def __init__(self, seed, H=1024, W=1024, device="cuda", background=2000.0, point_amp=20.0, psf_sigma=1.5,
+                 drift=0.01, vmax=2.0, clutter_amp=200.0, clutter_sigma=4.0, disk_r=64, disk_frac=1e-4, bits=12):
+        import torch
+        self.torch = torch
+        rng = np.random.default_rng(seed)
+        self.seed, self.H, self.W, self.device, self.bits = seed, H, W, device, bits
+        self.background, self.point_amp, self.psf_sigma, self.drift = background, point_amp, psf_sigma, drift
+        self.clutter_amp, self.clutter_sigma = clutter_amp, clutter_sigma
+        m = 3 * disk_r
+        self.p0 = np.stack([rng.uniform(16, H - 16, self.N_POINTS), rng.uniform(16, W - 16, self.N_POINTS)], 1)
+        speed = rng.uniform(0, vmax, self.N_POINTS)
+        ang = rng.uniform(0, 2 * math.pi, self.N_POINTS)
+        self.v = np.stack([speed * np.sin(ang), speed * np.cos(ang)], 1)        # px per cycle (y, x)
+        self.phi = rng.uniform(0, 2 * math.pi, self.N_POINTS)
+        nc = self.N_CLUTTER_AC + self.N_CLUTTER_DC
+        self.clutter = np.stack([rng.uniform(32, H - 32, nc), rng.uniform(32, W - 32, nc)], 1)
+        self.psi = rng.uniform(0, 2 * math.pi, self.N_CLUTTER_AC)
+        self.disk = (float(rng.uniform(m, H - m)), float(rng.uniform(m, W - m)), disk_r)
+        self.phi_d = float(rng.uniform(0, 2 * math.pi))
+        self.disk_amp = disk_frac * background
+        yy = torch.arange(H, device=device, dtype=torch.float32)[:, None]
+        xx = torch.arange(W, device=device, dtype=torch.float32)[None, :]
+        self.yy, self.xx = yy, xx
+        cy, cx, r = self.disk
+        self.disk_mask = (((yy - cy) ** 2 + (xx - cx) ** 2) <= r * r).to(torch.float32)
+        cl = torch.zeros((nc, H, W), device=device)
+        for j in range(nc):
+            cl[j] = torch.exp(-((yy - self.clutter[j, 0]) ** 2 + (xx - self.clutter[j, 1]) ** 2)
+                              / (2 * clutter_sigma ** 2))
+        self.cl = cl
+        self.gen = torch.Generator(device=device)
+        self.gen.manual_seed(int(seed))
+
+    def point_positions(self, t):
+        """(y, x) of the point sources at frame t (wrapped into the frame)."""
+        p = self.p0 + self.v * (t / 4.0)
+        return np.stack([np.mod(p[:, 0], self.H), np.mod(p[:, 1], self.W)], 1)
+
+    def _spots(self, t):
+        torch = self.torch
+        pos = self.point_positions(t)
+        c = t // 4
+        out = torch.zeros((self.H, self.W), device=self.device)
+        for i in range(self.N_POINTS):
+            dy = torch.remainder(self.yy - float(pos[i, 0]) + self.H / 2, self.H) - self.H / 2
+            dx = torch.remainder(self.xx - float(pos[i, 1]) + self.W / 2, self.W) - self.W / 2
+            g = torch.exp(-(dy * dy + dx * dx) / (2 * self.psf_sigma ** 2))
+            out += g * (self.point_amp * (1.0 + math.cos(math.pi * t / 2 + self.phi[i] + self.drift * c)))
+        return out
+
+    def signal_rates(self, t):
+        return self._spots(t) + self.disk_mask * (self.disk_amp * (1.0 + math.cos(math.pi * t / 2 + self.phi_d)))
+
+    def rates(self, t):
+        lam = self.signal_rates(t) + self.background
+        for j in range(self.N_CLUTTER_AC):
+            lam += self.cl[j] * (self.clutter_amp * (1.0 + math.cos(3 * math.pi * t / 4 + self.psi[j])))
+        for j in range(self.N_CLUTTER_DC):
+            lam += self.cl[self.N_CLUTTER_AC + j] * self.clutter_amp
+        return lam
+
+    def frames(self, c0, n_cycles):
+        """uint16 samples (as a torch int16 tensor [4 n][H][W] on the device)."""
+        torch = self.torch
+        top = float((1 << self.bits) - 1)
+        out = torch.empty((4 * n_cycles, self.H, self.W), dtype=torch.int16, device=self.device)
+        for k in range(4 * n_cycles):
+            lam = self.rates(4 * c0 + k)
+            out[k] = torch.clamp(torch.poisson(lam, generator=self.gen), max=top).to(torch.int32).to(torch.int16)
+        return out
+
+    def source_regions(self, t):
+        """(name, source mask, surround mask) per source at frame t, as numpy bool
+        [H][W]: a 3 x 3 block and its 3-px ring for the spots (points and
+        clutter), the disk and the annulus r..3r for the disk (clipped)."""
+        H, W = self.H, self.W
+        out = []
+
+        def block(cy, cx, half):
+            m = np.zeros((H, W), dtype=bool)
+            y, x = int(round(cy)) % H, int(round(cx)) % W
+            m[max(0, y - half):y + half + 1, max(0, x - half):x + half + 1] = True
+            return m
+
+        for i, (cy, cx) in enumerate(self.point_positions(t)):
+            src = block(cy, cx, 1)
+            out.append(("point%d" % i, src, block(cy, cx, 4) & ~src))
+        for j, (cy, cx) in enumerate(self.clutter):
+            kind = "clutter_1.5f%d" % j if j < self.N_CLUTTER_AC else "clutter_dc%d" % (j - self.N_CLUTTER_AC)
+            src = block(cy, cx, 1)
+            out.append((kind, src, block(cy, cx, 4) & ~src))
+        cy, cx, r = self.disk
+        yy, xx = np.mgrid[0:H, 0:W]
+        d2 = (yy - cy) ** 2 + (xx - cx) ** 2
+        out.append(("disk", d2 <= r * r, (d2 > r * r) & (d2 <= 9 * r * r)))
+        return out
