@@ -24,16 +24,18 @@
 //     are combined with int32 atomics (exact, order-free).  The splits of one
 //     tile sit on the same XCD (work-group ids are dealt round-robin over the
 //     8 XCDs), so their atomics meet in one L2;
-//   * per-frame statistics: the lane sum (v_dot2_u32_u16 / v_sad_u8) is reduced
-//     across the wave with DPP row shifts and row broadcasts, and written into
-//     lane `slot` of a buffer register that is stored every 64
-//     frames as per-wave partials; a small kernel folds them into frame_sum.
-//     Clipped samples are rare: a packed max per frame detects whether any
-//     sample reaches 2^bits - 1 and only then are they counted with ballots.
+//   * per-frame statistics: each lane's sum of its samples (v_dot2_u32_u16 /
+//     v_sad_u8) goes to LDS, one row per frame; every 64 frames lane j adds up
+//     row j, which transposes the cross-lane reduction into plain adds, and
+//     stores the per-wave partial; a small kernel folds the partials into
+//     frame_sum.  Clipped samples are rare: a packed max per frame detects
+//     whether any sample reaches 2^bits - 1 and only then are they counted
+//     with ballots.  (The scalar kernel reduces with DPP row shifts instead.)
 #include "qld_internal.hpp"
 
 namespace qld {
 namespace {
+
 
 constexpr int kBlock = 256;            // lanes per work-group (4 waves)
 constexpr int kWavesPerBlock = kBlock / 64;
@@ -106,6 +108,95 @@ struct Stats {
     uint32_t *part_sum, *part_sat;
 };
 
+// Per-wave, per-frame statistics of the vector kernel, transposed through LDS:
+// each lane writes its lane sum of frame slot j into row j of a
+// [kStatsSlots][65]-word buffer (one store per frame, consecutive banks); at a
+// flush lane j adds up row j (the padding column puts the lanes' reads in
+// different banks) and stores that frame's wave partial.  Slots follow the
+// wave's frames in order (cycle k0 + j/4, phase j%4), so a slot's frame index
+// is computed at the flush instead of being carried.  The saturation count is
+// wave-uniform; it is written into lane j's register only for frames that have
+// a clipped sample (rare), else stays 0.
+constexpr int kStatsRow = 65;
+constexpr int kStatsSlots = 64;   // frames buffered per wave between flushes (multiple of 4)
+
+struct StatsLds {
+    uint32_t buf_sat = 0;
+    int slot = 0;
+    int64_t k0 = 0;                      // wave cycle index of slot 0
+    int64_t split = 0, S = 1;            // frame of (cycle k, phase j) = 4 (split + k S) + j
+    int64_t row;
+    uint32_t *lds;                       // this wave's [kStatsSlots][kStatsRow] words
+    uint32_t *part_sum, *part_sat;
+
+    __device__ __forceinline__ void put(uint32_t lane_sum) {
+        lds[slot * kStatsRow + (int)(threadIdx.x & 63)] = lane_sum;
+        ++slot;
+    }
+    __device__ __forceinline__ void sat(int j, uint32_t wave_sat) {   // slot j's clipped count
+        buf_sat = (int)(threadIdx.x & 63) == j ? wave_sat : buf_sat;
+    }
+
+    __device__ __forceinline__ void flush() {
+        const int lane = (int)(threadIdx.x & 63);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < slot) {
+            const uint32_t *r = lds + lane * kStatsRow;
+            uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll 4
+            for (int i = 0; i < 64; i += 4) {
+                s0 += r[i];
+                s1 += r[i + 1];
+                s2 += r[i + 2];
+                s3 += r[i + 3];
+            }
+            const int64_t t = 4 * (split + (k0 + lane / 4) * S) + lane % 4;
+            part_sum[row + t] = (s0 + s1) + (s2 + s3);
+            part_sat[row + t] = buf_sat;
+        }
+        __builtin_amdgcn_wave_barrier();
+        k0 += slot / 4;
+        slot = 0;
+        buf_sat = 0;
+    }
+};
+
+// Lane sum of one 16-byte group of samples.
+template <int ELEM>
+__device__ __forceinline__ uint32_t lane_sum16(const u32x4 &d) {
+    if constexpr (ELEM == 2) {
+        const u16x2 one = {1, 1};
+        uint32_t s = __builtin_amdgcn_udot2(h2(d[0]), one, 0u, false);
+        s = __builtin_amdgcn_udot2(h2(d[1]), one, s, false);
+        s = __builtin_amdgcn_udot2(h2(d[2]), one, s, false);
+        return __builtin_amdgcn_udot2(h2(d[3]), one, s, false);
+    } else {
+        uint32_t s = __builtin_amdgcn_sad_u8(d[0], 0u, 0u);
+        s = __builtin_amdgcn_sad_u8(d[1], 0u, s);
+        s = __builtin_amdgcn_sad_u8(d[2], 0u, s);
+        return __builtin_amdgcn_sad_u8(d[3], 0u, s);
+    }
+}
+
+// Largest sample of a lane's 16-byte group, as packed 16-bit halves.
+template <int ELEM>
+__device__ __forceinline__ u16x2 lane_max16(const u32x4 &d) {
+    if constexpr (ELEM == 2) {
+        return __builtin_elementwise_max(__builtin_elementwise_max(h2(d[0]), h2(d[1])),
+                                         __builtin_elementwise_max(h2(d[2]), h2(d[3])));
+    } else {
+        // Even and odd bytes widened to 16-bit halves.
+        const uint32_t b = 0x00ff00ffu;
+        u16x2 mx = h2(d[0] & b);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k) mx = __builtin_elementwise_max(mx, h2(d[k] & b));
+            mx = __builtin_elementwise_max(mx, h2((d[k] >> 8) & b));
+        }
+        return mx;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Vector kernel: 16 bytes per lane.
 // ---------------------------------------------------------------------------
@@ -131,39 +222,26 @@ __device__ __forceinline__ uint32_t count_top(const u32x4 &d, uint32_t top) {
     return c;
 }
 
-template <int ELEM, bool STATS>
-__device__ __forceinline__ void frame_stats(const u32x4 &d, uint32_t top, Stats &st, uint32_t t) {
-    uint32_t s;
-    uint32_t m;
-    if constexpr (ELEM == 2) {
-        const u16x2 one = {1, 1};
-        s = __builtin_amdgcn_udot2(h2(d[0]), one, 0u, false);
-        s = __builtin_amdgcn_udot2(h2(d[1]), one, s, false);
-        s = __builtin_amdgcn_udot2(h2(d[2]), one, s, false);
-        s = __builtin_amdgcn_udot2(h2(d[3]), one, s, false);
-        u16x2 mx = __builtin_elementwise_max(__builtin_elementwise_max(h2(d[0]),
-                                                                       h2(d[1])),
-                                             __builtin_elementwise_max(h2(d[2]),
-                                                                       h2(d[3])));
-        m = max((uint32_t)mx[0], (uint32_t)mx[1]);
-    } else {
-        s = __builtin_amdgcn_sad_u8(d[0], 0u, 0u);
-        s = __builtin_amdgcn_sad_u8(d[1], 0u, s);
-        s = __builtin_amdgcn_sad_u8(d[2], 0u, s);
-        s = __builtin_amdgcn_sad_u8(d[3], 0u, s);
-        // Largest byte: even and odd bytes widened to 16-bit halves, packed max.
-        const uint32_t b = 0x00ff00ffu;
-        u16x2 mx = h2(d[0] & b);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (k) mx = __builtin_elementwise_max(mx, h2(d[k] & b));
-            mx = __builtin_elementwise_max(mx, h2((d[k] >> 8) & b));
-        }
-        m = max((uint32_t)mx[0], (uint32_t)mx[1]);
-    }
-    uint32_t c = 0;
-    if (__ballot(m >= top)) c = count_top<ELEM>(d, top);   // rare: clipped samples present
-    st.put(s, c, t);
+// Statistics of one frame: its lane sum into the LDS buffer; a packed max tells
+// whether any sample is clipped, and only then are they counted with ballots.
+// (Checking once per cycle instead measured slower on MI355X.)
+template <int ELEM>
+__device__ __forceinline__ void frame_stats(const u32x4 &d, uint32_t top, StatsLds &st) {
+    const int j = st.slot;
+    st.put(lane_sum16<ELEM>(d));
+    const u16x2 mx = lane_max16<ELEM>(d);
+    if (__ballot(max((uint32_t)mx[0], (uint32_t)mx[1]) >= top)) st.sat(j, count_top<ELEM>(d, top));
+}
+
+// Statistics of one cycle (four frames) of the vector kernel.
+template <int ELEM>
+__device__ __forceinline__ void cycle_stats(const u32x4 &d0, const u32x4 &d1, const u32x4 &d2, const u32x4 &d3,
+                                            uint32_t top, StatsLds &st) {
+    frame_stats<ELEM>(d0, top, st);
+    frame_stats<ELEM>(d1, top, st);
+    frame_stats<ELEM>(d2, top, st);
+    frame_stats<ELEM>(d3, top, st);
+    if (st.slot == kStatsSlots) st.flush();
 }
 
 // Accumulators of one lane: int32 I/Q per pixel plus packed 16-bit partials.
@@ -252,7 +330,7 @@ __device__ __forceinline__ u32x4 ld16(const uint8_t *p) {
 // MASKED: some lanes of this work-group are past the last vector; they read
 // a valid address and zero what they read.
 template <int ELEM, bool STATS, bool PACKED, bool MASKED>
-__device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split) {
+__device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split, uint32_t *stats_lds) {
     constexpr int kPx = 16 / ELEM;
     const int nvx = a.ncols / kPx;
     const int64_t n_vec = (int64_t)nvx * a.H;
@@ -274,11 +352,14 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
 
     Acc<ELEM> acc;
     acc.zero();
-    Stats st;
+    StatsLds st;
     if constexpr (STATS) {
         st.part_sum = a.part_sum;
         st.part_sat = a.part_sat;
         st.row = ((int64_t)a.wave_base + (int64_t)tile * kWavesPerBlock + (threadIdx.x >> 6)) * a.n_frames;
+        st.lds = stats_lds + (threadIdx.x >> 6) * kStatsSlots * kStatsRow;
+        st.split = split;
+        st.S = a.n_split;
     }
     auto load = [&](const uint8_t *q) {
         u32x4 d = ld16(q);
@@ -288,7 +369,7 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
     const int fold_every = ELEM == 2 ? (int)(32767u / max(a.top, 1u)) : 128;
 
     int since_fold = 0;
-    auto process = [&](const u32x4 &s0, const u32x4 &s1, const u32x4 &s2, const u32x4 &s3, int64_t k) {
+    auto process = [&](const u32x4 &s0, const u32x4 &s1, const u32x4 &s2, const u32x4 &s3) {
         if constexpr (PACKED) {
             acc.cycle(s0, s1, s2, s3);
             if (++since_fold == fold_every) {
@@ -301,21 +382,18 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
             acc.frame32(s2, -1, 0);
             acc.frame32(s3, 0, -1);
         }
-        if constexpr (STATS) {
-            const uint32_t t = (uint32_t)(4 * (split + k * S));
-            frame_stats<ELEM, STATS>(s0, a.top, st, t);
-            frame_stats<ELEM, STATS>(s1, a.top, st, t + 1);
-            frame_stats<ELEM, STATS>(s2, a.top, st, t + 2);
-            frame_stats<ELEM, STATS>(s3, a.top, st, t + 3);
-        }
+        if constexpr (STATS) cycle_stats<ELEM>(s0, s1, s2, s3, a.top, st);
     };
-    // One cycle (four frames, 4 x 16 B per lane) per iteration.  Measured on
-    // MI355X: keeping only four frames in flight per wave streams faster than
-    // deeper unrolling or register double-buffering (fewer DRAM pages open).
+    // One cycle (four frames, 4 x 16 B per lane) per iteration.  The four
+    // loads are kept together ahead of the arithmetic (left to itself the
+    // compiler issued three, waited, then the fourth).  Measured on MI355X:
+    // four frames in flight per wave stream faster than deeper software
+    // pipelining with two register sets.
     for (int64_t k = 0; k < my; ++k) {
         const u32x4 s0 = load(p), s1 = load(p + fs), s2 = load(p + 2 * fs), s3 = load(p + 3 * fs);
+        __builtin_amdgcn_sched_barrier(0);
         p += step;
-        process(s0, s1, s2, s3, k);
+        process(s0, s1, s2, s3);
     }
     if constexpr (PACKED) acc.fold();
     // Partial cycle at the end of the stack: taken by the split next in turn.
@@ -325,7 +403,7 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
         for (int j = 0; j < rem; ++j) {
             const u32x4 s = load(q + j * fs);
             acc.frame32(s, j == 0 ? 1 : (j == 2 ? -1 : 0), j == 1 ? 1 : 0);
-            if constexpr (STATS) frame_stats<ELEM, STATS>(s, a.top, st, (uint32_t)(4 * n_cyc_all + j));
+            if constexpr (STATS) frame_stats<ELEM>(s, a.top, st);
         }
     }
     if constexpr (STATS) {
@@ -364,8 +442,13 @@ __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
     tile_and_split(a, tile, split);
     if (tile >= a.n_tiles) return;
     const int64_t n_vec = (int64_t)(a.ncols / (16 / ELEM)) * a.H;
-    if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split);
-    else vec_body<ELEM, STATS, PACKED, true>(a, tile, split);
+    uint32_t *lds = nullptr;
+    if constexpr (STATS) {
+        __shared__ uint32_t stats_lds[kWavesPerBlock * kStatsSlots * kStatsRow];
+        lds = stats_lds;
+    }
+    if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split, lds);
+    else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, lds);
 }
 
 // ---------------------------------------------------------------------------
