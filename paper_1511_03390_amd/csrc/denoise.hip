@@ -399,37 +399,60 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float *__restric
 }
 
 // Gate: pool[b][c] = mean_p a3[b][p][c]; gate[b] = pool[b] . Wg + bg.
+// Stage 1: each work-group sums a contiguous chunk of a tile's pixels (a lane
+// reads 8 channels of a pixel with one 16-byte load; 64 pixels per step) into
+// 32 per-chunk sums; stage 2 adds a tile's chunks in order, so the pooled
+// values do not depend on timing.
+int pool_chunks(int B) { return (int)std::max<int64_t>(64, std::min<int64_t>(1024, ceil_div(4096, B))); }
+
 __global__ __launch_bounds__(256) void pool_kernel(const __bf16 *__restrict__ a3, int64_t npx, int chunks,
                                                    float *__restrict__ part) {
+    __shared__ float red[64][33];
+    const int b = blockIdx.y, ch = blockIdx.x;
+    const int g = threadIdx.x & 3, r = threadIdx.x >> 2;
+    const int64_t per = ceil_div(npx, (int64_t)chunks);
+    const int64_t p0 = ch * per, p1 = std::min<int64_t>(npx, p0 + per);
+    const bf16x8 *src = reinterpret_cast<const bf16x8 *>(a3 + (int64_t)b * npx * 32) + g;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 2
+    for (int64_t p = p0 + r; p < p1; p += 64) {
+        const bf16x8 v = src[p * 4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[r][g * 8 + i] = acc[i];
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float t = 0.f;
+        for (int k = 0; k < 64; ++k) t += red[k][threadIdx.x];
+        part[((int64_t)b * chunks + ch) * 32 + threadIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void gate_fwd_kernel(const float *__restrict__ part, int chunks, int64_t npx,
+                                                       const float *__restrict__ p, float *__restrict__ pool,
+                                                       float *__restrict__ gate) {
     __shared__ float red[8][32];
-    const int b = blockIdx.x / chunks, ch = blockIdx.x % chunks;
-    const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const int64_t per = ceil_div(npx, chunks);
-    const int64_t p0 = ch * per, p1 = min(npx, p0 + per);
+    __shared__ float pooled[32];
+    const int b = blockIdx.x, c = threadIdx.x & 31, r = threadIdx.x >> 5;
     float s = 0.f;
-    for (int64_t p = p0 + g; p < p1; p += 8) s += (float)a3[((int64_t)b * npx + p) * 32 + c];
-    red[g][c] = s;
+    for (int k = r; k < chunks; k += 8) s += part[((int64_t)b * chunks + k) * 32 + c];
+    red[r][c] = s;
     __syncthreads();
     if (threadIdx.x < 32) {
         float t = 0.f;
         for (int k = 0; k < 8; ++k) t += red[k][c];
-        part[(int64_t)blockIdx.x * 32 + c] = t;
-    }
-}
-
-__global__ void gate_fwd_kernel(const float *__restrict__ part, int chunks, int64_t npx, const float *__restrict__ p,
-                                float *__restrict__ pool, float *__restrict__ gate, int B) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    float g = p[OFF_BG];
-    for (int c = 0; c < 32; ++c) {
-        float s = 0.f;
-        for (int k = 0; k < chunks; ++k) s += part[((int64_t)b * chunks + k) * 32 + c];
-        const float v = s / (float)npx;
+        const float v = t / (float)npx;
         pool[b * 32 + c] = v;
-        g = fmaf(v, p[OFF_WG + c], g);
+        pooled[c] = v;
     }
-    gate[b] = g;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float g = p[OFF_BG];
+        for (int k = 0; k < 32; ++k) g = fmaf(pooled[k], p[OFF_WG + k], g);
+        gate[b] = g;
+    }
 }
 
 // Gate gradient (its own loss, w * mean_b (gate - e)^2; e = ea - eb), one work-group.
@@ -502,7 +525,6 @@ namespace {
 
 constexpr int kGradBlocks = 256;     // work-groups of the MFMA weight-gradient reduction
 constexpr int kSmallBlocks = 1024;   // work-groups of the VALU gradient reductions
-constexpr int kPoolChunks = 64;
 constexpr int kLossBlocks = 256;
 
 template <typename T>
@@ -569,7 +591,7 @@ using namespace qld;
 
 extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batch, qld_denoiser **out) {
     clear_error();
-    if (!out || H < 1 || W < 1 || max_batch < 1) {
+    if (!out || H < 1 || W < 1 || max_batch < 1 || max_batch > 65535) {
         set_error("invalid denoiser shape %dx%d, batch %d", H, W, max_batch);
         return QLD_E_INVAL;
     }
@@ -579,7 +601,8 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     d->W = W;
     d->max_batch = max_batch;
     const size_t npx = (size_t)max_batch * H * W;
-    d->part_floats = std::max<int64_t>((int64_t)kGradBlocks * 9 * 1024, (int64_t)max_batch * kPoolChunks * 32);
+    d->part_floats = std::max<int64_t>((int64_t)kGradBlocks * 9 * 1024,
+                                       ((int64_t)max_batch * 64 + 4096 + max_batch) * 32);   // >= B * pool_chunks(B) * 32
     qld_status st = QLD_OK;
     if (st == QLD_OK) st = dalloc(d, &d->params, N_ALL);
     if (st == QLD_OK) st = dalloc(d, &d->grads, N_ALL);
@@ -727,10 +750,10 @@ extern "C" qld_status qld_denoiser_forward(qld_denoiser *d, const float *x, int3
     hipLaunchKernelGGL(conv_out_kernel, dim3((unsigned)ceil_div(npx, 256)), dim3(256), 0, s, d->a3, d->w4,
                        d->params + OFF_B4, d->y, B, H, W);
     if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
-    hipLaunchKernelGGL(pool_kernel, dim3(B * kPoolChunks), dim3(256), 0, s, d->a3, (int64_t)H * W, kPoolChunks,
-                       d->part);
-    hipLaunchKernelGGL(gate_fwd_kernel, dim3((unsigned)ceil_div(B, 64)), dim3(64), 0, s, d->part, kPoolChunks,
-                       (int64_t)H * W, d->params, d->pool, d->gate, B);
+    const int chunks = pool_chunks(B);
+    hipLaunchKernelGGL(pool_kernel, dim3(chunks, B), dim3(256), 0, s, d->a3, (int64_t)H * W, chunks, d->part);
+    hipLaunchKernelGGL(gate_fwd_kernel, dim3(B), dim3(256), 0, s, d->part, chunks, (int64_t)H * W, d->params, d->pool,
+                       d->gate);
     QLD_TRY(check_hip(hipGetLastError(), "forward launch"));
     if (y_out) QLD_TRY(check_hip(hipMemcpyAsync(y_out, d->y, npx * sizeof(float), hipMemcpyDeviceToDevice, s), "y copy"));
     if (gate_out)

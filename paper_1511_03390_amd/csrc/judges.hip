@@ -3,8 +3,9 @@
 // CNR follows the paper's Eq. CNR (Methods, "Estimation of contrast-to-noise
 // ratio"): (mean over the source - mean over the surround) divided by the RMS
 // of the surround about its own mean.  NRMSE(x) = RMS(x - ref) / RMS(ref) per
-// tile.  Both reduce in double precision with a fixed order (one work-group
-// per tile, tree reduction in LDS), so results are deterministic.
+// tile.  Both reduce in double precision with a fixed order (chunks of a tile
+// reduced by work-group trees, then the chunks added in order), so results are
+// deterministic.
 //
 // Learned-path preparation (not in the paper):
 //   b      = mean sample level of a window = sum / (H W 4 M)
@@ -78,30 +79,64 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[256]) {
     for (int k = 0; k < N; ++k) v[k] = red[k][0];
 }
 
-__global__ __launch_bounds__(256) void nrmse_kernel(const float *__restrict__ x, const float *__restrict__ scale,
-                                                    const float *__restrict__ ref, int64_t n, float *__restrict__ out) {
+// Two-stage fixed-order reductions: stage 1 splits each tile into `chunks`
+// contiguous pieces (enough work-groups to fill the GPU for any batch), each
+// reduced by a work-group tree into double partials; stage 2 adds a tile's
+// partials in chunk order.  The result depends only on (B, n), never on timing.
+constexpr int kJudgeBlocks = 1024;   // target work-groups of stage 1
+constexpr int kMaxChunks = 256;
+
+int judge_chunks(int B, int64_t n) {
+    const int64_t want = std::min<int64_t>(std::max<int64_t>(1, ceil_div(kJudgeBlocks, B)), kMaxChunks);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(n, 1024)));
+}
+
+__global__ __launch_bounds__(256) void nrmse_part_kernel(const float *__restrict__ x, const float *__restrict__ scale,
+                                                         const float *__restrict__ ref, int64_t n, int chunks,
+                                                         double *__restrict__ part) {
     __shared__ double red[2][256];
-    const int b = blockIdx.x;
+    const int b = blockIdx.y, ch = blockIdx.x;
+    const int64_t per = ceil_div(n, (int64_t)chunks);
+    const int64_t p0 = ch * per, p1 = std::min<int64_t>(n, p0 + per);
     const double sc = scale ? (double)scale[b] : 1.0;
+    const float *xb = x + (int64_t)b * n, *rb = ref + (int64_t)b * n;
     double v[2] = {0.0, 0.0};
-    for (int64_t p = threadIdx.x; p < n; p += 256) {
-        const double r = ref[(int64_t)b * n + p];
-        const double d = (double)x[(int64_t)b * n + p] * sc - r;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+        const double r = rb[p];
+        const double d = (double)xb[p] * sc - r;
         v[0] += d * d;
         v[1] += r * r;
     }
     block_sum<2>(v, red);
-    if (threadIdx.x == 0) out[b] = v[1] > 0.0 ? (float)sqrt(v[0] / v[1]) : 0.0f;
+    if (threadIdx.x == 0) {
+        part[((int64_t)b * chunks + ch) * 2] = v[0];
+        part[((int64_t)b * chunks + ch) * 2 + 1] = v[1];
+    }
 }
 
-__global__ __launch_bounds__(256) void cnr_kernel(const float *__restrict__ img, const uint8_t *__restrict__ lab,
-                                                  int64_t n, float *__restrict__ out) {
+__global__ void nrmse_final_kernel(const double *__restrict__ part, int chunks, int B, float *__restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double e = 0.0, r = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        e += part[((int64_t)b * chunks + c) * 2];
+        r += part[((int64_t)b * chunks + c) * 2 + 1];
+    }
+    out[b] = r > 0.0 ? (float)sqrt(e / r) : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void cnr_part_kernel(const float *__restrict__ img, const uint8_t *__restrict__ lab,
+                                                       int64_t n, int chunks, double *__restrict__ part) {
     __shared__ double red[5][256];
-    const int b = blockIdx.x;
+    const int b = blockIdx.y, ch = blockIdx.x;
+    const int64_t per = ceil_div(n, (int64_t)chunks);
+    const int64_t p0 = ch * per, p1 = std::min<int64_t>(n, p0 + per);
+    const float *ib = img + (int64_t)b * n;
+    const uint8_t *lb = lab + (int64_t)b * n;
     double v[5] = {0, 0, 0, 0, 0};   // sum_src, n_src, sum_surr, sum_surr^2, n_surr
-    for (int64_t p = threadIdx.x; p < n; p += 256) {
-        const uint8_t l = lab[(int64_t)b * n + p];
-        const double z = img[(int64_t)b * n + p];
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+        const uint8_t l = lb[p];
+        const double z = ib[p];
         if (l == 1) {
             v[0] += z;
             v[1] += 1.0;
@@ -112,11 +147,21 @@ __global__ __launch_bounds__(256) void cnr_kernel(const float *__restrict__ img,
         }
     }
     block_sum<5>(v, red);
-    if (threadIdx.x == 0) {
-        const double ms = v[0] / v[1], mr = v[2] / v[4];
-        const double var = v[3] / v[4] - mr * mr;
-        out[b] = (v[1] > 0 && v[4] > 0 && var > 0) ? (float)((ms - mr) / sqrt(var)) : 0.0f;
-    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) part[((int64_t)b * chunks + ch) * 5 + k] = v[k];
+}
+
+__global__ void cnr_final_kernel(const double *__restrict__ part, int chunks, int B, float *__restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int c = 0; c < chunks; ++c)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v[k] += part[((int64_t)b * chunks + c) * 5 + k];
+    const double ms = v[0] / v[1], mr = v[2] / v[4];
+    const double var = v[3] / v[4] - mr * mr;
+    out[b] = (v[1] > 0 && v[4] > 0 && var > 0) ? (float)((ms - mr) / sqrt(var)) : 0.0f;
 }
 
 dim3 pix_grid(int64_t npx, int B) { return dim3((unsigned)std::min<int64_t>(ceil_div(npx, 256), 1024), (unsigned)B); }
@@ -174,24 +219,33 @@ extern "C" qld_status qld_clean_amplitude(const uint8_t *mask, const double *rat
 extern "C" qld_status qld_judge_nrmse(const float *x, const float *scale, const float *ref, int32_t B, int64_t n,
                                       float *out, qld_hip_stream stream) {
     clear_error();
-    if (!x || !ref || !out || B < 0 || n < 0) {
+    if (!x || !ref || !out || B < 0 || B > 65535 || n < 0) {
         set_error("nrmse: bad arguments");
         return QLD_E_INVAL;
     }
     if (B == 0) return QLD_OK;
-    hipLaunchKernelGGL(nrmse_kernel, dim3(B), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), x, scale, ref, n,
-                       out);
-    return check_hip(hipGetLastError(), "nrmse_kernel launch");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int chunks = judge_chunks(B, n);
+    double *part = static_cast<double *>(stream_workspace(s, sizeof(double) * 2 * (size_t)B * chunks));
+    if (!part) return QLD_E_NOMEM;
+    hipLaunchKernelGGL(nrmse_part_kernel, dim3(chunks, B), dim3(256), 0, s, x, scale, ref, n, chunks, part);
+    hipLaunchKernelGGL(nrmse_final_kernel, dim3((unsigned)ceil_div(B, 64)), dim3(64), 0, s, part, chunks, B, out);
+    return check_hip(hipGetLastError(), "nrmse launch");
 }
 
 extern "C" qld_status qld_judge_cnr(const float *img, const uint8_t *labels, int32_t B, int64_t n, float *out,
                                     qld_hip_stream stream) {
     clear_error();
-    if (!img || !labels || !out || B < 0 || n < 0) {
+    if (!img || !labels || !out || B < 0 || B > 65535 || n < 0) {
         set_error("cnr: bad arguments");
         return QLD_E_INVAL;
     }
     if (B == 0) return QLD_OK;
-    hipLaunchKernelGGL(cnr_kernel, dim3(B), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), img, labels, n, out);
-    return check_hip(hipGetLastError(), "cnr_kernel launch");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int chunks = judge_chunks(B, n);
+    double *part = static_cast<double *>(stream_workspace(s, sizeof(double) * 5 * (size_t)B * chunks));
+    if (!part) return QLD_E_NOMEM;
+    hipLaunchKernelGGL(cnr_part_kernel, dim3(chunks, B), dim3(256), 0, s, img, labels, n, chunks, part);
+    hipLaunchKernelGGL(cnr_final_kernel, dim3((unsigned)ceil_div(B, 64)), dim3(64), 0, s, part, chunks, B, out);
+    return check_hip(hipGetLastError(), "cnr launch");
 }
