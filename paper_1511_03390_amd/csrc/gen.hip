@@ -18,8 +18,11 @@
 //   total = sum w (ascending k); thr[k] = min(floor(cum_k/total * 2^32), 2^32-1), k < hi
 //   X(u) = lo + #{k : thr[k] <= u}
 // A 1024-entry guide table (Chen and Asau, 1974) brackets the answer for each
-// u >> 22; a binary search inside the bracket finishes it (a few steps at
-// most, one or none in the bulk of the distribution).
+// u >> 22, with two 256-entry sub-guides of 2^16-wide buckets over the first
+// and the last 2^24 values of u, where one main bucket would span hundreds of
+// thresholds; a binary search inside the bracket finishes it.  Brackets hold
+// at most a few thresholds except in the outermost sub-buckets (probability
+// 2^-16 each), so the lanes of a wave rarely wait on a long search.
 #include "qld_internal.hpp"
 
 namespace qld {
@@ -27,12 +30,16 @@ namespace {
 
 constexpr int kTableMax = 2048;     // thresholds per rate (lambda up to ~6900)
 constexpr int kGuide = 1024;
-constexpr int kBlock = 512;      // one work-group per CU (the eight tables take 82 KB of LDS)
+constexpr int kSub = 256;           // sub-guide entries over [0, 2^24) and [2^32 - 2^24, 2^32)
+constexpr uint32_t kHighStart = 0xFF000000u;
+constexpr int kBlock = 1024;     // one work-group per CU (the eight tables take 86 KB of LDS)
 constexpr double kRateMax = 6000.0;  // tables of at most kTableMax thresholds
 
 struct Table {
     int32_t lo, n;                  // n thresholds
-    uint16_t guide[kGuide];         // candidate index (from lo) for u >> 22
+    uint16_t guide[kGuide];         // #{thr <= g 2^22}
+    uint16_t lguide[kSub];          // #{thr <= i 2^16}
+    uint16_t hguide[kSub];          // #{thr <= 2^32 - 2^24 + i 2^16}
     uint32_t thr[kTableMax];
 };
 
@@ -95,16 +102,20 @@ __global__ __launch_bounds__(64) void build_tables_kernel(const double *__restri
         T.thr[i] = f >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)f;
     }
     __syncthreads();
-    // guide[g] = #{thr <= g * 2^22}: binary search per entry.
-    for (int g = threadIdx.x; g < kGuide; g += 64) {
-        const uint32_t u = (uint32_t)g << 22;
+    // Guide entries: #{thr <= v} by binary search, one entry per lane.
+    auto count_le = [&](uint32_t v) {
         int32_t a = 0, b = n;
         while (a < b) {
             const int32_t mid = (a + b) >> 1;
-            if (T.thr[mid] <= u) a = mid + 1;
+            if (T.thr[mid] <= v) a = mid + 1;
             else b = mid;
         }
-        T.guide[g] = (uint16_t)a;
+        return (uint16_t)a;
+    };
+    for (int g = threadIdx.x; g < kGuide; g += 64) T.guide[g] = count_le((uint32_t)g << 22);
+    for (int i = threadIdx.x; i < kSub; i += 64) {
+        T.lguide[i] = count_le((uint32_t)i << 16);
+        T.hguide[i] = count_le(kHighStart + ((uint32_t)i << 16));
     }
 }
 
@@ -121,12 +132,22 @@ struct GenArgs {
 
 // X(u) = lo + #{k : thr[k] <= u}.  The count lies between the guide entries of
 // u's bucket and of the next bucket (thresholds are non-decreasing); a binary
-// search between them takes at most ~10 steps even in the tails, where one
-// bucket spans hundreds of thresholds.
+// search between them finishes it.
 __device__ __forceinline__ int32_t invert(const Table *__restrict__ T, uint32_t u) {
-    const uint32_t g = u >> 22;
-    int32_t a = T->guide[g];
-    int32_t b = g + 1 < (uint32_t)kGuide ? (int32_t)T->guide[g + 1] : T->n;
+    int32_t a, b;
+    if (u < (1u << 24)) {
+        const uint32_t i = u >> 16;
+        a = T->lguide[i];
+        b = i + 1 < (uint32_t)kSub ? (int32_t)T->lguide[i + 1] : (int32_t)T->guide[4];
+    } else if (u >= kHighStart) {
+        const uint32_t i = (u - kHighStart) >> 16;
+        a = T->hguide[i];
+        b = i + 1 < (uint32_t)kSub ? (int32_t)T->hguide[i + 1] : T->n;
+    } else {
+        const uint32_t g = u >> 22;
+        a = T->guide[g];
+        b = T->guide[g + 1];                        // g + 1 <= 1020 < kGuide here
+    }
     while (a < b) {
         const int32_t mid = (a + b) >> 1;
         if (T->thr[mid] <= u) a = mid + 1;
