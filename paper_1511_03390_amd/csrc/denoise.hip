@@ -314,70 +314,85 @@ __global__ __launch_bounds__(256) void small_grad_kernel(const XT *__restrict__ 
     }
 }
 
-// 32x32 weight gradient on the matrix cores: D[co][ci] += sum_px dz[px][co] a[px + tap][ci].
-// A (16 co x 32 px) and B (32 px x 16 ci) gathered per lane (8 pixels of one
-// channel).  Wave w of a work-group owns taps w, w+4, w+8.  Segments of 32
-// pixels of one row are dealt to work-groups; partial[block][tap][ci][co].
+// 32x32 weight gradient on the matrix cores: D[tap][ci][co] = sum_px a[px + tap][ci] dz[px][co]
+// (v_mfma_f32_16x16x32_bf16: M = co, N = ci, K = 32 pixels).  An MFMA operand
+// lane holds 8 consecutive pixels of one channel, so a work-group stages each
+// 64-pixel row segment transposed in LDS: dT[co][px] from dz, and aT[r][ci][px]
+// from the three input rows around it (pixels x0-1 .. x0+64, zero outside the
+// image).  A lane then reads its 8 pixels with one 16-byte LDS read; the taps
+// at dx = -1 / +1 combine two aligned reads with a 16-bit funnel shift.  Wave w
+// owns the 16x16 block (co block w & 1, ci block w >> 1) for all 9 taps.
+// Segments are dealt round-robin to work-groups; each writes one row of
+// partial sums part[block][tap][ci][co], summed later in a fixed order.
+constexpr int kSegPx = 64;
+constexpr int kAStride = 88;   // bf16 per aT row: pixels x0-8 .. x0+71 (+8 pad); 176 B, 16-B multiple
+constexpr int kDStride = 72;   // bf16 per dT row: 64 pixels (+8 pad); 144 B
+
+typedef uint32_t u32x4w __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a, const __bf16 *__restrict__ dz, int B,
                                                    int H, int W, float *__restrict__ part) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, m = lane & 15, kb = lane >> 4;
-    const int segs_x = (W + 31) / 32;
+    __shared__ __align__(16) __bf16 aT[3][32][kAStride];
+    __shared__ __align__(16) __bf16 dT[32][kDStride];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
+    const int cb = wave & 1, cib = wave >> 1;
+    const int segs_x = (W + kSegPx - 1) / kSegPx;
     const int64_t n_seg = (int64_t)B * H * segs_x;
-    f32x4 acc[3][2][2];
+    f32x4 acc[9];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j][0] = acc[i][j][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
-        const int sx = (int)(s % segs_x);
-        const int64_t row = s / segs_x;             // b * H + y
+    for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = zero8();
+    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+        const int x0 = (int)(sg % segs_x) * kSegPx;
+        const int64_t row = sg / segs_x;            // b * H + y
         const int y = (int)(row % H);
-        const int px0 = sx * 32 + kb * 8;
-        bf16x8 A[2];
+        __syncthreads();                            // the previous segment's readers are done
+        {   // dz: pixel x0 + (t & 63), channels 8 (t >> 6) .. +8
+            const int px = t & 63, cg = t >> 6, x = x0 + px;
+            const bf16x8 v = x < W ? *reinterpret_cast<const bf16x8 *>(dz + (row * W + x) * 32 + cg * 8) : zero;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+            for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = v[i];
+        }
+        // a: rows y-1, y, y+1; pixels x0-1 .. x0+64 at aT columns 7 .. 72.
+        for (int item = t; item < 3 * 4 * 66; item += 256) {
+            const int px = item % 66, q = item / 66, cg = q & 3, r = q >> 2;
+            const int x = x0 - 1 + px, iy = y + r - 1;
+            const bool ok = x >= 0 && x < W && iy >= 0 && iy < H;
+            const bf16x8 v = ok ? *reinterpret_cast<const bf16x8 *>(a + ((row - y + iy) * W + x) * 32 + cg * 8) : zero;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int px = px0 + e;
-                A[cb][e] = px < W ? dz[(row * W + px) * 32 + 16 * cb + m] : (__bf16)0.0f;
-            }
+            for (int i = 0; i < 8; ++i) aT[r][cg * 8 + i][px + 7] = v[i];
+        }
+        __syncthreads();
 #pragma unroll
-        for (int ti = 0; ti < 3; ++ti) {
-            const int t = wave + 4 * ti;
-            if (t >= 9) break;
-            const int iy = y + tap_dy(t), dx = tap_dx(t);
-            const bool row_ok = iy >= 0 && iy < H;
-            const int64_t irow = row - y + iy;
-            bf16x8 Bv[2];
+        for (int kk = 0; kk < 2; ++kk) {
+            const int pxb = kk * 32 + kb * 8;       // this lane's 8 pixels: x0 + pxb .. +8
+            const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&dT[cb * 16 + m][pxb]);
 #pragma unroll
-            for (int cib = 0; cib < 2; ++cib)
+            for (int r = 0; r < 3; ++r) {
+                const __bf16 *rp = &aT[r][cib * 16 + m][0];
+                const u32x4w pv = *reinterpret_cast<const u32x4w *>(rp + pxb);        // pixels pxb-8 ..
+                const u32x4w c = *reinterpret_cast<const u32x4w *>(rp + pxb + 8);     // pixels pxb ..
+                const u32x4w nx = *reinterpret_cast<const u32x4w *>(rp + pxb + 16);   // pixels pxb+8 ..
+                u32x4w lft, rgt;                                                      // shifted by -1 / +1
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int px = px0 + e, ix = px + dx;
-                    Bv[cib][e] = (row_ok && px < W && ix >= 0 && ix < W) ? a[(irow * W + ix) * 32 + 16 * cib + m]
-                                                                          : (__bf16)0.0f;
+                for (int k = 0; k < 4; ++k) {
+                    lft[k] = __builtin_amdgcn_alignbit(c[k], k ? c[k - 1] : pv[3], 16);
+                    rgt[k] = __builtin_amdgcn_alignbit(k < 3 ? c[k + 1] : nx[0], c[k], 16);
                 }
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                for (int cib = 0; cib < 2; ++cib) acc[ti][cb][cib] = mfma16(A[cb], Bv[cib], acc[ti][cb][cib]);
+                acc[3 * r + 0] = mfma16(A, __builtin_bit_cast(bf16x8, lft), acc[3 * r + 0]);
+                acc[3 * r + 1] = mfma16(A, __builtin_bit_cast(bf16x8, c), acc[3 * r + 1]);
+                acc[3 * r + 2] = mfma16(A, __builtin_bit_cast(bf16x8, rgt), acc[3 * r + 2]);
+            }
         }
     }
     float *pb = part + (int64_t)blockIdx.x * 9 * 1024;
 #pragma unroll
-    for (int ti = 0; ti < 3; ++ti) {
-        const int t = wave + 4 * ti;
-        if (t >= 9) break;
+    for (int k = 0; k < 9; ++k)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-            for (int cib = 0; cib < 2; ++cib)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int co = 16 * cb + 4 * kb + i, ci = 16 * cib + m;
-                    pb[(t * 32 + ci) * 32 + co] = acc[ti][cb][cib][i];
-                }
-    }
+        for (int i = 0; i < 4; ++i) {
+            const int co = 16 * cb + 4 * kb + i, ci = 16 * cib + m;
+            pb[(k * 32 + ci) * 32 + co] = acc[k][i];
+        }
 }
 
 // Column sums of part[R][n] in a fixed order.  Work-group (cx, slab): 64
@@ -523,7 +538,7 @@ struct qld_denoiser {
 namespace qld {
 namespace {
 
-constexpr int kGradBlocks = 256;     // work-groups of the MFMA weight-gradient reduction
+constexpr int kGradBlocks = 512;     // work-groups of the MFMA weight-gradient reduction
 constexpr int kSmallBlocks = 1024;   // work-groups of the VALU gradient reductions
 constexpr int kLossBlocks = 256;
 
