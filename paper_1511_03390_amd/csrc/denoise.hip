@@ -321,12 +321,15 @@ __global__ __launch_bounds__(256) void small_grad_kernel(const XT *__restrict__ 
 // from the three input rows around it (pixels x0-1 .. x0+64, zero outside the
 // image).  A lane then reads its 8 pixels with one 16-byte LDS read; the taps
 // at dx = -1 / +1 combine two aligned reads with a 16-bit funnel shift.  Wave w
-// owns the 16x16 block (co block w & 1, ci block w >> 1) for all 9 taps.
-// Segments are dealt round-robin to work-groups; each writes one row of
-// partial sums part[block][tap][ci][co], summed later in a fixed order.
+// owns the 16x16 block (co block w & 1, ci block w >> 1) for all 9 taps; waves
+// 0 and 1 also sum their dz operands for the bias gradient.  Segments are
+// dealt round-robin to work-groups; each writes one row of partial sums
+// part[block][tap][ci][co] followed by the 32 bias sums (the canonical order
+// of W and b), summed later in a fixed order.
 constexpr int kSegPx = 64;
 constexpr int kAStride = 88;   // bf16 per aT row: pixels x0-8 .. x0+71 (+8 pad); 176 B, 16-B multiple
 constexpr int kDStride = 72;   // bf16 per dT row: 64 pixels (+8 pad); 144 B
+constexpr int kW32Row = 9 * 1024 + 32;   // partial row: weights then bias
 
 typedef uint32_t u32x4w __attribute__((ext_vector_type(4)));
 
@@ -341,6 +344,7 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
     f32x4 acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
     const bf16x8 zero = zero8();
     for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
         const int x0 = (int)(sg % segs_x) * kSegPx;
@@ -367,6 +371,12 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
         for (int kk = 0; kk < 2; ++kk) {
             const int pxb = kk * 32 + kb * 8;       // this lane's 8 pixels: x0 + pxb .. +8
             const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&dT[cb * 16 + m][pxb]);
+            if (cib == 0) {
+                float sb = 0.f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sb += (float)A[e];
+                bacc += sb;
+            }
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const __bf16 *rp = &aT[r][cib * 16 + m][0];
@@ -385,7 +395,7 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
             }
         }
     }
-    float *pb = part + (int64_t)blockIdx.x * 9 * 1024;
+    float *pb = part + (int64_t)blockIdx.x * kW32Row;
 #pragma unroll
     for (int k = 0; k < 9; ++k)
 #pragma unroll
@@ -393,6 +403,73 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
             const int co = 16 * cb + 4 * kb + i, ci = 16 * cib + m;
             pb[(k * 32 + ci) * 32 + co] = acc[k][i];
         }
+    if (cib == 0) {
+        bacc += __shfl_xor(bacc, 16);
+        bacc += __shfl_xor(bacc, 32);
+        if (kb == 0) pb[9 * 1024 + cb * 16 + m] = bacc;
+    }
+}
+
+// Output layer (32 -> 1) weight and bias gradients on the VALU:
+// dW4[tap][ci] = sum_px a3[px + tap][ci] dy[px], db4 = sum_px dy[px].  Staged
+// like dw32_kernel (a3 rows transposed in LDS, dy of the segment in LDS);
+// thread (ci, r, half) slides along its 32 pixels of row r and accumulates
+// the three taps of that row.  Partial rows part[2 block + half][289].
+constexpr int kOutRow = 289;
+
+__global__ __launch_bounds__(256) void dw_out_kernel(const __bf16 *__restrict__ a, const float *__restrict__ dy, int B,
+                                                     int H, int W, float *__restrict__ part) {
+    __shared__ __align__(16) __bf16 aT[3][32][kAStride];
+    __shared__ float dyS[kSegPx];
+    const int t = threadIdx.x;
+    const int ci = t & 31, q = t >> 5, r = q % 3, half = q / 3;   // q < 6 for t < 192
+    const int segs_x = (W + kSegPx - 1) / kSegPx;
+    const int64_t n_seg = (int64_t)B * H * segs_x;
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, bacc = 0.f;
+    const bf16x8 zero = zero8();
+    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+        const int x0 = (int)(sg % segs_x) * kSegPx;
+        const int64_t row = sg / segs_x;
+        const int y = (int)(row % H);
+        __syncthreads();
+        if (t < kSegPx) dyS[t] = x0 + t < W ? dy[row * W + x0 + t] : 0.f;
+        for (int item = t; item < 3 * 4 * 66; item += 256) {
+            const int px = item % 66, qq = item / 66, cg = qq & 3, rr = qq >> 2;
+            const int x = x0 - 1 + px, iy = y + rr - 1;
+            const bool ok = x >= 0 && x < W && iy >= 0 && iy < H;
+            const bf16x8 v = ok ? *reinterpret_cast<const bf16x8 *>(a + ((row - y + iy) * W + x) * 32 + cg * 8) : zero;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) aT[rr][cg * 8 + i][px + 7] = v[i];
+        }
+        __syncthreads();
+        if (t < 192) {
+            const __bf16 *rp = &aT[r][ci][0];
+            const int p0 = half * 32;
+            float vm = (float)rp[p0 + 7], v0 = (float)rp[p0 + 8];
+#pragma unroll 8
+            for (int px = p0; px < p0 + 32; ++px) {
+                const float vp = (float)rp[px + 9], g = dyS[px];
+                acc0 = fmaf(vm, g, acc0);
+                acc1 = fmaf(v0, g, acc1);
+                acc2 = fmaf(vp, g, acc2);
+                vm = v0;
+                v0 = vp;
+            }
+        } else if (t == 192) {
+            float sb = 0.f;
+            for (int px = 0; px < kSegPx; ++px) sb += dyS[px];
+            bacc += sb;
+        }
+    }
+    if (t < 192) {
+        float *pb = part + ((int64_t)blockIdx.x * 2 + half) * kOutRow;
+        pb[(3 * r + 0) * 32 + ci] = acc0;
+        pb[(3 * r + 1) * 32 + ci] = acc1;
+        pb[(3 * r + 2) * 32 + ci] = acc2;
+    } else if (t == 192) {
+        part[(int64_t)blockIdx.x * 2 * kOutRow + 288] = bacc;
+        part[((int64_t)blockIdx.x * 2 + 1) * kOutRow + 288] = 0.f;
+    }
 }
 
 // Column sums of part[R][n] in a fixed order.  Work-group (cx, slab): 64
@@ -593,10 +670,20 @@ qld_status small_grad(qld_denoiser *d, const XT *X, const DT *D, int B, int64_t 
     return reduce_rows(d, d->part, blocks, NT * CI * CO, d->grads + off, s);
 }
 
+// Weights and bias of a 32 -> 32 layer (the bias follows the weights in the canonical order).
 qld_status dw32(qld_denoiser *d, const __bf16 *a, const __bf16 *dz, int B, int64_t off, hipStream_t s) {
     hipLaunchKernelGGL(dw32_kernel, dim3(kGradBlocks), dim3(256), 0, s, a, dz, B, d->H, d->W, d->part);
     QLD_TRY(check_hip(hipGetLastError(), "dw32 launch"));
-    return reduce_rows(d, d->part, kGradBlocks, 9 * 1024, d->grads + off, s);
+    return reduce_rows(d, d->part, kGradBlocks, kW32Row, d->grads + off, s);
+}
+
+// Weights and bias of the output layer.
+qld_status dw_out(qld_denoiser *d, int B, hipStream_t s) {
+    const int64_t n_seg = (int64_t)B * d->H * ceil_div(d->W, kSegPx);
+    const int blocks = (int)std::min<int64_t>(kSmallBlocks, n_seg);
+    hipLaunchKernelGGL(dw_out_kernel, dim3(blocks), dim3(256), 0, s, d->a3, d->dy, B, d->H, d->W, d->part);
+    QLD_TRY(check_hip(hipGetLastError(), "dw_out launch"));
+    return reduce_rows(d, d->part, 2 * blocks, kOutRow, d->grads + OFF_W4, s);
 }
 
 }  // namespace
@@ -616,7 +703,7 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     d->W = W;
     d->max_batch = max_batch;
     const size_t npx = (size_t)max_batch * H * W;
-    d->part_floats = std::max<int64_t>((int64_t)kGradBlocks * 9 * 1024,
+    d->part_floats = std::max<int64_t>((int64_t)kGradBlocks * kW32Row,
                                        ((int64_t)max_batch * 64 + 4096 + max_batch) * 32);   // >= B * pool_chunks(B) * 32
     qld_status st = QLD_OK;
     if (st == QLD_OK) st = dalloc(d, &d->params, N_ALL);
@@ -790,18 +877,15 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, s, d->y, t, d->dy, npx, d->lpart);
     hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, d->lpart, kLossBlocks, npx, d->loss);
     // Output layer: dW4, db4, and dz3 = bf16(d a3 * (a3 > 0)).
-    QLD_TRY(small_grad<__bf16, float, 32, 1, 9>(d, d->a3, d->dy, B, OFF_W4, s));
-    QLD_TRY(small_grad<__bf16, float, 1, 1, 1>(d, nullptr, d->dy, B, OFF_B4, s));
+    QLD_TRY(dw_out(d, B, s));
     hipLaunchKernelGGL(out_back_kernel, dim3((unsigned)ceil_div(npx, 256)), dim3(256), 0, s, d->dy, d->w4, d->a3,
                        d->dzA, B, H, W);
     const int g = conv_grid(B, H, W);
     // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
-    QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));
-    QLD_TRY(small_grad<__bf16, __bf16, 1, 32, 1>(d, nullptr, d->dzA, B, OFF_B3, s));
+    QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));   // and b3
     hipLaunchKernelGGL((conv32_kernel<1>), dim3(g), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W);
     // Layer 2: dW2 from (a1, dz2); dz1 = bf16(conv^T(dz2, W2) * (a1 > 0)).
-    QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));
-    QLD_TRY(small_grad<__bf16, __bf16, 1, 32, 1>(d, nullptr, d->dzB, B, OFF_B2, s));
+    QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));   // and b2
     hipLaunchKernelGGL((conv32_kernel<1>), dim3(g), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W);
     // Layer 1: dW1 from (x0, dz1).
     QLD_TRY(small_grad<__bf16, __bf16, 2, 32, 9>(d, d->x0, d->dzC, B, OFF_W1, s));
