@@ -55,9 +55,10 @@ __device__ __forceinline__ bf16x8 zero8() {
 //   wNf [9][32 co][32 ci]   forward B operand (K = ci contiguous)
 //   wNb [9][32 ci][32 co]   input-gradient B operand (K = co contiguous)
 //   w4  [9][32]
+//   w4f [9][16][32]  output-layer B operand: row 0 = w4[tap], rows 1..15 zero
 // ---------------------------------------------------------------------------
 __global__ void pack_kernel(const float *__restrict__ p, __bf16 *w1f, __bf16 *w2f, __bf16 *w2b, __bf16 *w3f,
-                            __bf16 *w3b, __bf16 *w4) {
+                            __bf16 *w3b, __bf16 *w4, __bf16 *w4f) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 1024) {
         const int co = i / 32, k = i % 32;
@@ -74,6 +75,10 @@ __global__ void pack_kernel(const float *__restrict__ p, __bf16 *w1f, __bf16 *w2
         w3b[i] = (__bf16)p[OFF_W3 + (t * 32 + a) * 32 + b];
     }
     if (i < 288) w4[i] = (__bf16)p[OFF_W4 + i];
+    if (i < 9 * 512) {
+        const int t = i / 512, co = (i / 32) % 16, ci = i % 32;
+        w4f[i] = (__bf16)(co == 0 ? p[OFF_W4 + t * 32 + ci] : 0.0f);
+    }
 }
 
 __global__ void to_bf16_kernel(const float *__restrict__ x, __bf16 *__restrict__ y, int64_t n) {
@@ -93,53 +98,85 @@ __device__ __forceinline__ bool tile_of(int H, int W, int &b, int &y, int &x0) {
 }
 
 // ---------------------------------------------------------------------------
-// 32 -> 32 convolution on the matrix cores.
+// 3x3 convolutions with 32 input channels on the matrix cores (implicit GEMM).
+// A work-group computes 4 output rows x 64 pixels: it stages its input tile
+// (rows y0-1 .. y0+4, pixels x0-1 .. x0+64, 32 channels, zero outside the
+// image; 25 KB) in LDS once, each lane keeps its B-operand fragments of all 9
+// taps in registers, and wave w computes output row y0 + w: per tap and group
+// of 16 pixels one 16-byte LDS read (a lane's 8 input channels of one pixel;
+// the 64 lanes read 1 KiB contiguous) and one MFMA per 16 output channels.
 // MODE 0 (forward):        out = bf16(relu(sum_tap in[p + tap] W[tap] + bias))
 // MODE 1 (input gradient): out = bf16((sum_tap in[p - tap] W^T[tap]) * (act[p] > 0))
+// MODE 2 (output layer):   y   = sum_tap in[p + tap] . w4[tap] + b4 (fp32; the
+//                          weights form one 16-column block with column 0 used)
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(256) void conv32_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
-                                                     const float *__restrict__ bias, const __bf16 *__restrict__ act,
-                                                     __bf16 *__restrict__ out, int H, int W) {
-    int b, y, x0;
-    if (!tile_of(H, W, b, y, x0)) return;
-    const int lane = threadIdx.x & 63, m = lane & 15, kb = lane >> 4;
-    f32x4 acc[4][2];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) acc[g][0] = acc[g][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+__global__ __launch_bounds__(256) void conv_tile_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
+                                                        const float *__restrict__ bias, const __bf16 *__restrict__ act,
+                                                        void *__restrict__ out, int H, int W) {
+    constexpr int NCB = MODE == 2 ? 1 : 2;          // 16-channel output blocks
+    __shared__ __align__(16) __bf16 tile[kRows + 2][kCols + 2][32];
+    const int tx = (W + kCols - 1) / kCols, ty = (H + kRows - 1) / kRows;
+    int id = blockIdx.x;
+    const int x0 = (id % tx) * kCols;
+    id /= tx;
+    const int y0 = (id % ty) * kRows;
+    const int b = id / ty;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
     const int64_t img = (int64_t)b * H;
-#pragma unroll 1
-    for (int t = 0; t < 9; ++t) {
-        const int sy = MODE == 0 ? tap_dy(t) : -tap_dy(t);
-        const int sx = MODE == 0 ? tap_dx(t) : -tap_dx(t);
-        const bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(wt + ((t * 32 + m) * 32 + kb * 8));
-        const bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(wt + ((t * 32 + 16 + m) * 32 + kb * 8));
-        const int iy = y + sy;
-        const bool row_ok = iy >= 0 && iy < H;
+    bf16x8 w[9][NCB];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int ix = x0 + 16 * g + m + sx;
-            bf16x8 a = zero8();
-            if (row_ok && ix >= 0 && ix < W) a = *reinterpret_cast<const bf16x8 *>(in + ((img + iy) * W + ix) * 32 + kb * 8);
-            acc[g][0] = mfma16(a, w0, acc[g][0]);
-            acc[g][1] = mfma16(a, w1, acc[g][1]);
-        }
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+            w[k][cb] = *reinterpret_cast<const bf16x8 *>(wt + ((k * 16 * NCB + cb * 16 + m) * 32 + kb * 8));
+    for (int item = t; item < (kRows + 2) * (kCols + 2) * 4; item += 256) {
+        const int cg = item & 3, q = item >> 2, px = q % (kCols + 2), r = q / (kCols + 2);
+        const int iy = y0 - 1 + r, ix = x0 - 1 + px;
+        bf16x8 v = zero8();
+        if (iy >= 0 && iy < H && ix >= 0 && ix < W)
+            v = *reinterpret_cast<const bf16x8 *>(in + ((img + iy) * W + ix) * 32 + cg * 8);
+        *reinterpret_cast<bf16x8 *>(&tile[r][px][cg * 8]) = v;
     }
+    __syncthreads();
+    f32x4 acc[4][NCB];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < NCB; ++cb) acc[g][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int px = x0 + 16 * g + 4 * kb + i;
-                if (px >= W) continue;
-                const int co = 16 * cb + m;
-                const int64_t idx = ((img + y) * W + px) * 32 + co;
-                float v = acc[g][cb][i];
-                if (MODE == 0) v = fmaxf(v + bias[co], 0.0f);
-                else v = (float)act[idx] > 0.0f ? v : 0.0f;
-                out[idx] = (__bf16)v;
+    for (int k = 0; k < 9; ++k) {
+        const int sy = MODE == 1 ? -tap_dy(k) : tap_dy(k);
+        const int sx = MODE == 1 ? -tap_dx(k) : tap_dx(k);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&tile[wave + 1 + sy][16 * g + m + 1 + sx][kb * 8]);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[g][cb] = mfma16(a, w[k][cb], acc[g][cb]);
+        }
+    }
+    const int y = y0 + wave;
+    if (y >= H) return;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int px = x0 + 16 * g + 4 * kb + i;
+            if (px >= W) continue;
+            if constexpr (MODE == 2) {
+                if (m == 0) static_cast<float *>(out)[(img + y) * W + px] = acc[g][0][i] + bias[0];
+            } else {
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const int co = 16 * cb + m;
+                    const int64_t idx = ((img + y) * W + px) * 32 + co;
+                    float v = acc[g][cb][i];
+                    if (MODE == 0) v = fmaxf(v + bias[co], 0.0f);
+                    else v = (float)act[idx] > 0.0f ? v : 0.0f;
+                    static_cast<__bf16 *>(out)[idx] = (__bf16)v;
+                }
             }
+        }
 }
 
 // 2 -> 32 input layer: the 18 (tap, channel) products form one K = 32 MFMA.
@@ -183,26 +220,6 @@ __global__ __launch_bounds__(256) void conv1_kernel(const __bf16 *__restrict__ x
                 const int co = 16 * cb + m;
                 out[((img + y) * W + px) * 32 + co] = (__bf16)fmaxf(acc[g][cb][i] + bias[co], 0.0f);
             }
-}
-
-// 32 -> 1 output layer (VALU): y[p] = b4 + sum_tap sum_c a3[p + tap][c] w4[tap][c].
-__global__ __launch_bounds__(256) void conv_out_kernel(const __bf16 *__restrict__ a3, const __bf16 *__restrict__ w4,
-                                                       const float *__restrict__ b4, float *__restrict__ yout, int B,
-                                                       int H, int W) {
-    const int64_t n = (int64_t)B * H * W;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int x = (int)(p % W), y = (int)((p / W) % H);
-    const int64_t b = p / ((int64_t)H * W);
-    float acc = b4[0];
-    for (int t = 0; t < 9; ++t) {
-        const int iy = y + tap_dy(t), ix = x + tap_dx(t);
-        if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
-        const __bf16 *src = a3 + ((b * H + iy) * W + ix) * 32;
-#pragma unroll
-        for (int c = 0; c < 32; ++c) acc = fmaf((float)src[c], (float)w4[t * 32 + c], acc);
-    }
-    yout[p] = acc;
 }
 
 // dy = 2 (y - t) / N; per-block partial sums of (y - t)^2.
@@ -603,7 +620,7 @@ struct qld_denoiser {
     int H, W, max_batch;
     int64_t step;
     float *params, *grads, *m, *v;
-    __bf16 *w1f, *w2f, *w2b, *w3f, *w3b, *w4;
+    __bf16 *w1f, *w2f, *w2b, *w3f, *w3b, *w4, *w4f;
     __bf16 *x0, *a1, *a2, *a3, *dzA, *dzB, *dzC;   // dz3, dz2, dz1
     float *y, *dy, *pool, *gate, *part, *part2, *loss;
     double *lpart;
@@ -638,7 +655,7 @@ int conv_grid(int B, int H, int W) {
 
 qld_status pack(qld_denoiser *d, hipStream_t s) {
     hipLaunchKernelGGL(pack_kernel, dim3(36), dim3(256), 0, s, d->params, d->w1f, d->w2f, d->w2b, d->w3f, d->w3b,
-                       d->w4);
+                       d->w4, d->w4f);
     return check_hip(hipGetLastError(), "pack_kernel launch");
 }
 
@@ -716,6 +733,7 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     if (st == QLD_OK) st = dalloc(d, &d->w3f, 9 * 1024);
     if (st == QLD_OK) st = dalloc(d, &d->w3b, 9 * 1024);
     if (st == QLD_OK) st = dalloc(d, &d->w4, 288);
+    if (st == QLD_OK) st = dalloc(d, &d->w4f, 9 * 512);
     if (st == QLD_OK) st = dalloc(d, &d->x0, npx * 2);
     if (st == QLD_OK) st = dalloc(d, &d->a1, npx * 32);
     if (st == QLD_OK) st = dalloc(d, &d->a2, npx * 32);
@@ -845,12 +863,12 @@ extern "C" qld_status qld_denoiser_forward(qld_denoiser *d, const float *x, int3
     take_kernel_timer(&ev0, &ev1);
     if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
     hipLaunchKernelGGL(conv1_kernel, dim3(g), dim3(256), 0, s, d->x0, d->w1f, d->params + OFF_B1, d->a1, H, W);
-    hipLaunchKernelGGL((conv32_kernel<0>), dim3(g), dim3(256), 0, s, d->a1, d->w2f, d->params + OFF_B2, nullptr, d->a2,
+    hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(g), dim3(256), 0, s, d->a1, d->w2f, d->params + OFF_B2, nullptr, d->a2,
                        H, W);
-    hipLaunchKernelGGL((conv32_kernel<0>), dim3(g), dim3(256), 0, s, d->a2, d->w3f, d->params + OFF_B3, nullptr, d->a3,
+    hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(g), dim3(256), 0, s, d->a2, d->w3f, d->params + OFF_B3, nullptr, d->a3,
                        H, W);
-    hipLaunchKernelGGL(conv_out_kernel, dim3((unsigned)ceil_div(npx, 256)), dim3(256), 0, s, d->a3, d->w4,
-                       d->params + OFF_B4, d->y, B, H, W);
+    hipLaunchKernelGGL((conv_tile_kernel<2>), dim3(g), dim3(256), 0, s, d->a3, d->w4f, d->params + OFF_B4, nullptr,
+                       d->y, H, W);
     if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
     const int chunks = pool_chunks(B);
     hipLaunchKernelGGL(pool_kernel, dim3(chunks, B), dim3(256), 0, s, d->a3, (int64_t)H * W, chunks, d->part);
@@ -883,10 +901,10 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     const int g = conv_grid(B, H, W);
     // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
     QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));   // and b3
-    hipLaunchKernelGGL((conv32_kernel<1>), dim3(g), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W);
+    hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(g), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W);
     // Layer 2: dW2 from (a1, dz2); dz1 = bf16(conv^T(dz2, W2) * (a1 > 0)).
     QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));   // and b2
-    hipLaunchKernelGGL((conv32_kernel<1>), dim3(g), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W);
+    hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(g), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W);
     // Layer 1: dW1 from (x0, dz1).
     QLD_TRY(small_grad<__bf16, __bf16, 2, 32, 9>(d, d->x0, d->dzC, B, OFF_W1, s));
     QLD_TRY(small_grad<__bf16, __bf16, 1, 32, 1>(d, nullptr, d->dzC, B, OFF_B1, s));
