@@ -6,16 +6,18 @@
 //
 // Layout: activations NHWC bfloat16 [B][H][W][32]; weights fp32 master copy in
 // a canonical order, packed to bfloat16 operand layouts after every update.
-// The 32-channel layers are implicit GEMMs on the matrix cores:
-// v_mfma_f32_16x16x32_bf16 with A = 16 pixels x 32 input channels (one 16-byte
-// load per lane from NHWC), B = 32 input x 16 output channels, fp32
-// accumulation; one MFMA per tap and 16x16 output block.  The same kernel,
-// with the tap offsets negated and the weights transposed, computes the
-// gradient with respect to the input.  Weight gradients are MFMA reductions
-// over pixels (K = 32 pixels per step) into per-work-group partials that a
+// Convolutions are implicit GEMMs on the matrix cores
+// (v_mfma_f32_16x16x32_bf16, fp32 accumulation): a work-group stages its
+// input tile in LDS once and each lane keeps its weight fragments of all nine
+// taps in registers.  The same kernel, with the tap offsets negated and the
+// weights transposed, computes the gradient with respect to the input; the
+// 1-channel output layer is the same kernel with one zero-padded 16-column
+// weight block.  Weight gradients are MFMA reductions over pixels (K = 32
+// pixels per step; operands staged transposed in LDS, the bias gradients
+// summed from the same staged tiles) into per-work-group partials that a
 // second kernel sums in a fixed order, so training is deterministic.  The
 // 2-channel input layer packs its 18 (tap, channel) products into one K = 32
-// MFMA; the 1-channel output layer and the small reductions use the VALU.
+// MFMA; the output layer's weight gradient and the pooling use the VALU.
 #include <cstring>
 #include <new>
 #include <vector>
@@ -269,68 +271,6 @@ __global__ __launch_bounds__(256) void out_back_kernel(const float *__restrict__
     for (int c = 0; c < 32; ++c) dp[c] = (__bf16)((float)ap[c] > 0.f ? acc[c] : 0.f);
 }
 
-// Small weight / bias gradients on the VALU.  Output o = (tap, ci, co) over
-// NT taps: sum over pixels of X[p + tap][ci] * D[p][co] (X == NULL: X = 1, a
-// bias gradient).  A work-group stages a 128-pixel row segment of D and the
-// three rows of X around it in LDS, then each thread accumulates its outputs
-// from LDS; segments are dealt round-robin to work-groups, each of which
-// writes one row of partial sums.
-constexpr int kSeg = 128;
-
-template <typename XT, typename DT, int CI, int CO, int NT>
-__global__ __launch_bounds__(256) void small_grad_kernel(const XT *__restrict__ X, const DT *__restrict__ D, int B,
-                                                         int H, int W, float *__restrict__ part) {
-    constexpr int NOUT = NT * CI * CO;
-    constexpr int PER = (NOUT + 255) / 256;
-    __shared__ float xs[3][kSeg + 2][CI];
-    __shared__ float ds[kSeg][CO];
-    float acc[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) acc[j] = 0.f;
-    const int segs_x = (W + kSeg - 1) / kSeg;
-    const int64_t n_seg = (int64_t)B * H * segs_x;
-    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
-        const int x0 = (int)(sg % segs_x) * kSeg;
-        const int64_t row = sg / segs_x;           // b * H + y
-        const int y = (int)(row % H);
-        __syncthreads();                           // the previous segment's readers are done
-        for (int i = threadIdx.x; i < kSeg * CO; i += 256) {
-            const int px = i / CO, c = i % CO, x = x0 + px;
-            ds[px][c] = x < W ? (float)D[(row * W + x) * CO + c] : 0.f;
-        }
-        if (X) {
-            for (int i = threadIdx.x; i < 3 * (kSeg + 2) * CI; i += 256) {
-                const int r = i / ((kSeg + 2) * CI), rem = i % ((kSeg + 2) * CI);
-                const int px = rem / CI, c = rem % CI;
-                const int iy = y + r - 1, ix = x0 + px - 1;
-                xs[r][px][c] = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? (float)X[((row - y + iy) * W + ix) * CI + c]
-                                                                         : 0.f;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int o = threadIdx.x + 256 * j;
-            if (o < NOUT) {
-                const int co = o % CO, ci = (o / CO) % CI, t = o / (CO * CI);
-                const int r = NT == 9 ? t / 3 : 1, dx = NT == 9 ? t % 3 : 1;
-                float a = acc[j];
-                if (X) {
-                    for (int px = 0; px < kSeg; ++px) a = fmaf(xs[r][px + dx][ci], ds[px][co], a);
-                } else {
-                    for (int px = 0; px < kSeg; ++px) a += ds[px][co];
-                }
-                acc[j] = a;
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int o = threadIdx.x + 256 * j;
-        if (o < NOUT) part[(int64_t)blockIdx.x * NOUT + o] = acc[j];
-    }
-}
-
 // 32x32 weight gradient on the matrix cores: D[tap][ci][co] = sum_px a[px + tap][ci] dz[px][co]
 // (v_mfma_f32_16x16x32_bf16: M = co, N = ci, K = 32 pixels).  An MFMA operand
 // lane holds 8 consecutive pixels of one channel, so a work-group stages each
@@ -424,6 +364,89 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
         bacc += __shfl_xor(bacc, 16);
         bacc += __shfl_xor(bacc, 32);
         if (kb == 0) pb[9 * 1024 + cb * 16 + m] = bacc;
+    }
+}
+
+// Input layer (2 -> 32) weight and bias gradients on the matrix cores:
+// dW1[tap][ci][co] = sum_px x0[px + tap][ci] dz1[px][co] with M = co, N = the
+// 18 (tap, ci) pairs in two 16-column blocks, K = 32 pixels; db1[co] = sum_px
+// dz1[px][co].  Staged like dw32_kernel: dz1 transposed dT[co][px] and the
+// three input rows transposed xT[r][ci][px].  Wave w: co block w & 1, column
+// block w >> 1; each lane's column (tap, ci) picks the shifted pixel window of
+// its tap.  Partial rows part[block][608]: W1 then b1 (the canonical order).
+constexpr int kW1Row = 576 + 32;
+
+__global__ __launch_bounds__(256) void dw1_kernel(const __bf16 *__restrict__ x, const __bf16 *__restrict__ dz, int B,
+                                                  int H, int W, float *__restrict__ part) {
+    __shared__ __align__(16) __bf16 xT[3][2][kAStride];
+    __shared__ __align__(16) __bf16 dT[32][kDStride];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
+    const int cb = wave & 1, nb = wave >> 1;
+    const int n = nb * 16 + m;                       // column: tap n / 2, input channel n % 2
+    const bool col_ok = n < 18;
+    const int tap = col_ok ? n >> 1 : 0, ch = n & 1;
+    const int r = tap / 3, dx = tap % 3 - 1;
+    const int segs_x = (W + kSegPx - 1) / kSegPx;
+    const int64_t n_seg = (int64_t)B * H * segs_x;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    const bf16x8 zero = zero8();
+    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+        const int x0 = (int)(sg % segs_x) * kSegPx;
+        const int64_t row = sg / segs_x;
+        const int y = (int)(row % H);
+        __syncthreads();
+        {
+            const int px = t & 63, cg = t >> 6, xx = x0 + px;
+            const bf16x8 v = xx < W ? *reinterpret_cast<const bf16x8 *>(dz + (row * W + xx) * 32 + cg * 8) : zero;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = v[i];
+        }
+        if (t < 3 * 66) {
+            const int px = t % 66, rr = t / 66;
+            const int xx = x0 - 1 + px, iy = y + rr - 1;
+            __bf16 v0 = (__bf16)0.0f, v1 = (__bf16)0.0f;
+            if (xx >= 0 && xx < W && iy >= 0 && iy < H) {
+                const __bf16 *q = x + ((row - y + iy) * W + xx) * 2;
+                v0 = q[0];
+                v1 = q[1];
+            }
+            xT[rr][0][px + 7] = v0;
+            xT[rr][1][px + 7] = v1;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int pxb = kk * 32 + kb * 8;
+            const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&dT[cb * 16 + m][pxb]);
+            if (nb == 0) {
+                float sb = 0.f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sb += (float)A[e];
+                bacc += sb;
+            }
+            const __bf16 *rp = &xT[r][ch][0];
+            const u32x4w pv = *reinterpret_cast<const u32x4w *>(rp + pxb);
+            const u32x4w c = *reinterpret_cast<const u32x4w *>(rp + pxb + 8);
+            const u32x4w nx = *reinterpret_cast<const u32x4w *>(rp + pxb + 16);
+            u32x4w bv;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t lft = __builtin_amdgcn_alignbit(c[k], k ? c[k - 1] : pv[3], 16);
+                const uint32_t rgt = __builtin_amdgcn_alignbit(k < 3 ? c[k + 1] : nx[0], c[k], 16);
+                bv[k] = !col_ok ? 0u : (dx < 0 ? lft : (dx > 0 ? rgt : c[k]));
+            }
+            acc = mfma16(A, __builtin_bit_cast(bf16x8, bv), acc);
+        }
+    }
+    float *pb = part + (int64_t)blockIdx.x * kW1Row;
+    if (col_ok)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pb[(tap * 2 + ch) * 32 + 16 * cb + 4 * kb + i] = acc[i];
+    if (nb == 0) {
+        bacc += __shfl_xor(bacc, 16);
+        bacc += __shfl_xor(bacc, 32);
+        if (kb == 0) pb[576 + cb * 16 + m] = bacc;
     }
 }
 
@@ -633,7 +656,7 @@ namespace qld {
 namespace {
 
 constexpr int kGradBlocks = 512;     // work-groups of the MFMA weight-gradient reduction
-constexpr int kSmallBlocks = 1024;   // work-groups of the VALU gradient reductions
+constexpr int kSmallBlocks = 1024;   // work-groups of the output-layer gradient
 constexpr int kLossBlocks = 256;
 
 template <typename T>
@@ -677,21 +700,18 @@ qld_status reduce_rows(qld_denoiser *d, const float *part, int R, int n, float *
     return check_hip(hipGetLastError(), "reduce_rows launch");
 }
 
-template <typename XT, typename DT, int CI, int CO, int NT>
-qld_status small_grad(qld_denoiser *d, const XT *X, const DT *D, int B, int64_t off, hipStream_t s) {
-    const int64_t n_seg = (int64_t)B * d->H * ceil_div(d->W, kSeg);
-    const int blocks = (int)std::min<int64_t>(kSmallBlocks, n_seg);
-    hipLaunchKernelGGL((small_grad_kernel<XT, DT, CI, CO, NT>), dim3(blocks), dim3(256), 0, s, X, D, B, d->H, d->W,
-                       d->part);
-    QLD_TRY(check_hip(hipGetLastError(), "small_grad launch"));
-    return reduce_rows(d, d->part, blocks, NT * CI * CO, d->grads + off, s);
-}
-
 // Weights and bias of a 32 -> 32 layer (the bias follows the weights in the canonical order).
 qld_status dw32(qld_denoiser *d, const __bf16 *a, const __bf16 *dz, int B, int64_t off, hipStream_t s) {
     hipLaunchKernelGGL(dw32_kernel, dim3(kGradBlocks), dim3(256), 0, s, a, dz, B, d->H, d->W, d->part);
     QLD_TRY(check_hip(hipGetLastError(), "dw32 launch"));
     return reduce_rows(d, d->part, kGradBlocks, kW32Row, d->grads + off, s);
+}
+
+// Weights and bias of the input layer.
+qld_status dw1(qld_denoiser *d, int B, hipStream_t s) {
+    hipLaunchKernelGGL(dw1_kernel, dim3(kGradBlocks), dim3(256), 0, s, d->x0, d->dzC, B, d->H, d->W, d->part);
+    QLD_TRY(check_hip(hipGetLastError(), "dw1 launch"));
+    return reduce_rows(d, d->part, kGradBlocks, kW1Row, d->grads + OFF_W1, s);
 }
 
 // Weights and bias of the output layer.
@@ -906,8 +926,7 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));   // and b2
     hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(g), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W);
     // Layer 1: dW1 from (x0, dz1).
-    QLD_TRY(small_grad<__bf16, __bf16, 2, 32, 9>(d, d->x0, d->dzC, B, OFF_W1, s));
-    QLD_TRY(small_grad<__bf16, __bf16, 1, 32, 1>(d, nullptr, d->dzC, B, OFF_B1, s));
+    QLD_TRY(dw1(d, B, s));   // and b1
     // Gate (its own loss; its gradient reaches only Wg, bg).
     if (e_a) {
         hipLaunchKernelGGL(gate_back_kernel, dim3(1), dim3(64), 0, s, d->pool, d->gate, e_a, e_b, gate_weight, B,
