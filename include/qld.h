@@ -161,6 +161,42 @@ qld_status qld_window_save(const qld_window *w, const char *path);
 qld_status qld_window_load(qld_window *w, const char *path);
 
 /* ------------------------------------------------------------------------ */
+/* Per-frame sliding window: an image for every camera frame                */
+/* (Supplementary, sliding sequence: the display refreshes on each frame)  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct qld_fwindow qld_fwindow;
+
+/* Device bytes of a per-frame window: a ring of 4*M_cycles raw frames plus
+ * int32 I/Q state (0 for an invalid desc). */
+size_t qld_fwindow_bytes(const qld_frame_desc *d, int32_t M_cycles);
+
+/* Create a per-frame window of the last 4*M_cycles frames on the current
+ * device.  Frame n (counted from creation or the last reset) has lock-in
+ * phase (phase0 + n) mod 4.  M_cycles >= 1 and M_cycles * (2^bits - 1) < 2^31
+ * (else QLD_E_OVERFLOW). */
+qld_status qld_fwindow_create(const qld_frame_desc *d, int32_t M_cycles, int32_t phase0, qld_fwindow **out);
+
+/*
+ * Feed one frame (device, layout of d: rows row_pitch elements apart) and
+ * refresh the window: with c, s the reference values of the frame's phase and
+ * S_old the frame 4*M_cycles earlier (0 while the window is filling),
+ *     I += c (S - S_old),   Q += s (S - S_old).
+ * I_out, Q_out (int32 [H][W], both or neither) and amp_out (float [H][W]) are
+ * device outputs, each may be NULL; warm_out (host, may be NULL) receives 1
+ * once the window holds 4*M_cycles frames.  The quadratures use the absolute
+ * phase of the frame counter, so the amplitude does not rotate between frames.
+ */
+qld_status qld_fwindow_update(qld_fwindow *w, const void *frame, int32_t *I_out, int32_t *Q_out,
+                              float *amp_out, int32_t *warm_out, qld_hip_stream stream);
+
+/* Forget every frame; the next frame has phase phase0 (e.g. after a gap). */
+qld_status qld_fwindow_reset(qld_fwindow *w, int32_t phase0);
+/* Frames currently in the window (0..4M) and frames fed since creation/reset. */
+qld_status qld_fwindow_info(const qld_fwindow *w, int32_t *n_in_window, int64_t *n_frames);
+qld_status qld_fwindow_destroy(qld_fwindow *w);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: many camera streams, one GPU, continuous batching               */
 /* ------------------------------------------------------------------------ */
 

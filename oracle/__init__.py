@@ -163,6 +163,29 @@ def dft_bin(frames, k: int, n_threads: int | None = None):
     return re + 1j * im
 
 
+def frame_window_series(frames, M: int, phase0: int = 0, resets=None):
+    """Per-frame sliding window (Supplementary, sliding sequence): after frame
+    f the window holds frames max(r, f - 4M + 1) .. f, r the latest reset at or
+    before f, and frame f has lock-in phase (p_r + f - r) mod 4 where p_r is
+    the phase given at that reset (phase0 for r = 0).  (I, Q) by re-summing the
+    stored frames with the lock-in definition; yields (I, Q, n_in_window).
+
+    ``frames``: sequence of [H][W] arrays.  ``resets``: {frame index: phase of
+    that frame}.
+    """
+    resets = dict(resets or {})
+    history = []
+    start, p_start = 0, int(phase0) % 4
+    for f, fr in enumerate(frames):
+        history.append(np.asarray(fr))
+        if f in resets:
+            start, p_start = f, int(resets[f]) % 4
+        lo = max(start, f - 4 * M + 1)
+        stack = np.stack(history[lo:f + 1], axis=0)
+        I, Q = qld(stack, (p_start + lo - start) % 4)
+        yield I, Q, f - lo + 1
+
+
 def window_series(cycles, M: int, resets=()):
     """Sliding-window (I, Q) after every cycle, by re-summing the stored history.
 

@@ -6,7 +6,7 @@ stream -> hipStream_t); every step of the computation runs in the HIP
 kernels of ``libqld.so``.  There is no fallback: if the library is missing
 or fails to load, importing this package raises.
 
-Build the library with ``python -m paper_1511_03390_amd._build`` (or
+Build the library with ``python paper_1511_03390_amd/_build.py`` (or
 ``__graft_entry__.build()``).
 """
 from __future__ import annotations
@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqld.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libqld.so is not built (%s); run python -m paper_1511_03390_amd._build" % LIB_PATH)
+    raise ImportError("libqld.so is not built (%s); run python paper_1511_03390_amd/_build.py" % LIB_PATH)
 _lib = ctypes.CDLL(LIB_PATH)
 
 # Status codes (qld_status).
@@ -35,6 +35,8 @@ EXPORTS = (
     "qld_accumulate", "qld_amplitude", "dft_bin_baseline",
     "qld_window_bytes", "qld_window_create", "qld_window_update", "qld_window_reset",
     "qld_window_destroy", "qld_window_info", "qld_window_save", "qld_window_load",
+    "qld_fwindow_bytes", "qld_fwindow_create", "qld_fwindow_update", "qld_fwindow_reset", "qld_fwindow_info",
+    "qld_fwindow_destroy",
     "qld_server_create", "qld_server_stream_bytes", "qld_stream_open", "qld_stream_state",
     "qld_stream_set_denoiser", "qld_stream_submit", "qld_stream_poll", "qld_stream_result_iq", "qld_server_drain",
     "qld_stream_close", "qld_server_destroy", "qld_server_stats",
@@ -86,6 +88,12 @@ _sig("qld_window_reset", ctypes.c_int, _vp)
 _sig("qld_window_destroy", ctypes.c_int, _vp)
 _sig("qld_window_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64))
 _sig("qld_window_save", ctypes.c_int, _vp, ctypes.c_char_p)
+_sig("qld_fwindow_bytes", _sz, _dp, _i32)
+_sig("qld_fwindow_create", ctypes.c_int, _dp, _i32, _i32, ctypes.POINTER(_vp))
+_sig("qld_fwindow_update", ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _vp)
+_sig("qld_fwindow_reset", ctypes.c_int, _vp, _i32)
+_sig("qld_fwindow_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64))
+_sig("qld_fwindow_destroy", ctypes.c_int, _vp)
 _sig("qld_window_load", ctypes.c_int, _vp, ctypes.c_char_p)
 _sig("qld_server_create", ctypes.c_int, _sz, _i32, _i32, ctypes.POINTER(_vp))
 _sig("qld_server_stream_bytes", _sz, _vp, _dp, _i32, _i32, _i32)
@@ -282,6 +290,54 @@ class Window:
     def close(self):
         if getattr(self, "_h", None):
             _check(_lib.qld_window_destroy(self._h), "qld_window_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FrameWindow:
+    """Per-frame sliding window of the last 4 M frames (an image for every frame)."""
+
+    def __init__(self, H, W, M, phase0=0, dtype=torch.int16, bits=None):
+        dt, nbits = _DT[dtype]
+        self.desc = FrameDesc(int(H), int(W), int(W), int(H) * int(W), dt, int(bits or nbits))
+        self.H, self.W, self.M = H, W, M
+        h = _vp()
+        _check(_lib.qld_fwindow_create(ctypes.byref(self.desc), int(M), int(phase0), ctypes.byref(h)),
+               "qld_fwindow_create")
+        self._h = h
+
+    @staticmethod
+    def bytes(H, W, M, dtype=torch.int16, bits=None):
+        dt, nbits = _DT[dtype]
+        d = FrameDesc(int(H), int(W), int(W), int(H) * int(W), dt, int(bits or nbits))
+        return int(_lib.qld_fwindow_bytes(ctypes.byref(d), int(M)))
+
+    def update(self, frame, I_out=None, Q_out=None, amp_out=None, stream=None):
+        """Feed one frame ([H][W] device tensor with contiguous rows); returns warm."""
+        if tuple(frame.shape) != (self.H, self.W) or (self.H > 1 and frame.stride(0) != self.W) or \
+                (self.W > 1 and frame.stride(1) != 1):
+            raise ValueError("frame must be a contiguous [%d][%d] tensor" % (self.H, self.W))
+        warm = _i32()
+        _check(_lib.qld_fwindow_update(self._h, _ptr(frame), _ptr(I_out), _ptr(Q_out), _ptr(amp_out),
+                                       ctypes.byref(warm), _stream(stream)), "qld_fwindow_update")
+        return warm.value
+
+    def reset(self, phase0=0):
+        _check(_lib.qld_fwindow_reset(self._h, int(phase0)), "qld_fwindow_reset")
+
+    def info(self):
+        n, c = _i32(), _i64()
+        _check(_lib.qld_fwindow_info(self._h, ctypes.byref(n), ctypes.byref(c)), "qld_fwindow_info")
+        return n.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.qld_fwindow_destroy(self._h), "qld_fwindow_destroy")
             self._h = None
 
     def __del__(self):

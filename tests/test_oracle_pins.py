@@ -224,6 +224,48 @@ def test_window_sinusoid_closed_form():
         assert I[0, 0] == 2 * n * a and Q[0, 0] == 2 * n * b
 
 
+def test_frame_window_sinusoid_closed_form():
+    # Every full period of a pure sinusoid adds (2a, 2b) whatever frame it
+    # starts on, so a window of n frames (n a multiple of 4) gives I = 2 (n/4) a.
+    a, b, c, M = 5, -3, 40, 3
+    per = [c + a, c + b, c - a, c - b]
+    frames = [np.full((2, 2), per[t % 4], dtype=np.uint16) for t in range(30)]
+    for f, (I, Q, n) in enumerate(oracle.frame_window_series(frames, M)):
+        assert n == min(f + 1, 4 * M)
+        if n % 4 == 0:
+            assert (I == 2 * (n // 4) * a).all() and (Q == 2 * (n // 4) * b).all(), f
+
+
+def test_frame_window_impulse_enters_and_leaves():
+    # One frame of value v at t0: it contributes v * (c, s)(phase of t0) while
+    # inside the window of 4M frames, and nothing once it has left.
+    M, t0, v, p0 = 2, 5, 7, 3
+    frames = [np.zeros((1, 1), dtype=np.uint16) for _ in range(20)]
+    frames[t0][0, 0] = v
+    c, s = oracle.reference_tables()
+    ph = (p0 + t0) % 4
+    for f, (I, Q, n) in enumerate(oracle.frame_window_series(frames, M, phase0=p0)):
+        inside = t0 <= f < t0 + 4 * M
+        assert I[0, 0] == (v * c[ph] if inside else 0) and Q[0, 0] == (v * s[ph] if inside else 0), f
+
+
+def test_frame_window_matches_cycle_window_and_reset():
+    rng = np.random.default_rng(12)
+    frames = [rng.integers(0, 4096, size=(3, 4)).astype(np.uint16) for _ in range(24)]
+    cycles = [np.stack(frames[4 * k:4 * k + 4]) for k in range(6)]
+    fw = list(oracle.frame_window_series(frames, 2))
+    cw = list(oracle.window_series(cycles, 2))
+    for k in range(6):                       # cycle-aligned frames: the same window
+        assert (fw[4 * k + 3][0] == cw[k][0]).all() and (fw[4 * k + 3][1] == cw[k][1]).all()
+    # A reset at frame r with phase p equals a fresh window started there.
+    r, p = 9, 2
+    with_reset = list(oracle.frame_window_series(frames, 2, resets={r: p}))
+    fresh = list(oracle.frame_window_series(frames[r:], 2, phase0=p))
+    for f in range(r, 24):
+        assert (with_reset[f][0] == fresh[f - r][0]).all() and (with_reset[f][1] == fresh[f - r][1]).all()
+        assert with_reset[f][2] == fresh[f - r][2]
+
+
 def test_cnr_surround_matches_paper_example():
     g = read_kv("surround_fig_s.txt")
     src, surr = judges.square_masks((g["frame_h"], g["frame_w"]), 4, 4, g["source_side"])
