@@ -232,6 +232,32 @@ def bench_streaming(qld, torch, seconds, fps, M=64):
             "unpaced_launches": unpaced_batches, "wall_s": round(wall, 2)}
 
 
+def bench_frame_window(qld, torch, M=64, n=400):
+    """Per-frame sliding window on one 1024 x 1024 uint16 camera: the window of
+    the last 4M frames refreshed, and its amplitude written, for every frame."""
+    Hf = Wf = 1024
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1511033906)
+    bank = torch.randint(0, 4096, (16, Hf, Wf), generator=g, device="cuda", dtype=torch.int32).to(torch.int16)
+    fw = qld.FrameWindow(Hf, Wf, M, bits=12)
+    amp = torch.empty((Hf, Wf), dtype=torch.float32, device="cuda")
+    for f in range(4 * M + 8):                      # fill the window
+        fw.update(bank[f % 16], amp_out=amp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for f in range(n):
+        fw.update(bank[f % 16], amp_out=amp)
+    e1.record()
+    torch.cuda.synchronize()
+    fw.close()
+    ms = e0.elapsed_time(e1) / n
+    per_px = 2 + 2 + 2 + 16 + 4                    # frame in, ring out/in, I/Q read+write, amplitude out
+    return {"workload": "1024x1024 uint16 (12-bit), window of %d frames (M=%d cycles), amplitude every frame" % (4 * M, M),
+            "update_ms": round(ms, 4), "frames_per_s": round(1e3 / ms), "bytes_per_px_frame": per_px,
+            "achieved_gbs": round(per_px * Hf * Wf / (ms * 1e-3) / 1e9, 1)}
+
+
 def copy_calibration(torch, gib=1):
     """A plain device copy of known size (torch's elementwise negation of an
     int32 buffer: 4 B read and 4 B written per element).  Under rocprofv3
@@ -485,6 +511,9 @@ def main():
         log("learned path: %d training steps of 8 tiles" % args.learned_steps)
         learned = bench_learned(qld, torch, args.learned_steps, 2)
 
+    log("per-frame window")
+    frame_window = bench_frame_window(qld, torch)
+
     learned_serving = None
     if not args.no_learned_serving:
         log("learned serving: clutter and motion, %d cycles" % args.serving_cycles)
@@ -513,6 +542,7 @@ def main():
         "streaming": streaming,
         "learned": learned,
         "learned_serving": learned_serving,
+        "frame_window": frame_window,
         "library": qld.version(),
     }
     if calib is not None:

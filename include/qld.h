@@ -121,6 +121,23 @@ qld_status qld_amplitude(const int32_t *I, const int32_t *Q, int64_t n_pixels, f
 qld_status dft_bin_baseline(const void *frames, const qld_frame_desc *d, int32_t n_frames,
                             int32_t k_bin, float *re, float *im, qld_hip_stream stream);
 
+/*
+ * qld_lockin_ratio -- lock-in at a general frequency ratio f_mod / f_s = p / q
+ * (Methods, R(j,k) with reference tables of any frequency, precomputed once):
+ *     X = sum_{t < n} S_t exp(-2 pi i ((p (t0 + t)) mod q) / q) = I - iQ,
+ * I and Q the sums of the series times the cos and sin tables of the lock-in
+ * phase 2 pi p (t0 + t) / q; the image is R = |X|.  t0 >= 0 is the time index
+ * of frame 0.  With p / q = 1/4 and t0 = phase0 this is the four-sample QLD in
+ * float; with q = n_frames it is dft_bin_baseline at bin p.  A source at
+ * another frequency cancels over whole beat periods (the wrong-frequency
+ * rejection of the method).  Same tables, precision and layout as
+ * dft_bin_baseline.  QLD_E_INVAL for q < 1 or t0 < 0, QLD_E_SHAPE for
+ * n_frames < 1.
+ *   re, im  device float [H][W] (dense, overwritten)
+ */
+qld_status qld_lockin_ratio(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t p,
+                            int32_t q, int32_t t0, float *re, float *im, qld_hip_stream stream);
+
 /* ------------------------------------------------------------------------ */
 /* Sliding window (Supplementary: sliding sequence of N frames, buffer N n^2) */
 /* ------------------------------------------------------------------------ */

@@ -63,6 +63,9 @@ def _load():
         lib.oracle_dft_bin.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                        _f64p, _f64p, ctypes.c_int]
+        lib.oracle_lockin_ratio.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, _f64p, _f64p, ctypes.c_int]
         lib.oracle_reference_tables.argtypes = [_i64p, _i64p]
         u32p = ctypes.POINTER(ctypes.c_uint32)
         lib.oracle_philox4x32.argtypes = [u32p, u32p, ctypes.c_int, u32p]
@@ -160,6 +163,20 @@ def dft_bin(frames, k: int, n_threads: int | None = None):
                                     n_threads or threads())
         if rc:
             raise RuntimeError("oracle_dft_bin failed (%d)" % rc)
+    return re + 1j * im
+
+
+def lockin_ratio(frames, p: int, q: int, t0: int = 0, n_threads: int | None = None):
+    """Lock-in of every pixel's series at frequency ratio p/q (time of frame 0:
+    t0), complex128 [H][W]: X = I - iQ with the cos/sin reference tables."""
+    ptr, es, H, W, rp, fs, T, keep = _frames_args(frames)
+    re = np.zeros((H, W))
+    im = np.zeros((H, W))
+    if T and H and W:
+        rc = _load().oracle_lockin_ratio(ptr, es, H, W, rp, fs, T, int(p), int(q), int(t0),
+                                         re.ctypes.data_as(_f64p), im.ctypes.data_as(_f64p), n_threads or threads())
+        if rc:
+            raise RuntimeError("oracle_lockin_ratio failed (%d)" % rc)
     return re + 1j * im
 
 

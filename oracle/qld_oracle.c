@@ -159,6 +159,35 @@ int oracle_dft_bin(const void *frames, int elem, int H, int W, int64_t row_pitch
     return 0;
 }
 
+/*
+ * Lock-in at a general ratio f_mod / f_s = p / q (Methods, R(j,k) with the
+ * reference tables of that frequency): X = sum_n S_n (cos th_n - i sin th_n),
+ * th_n = 2 pi ((p (t0 + n)) mod q) / q, the angle reduced in exact integers
+ * first.  In double.
+ */
+int oracle_lockin_ratio(const void *frames, int elem, int H, int W, int64_t row_pitch, int64_t frame_stride,
+                        int T, int p, int q, int t0, double *re, double *im, int n_threads)
+{
+    if (elem != 1 && elem != 2) return 2;
+    if (T <= 0 || q <= 0 || t0 < 0) return 3;
+    memset(re, 0, sizeof(double) * (size_t)H * (size_t)W);
+    memset(im, 0, sizeof(double) * (size_t)H * (size_t)W);
+    if (n_threads < 1) n_threads = 1;
+    for (int n = 0; n < T; ++n) {
+        int64_t r = (((int64_t)p * ((int64_t)t0 + n)) % q + q) % q;
+        double th = 2.0 * ORACLE_PI * (double)r / (double)q;
+        double c = cos(th), s = sin(th);
+#pragma omp parallel for num_threads(n_threads) schedule(static)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                double v = (double)sample_at(frames, elem, (int64_t)n * frame_stride + (int64_t)y * row_pitch + x);
+                re[(int64_t)y * W + x] += v * c;
+                im[(int64_t)y * W + x] -= v * s;
+            }
+    }
+    return 0;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

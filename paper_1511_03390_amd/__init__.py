@@ -32,7 +32,7 @@ MODE_PLAIN, MODE_LEARNED = 0, 1
 
 # Every entry point the header declares (checked by the tests).
 EXPORTS = (
-    "qld_accumulate", "qld_amplitude", "dft_bin_baseline",
+    "qld_accumulate", "qld_amplitude", "dft_bin_baseline", "qld_lockin_ratio",
     "qld_window_bytes", "qld_window_create", "qld_window_update", "qld_window_reset",
     "qld_window_destroy", "qld_window_info", "qld_window_save", "qld_window_load",
     "qld_fwindow_bytes", "qld_fwindow_create", "qld_fwindow_update", "qld_fwindow_reset", "qld_fwindow_info",
@@ -88,6 +88,7 @@ _sig("qld_window_reset", ctypes.c_int, _vp)
 _sig("qld_window_destroy", ctypes.c_int, _vp)
 _sig("qld_window_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64))
 _sig("qld_window_save", ctypes.c_int, _vp, ctypes.c_char_p)
+_sig("qld_lockin_ratio", ctypes.c_int, _vp, _dp, _i32, _i32, _i32, _i32, _vp, _vp, _vp)
 _sig("qld_fwindow_bytes", _sz, _dp, _i32)
 _sig("qld_fwindow_create", ctypes.c_int, _dp, _i32, _i32, ctypes.POINTER(_vp))
 _sig("qld_fwindow_update", ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _vp)
@@ -221,6 +222,14 @@ def accumulate(frames, I, Q, phase0=0, bits=None, frame_sum=None, frame_sat=None
 
 def amplitude(I, Q, amp, stream=None):
     _check(_lib.qld_amplitude(_ptr(I), _ptr(Q), int(I.numel()), _ptr(amp), _stream(stream)), "qld_amplitude")
+
+
+def lockin_ratio(frames, p, q, re, im, t0=0, bits=None, stream=None):
+    """Lock-in at frequency ratio p/q (frames [T][H][W]); re/im float [H][W]; X = I - iQ."""
+    d = frame_desc(frames, bits)
+    n = frames.shape[0] if frames.dim() == 3 else 1
+    _check(_lib.qld_lockin_ratio(_ptr(frames), ctypes.byref(d), int(n), int(p), int(q), int(t0), _ptr(re), _ptr(im),
+                                 _stream(stream)), "qld_lockin_ratio")
 
 
 def dft_bin_baseline(frames, k, re, im, bits=None, stream=None):

@@ -37,12 +37,14 @@ struct DftArgs {
     float *part;            // [n_split][2][H*W] (n_split > 1)
 };
 
-__global__ __launch_bounds__(256) void dft_twiddle_kernel(int32_t N, int32_t k, float2 *tw) {
+// tw[n] = (cos, sin)(2 pi r / period), r = (k (t0 + n)) mod period, n < n_frames.
+__global__ __launch_bounds__(256) void dft_twiddle_kernel(int32_t n_frames, int32_t period, int32_t k, int32_t t0,
+                                                          float2 *tw) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    const int64_t r = (((int64_t)k * n) % N + N) % N;
+    if (n >= n_frames) return;
+    const int64_t r = (((int64_t)k * ((int64_t)t0 + n)) % period + period) % period;
     double s, c;
-    sincospi(2.0 * (double)r / (double)N, &s, &c);
+    sincospi(2.0 * (double)r / (double)period, &s, &c);
     tw[n] = make_float2((float)c, (float)s);
 }
 
@@ -178,15 +180,13 @@ hipError_t launch_dft(const DftArgs &a, int grid, hipStream_t s) {
 
 using namespace qld;
 
-extern "C" qld_status dft_bin_baseline(const void *frames, const qld_frame_desc *d, int32_t n_frames,
-                                       int32_t k_bin, float *re, float *im, qld_hip_stream stream) {
-    clear_error();
+namespace {
+
+// X = sum_{n < n_frames} S_n exp(-2 pi i ((k (t0 + n)) mod period) / period), float.
+qld_status single_frequency(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t k,
+                            int32_t period, int32_t t0, float *re, float *im, qld_hip_stream stream) {
     int eb = 0;
     QLD_TRY(check_desc(d, &eb));
-    if (n_frames < 1) {
-        set_error("dft_bin_baseline needs n_frames >= 1 (got %d)", n_frames);
-        return QLD_E_SHAPE;
-    }
     const int64_t npx = (int64_t)d->H * d->W;
     if (npx == 0) return QLD_OK;
     if (!frames || !re || !im) {
@@ -235,7 +235,7 @@ extern "C" qld_status dft_bin_baseline(const void *frames, const qld_frame_desc 
     a.im = im;
 
     hipLaunchKernelGGL(dft_twiddle_kernel, dim3((unsigned)ceil_div(n_frames, 256)), dim3(256), 0, s, n_frames,
-                       k_bin, tw);
+                       period, k, t0, tw);
     QLD_TRY(check_hip(hipGetLastError(), "dft_twiddle_kernel launch"));
     const int64_t grid = ceil_div(n_tiles, kXcds) * kXcds * n_split;
     hipEvent_t ev0, ev1;
@@ -253,4 +253,30 @@ extern "C" qld_status dft_bin_baseline(const void *frames, const qld_frame_desc 
         QLD_TRY(check_hip(hipGetLastError(), "dft_split_reduce_kernel launch"));
     }
     return QLD_OK;
+}
+
+}  // namespace
+
+extern "C" qld_status dft_bin_baseline(const void *frames, const qld_frame_desc *d, int32_t n_frames,
+                                       int32_t k_bin, float *re, float *im, qld_hip_stream stream) {
+    clear_error();
+    if (n_frames < 1) {
+        set_error("dft_bin_baseline needs n_frames >= 1 (got %d)", n_frames);
+        return QLD_E_SHAPE;
+    }
+    return single_frequency(frames, d, n_frames, k_bin, n_frames, 0, re, im, stream);
+}
+
+extern "C" qld_status qld_lockin_ratio(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t p,
+                                       int32_t q, int32_t t0, float *re, float *im, qld_hip_stream stream) {
+    clear_error();
+    if (n_frames < 1) {
+        set_error("qld_lockin_ratio needs n_frames >= 1 (got %d)", n_frames);
+        return QLD_E_SHAPE;
+    }
+    if (q < 1 || t0 < 0) {
+        set_error("qld_lockin_ratio needs q >= 1 and t0 >= 0 (got q=%d, t0=%d)", q, t0);
+        return QLD_E_INVAL;
+    }
+    return single_frequency(frames, d, n_frames, p, q, t0, re, im, stream);
 }

@@ -164,6 +164,56 @@ def test_dft_bin_baseline(T, H, W, k, dt):
         assert np.abs(im.cpu().numpy() + oQ).max() <= bound.max()
 
 
+@pytest.mark.parametrize("T,H,W,p,q,t0,dt", [(64, 33, 40, 1, 4, 3, np.uint16), (200, 16, 64, 3, 20, 0, np.uint16),
+                                              (37, 5, 9, 7, 11, 5, np.uint8), (300, 4, 24, -2, 9, 1, np.uint8),
+                                              (1024, 8, 72, 23, 100, 17, np.uint16)])
+def test_lockin_ratio(T, H, W, p, q, t0, dt):
+    """General-ratio lock-in against the oracle (double, exact angle reduction)
+    within the float accumulation bound; p/q = 1/4 equals the integer QLD."""
+    need_gpu()
+    rng = np.random.default_rng(T + W + q)
+    bits = 12 if dt == np.uint16 else 8
+    f = rng.integers(0, (1 << bits), size=(T, H, W)).astype(dt)
+    re = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    im = torch.empty_like(re)
+    qld.lockin_ratio(to_dev(f), p, q, re, im, t0=t0, bits=bits)
+    torch.cuda.synchronize()
+    X = oracle.lockin_ratio(f, p, q, t0)
+    bound = dft_bound(f, T)
+    err_r = np.abs(re.cpu().numpy() - X.real)
+    err_i = np.abs(im.cpu().numpy() - X.imag)
+    say("lock-in ratio", p, q, "max err", err_r.max(), err_i.max(), "bound", bound.min())
+    assert (err_r <= bound).all() and (err_i <= bound).all()
+    if (p, q) == (1, 4):
+        oI, oQ = oracle.qld(f, t0 % 4)
+        assert np.abs(re.cpu().numpy() - oI).max() <= bound.max()
+        assert np.abs(im.cpu().numpy() + oQ).max() <= bound.max()
+
+
+def test_lockin_ratio_rejects_another_frequency():
+    """Wrong-frequency rejection: a source at 3/20 of the frame rate next to one
+    at 7/20; each lock-in sees its own source (A T / 2) and not the other."""
+    need_gpu()
+    T, H, W = 400, 8, 32
+    t = np.arange(T)[:, None, None]
+    x = np.arange(W)[None, None, :]
+    left = x < W // 2
+    sig = 1000 + np.where(left, 200 * np.cos(2 * np.pi * 3 * t / 20), 120 * np.cos(2 * np.pi * 7 * t / 20 + 0.4))
+    f = np.broadcast_to(np.rint(sig), (T, H, W)).astype(np.uint16)
+    re = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    im = torch.empty_like(re)
+    amp = {}
+    for p in (3, 7):
+        qld.lockin_ratio(to_dev(f), p, 20, re, im, bits=12)
+        torch.cuda.synchronize()
+        amp[p] = np.hypot(re.cpu().numpy(), im.cpu().numpy())
+    resid = np.abs(np.rint(sig) - sig).sum(axis=0)              # sample rounding
+    tol = resid + dft_bound(f, T)
+    lmask = np.broadcast_to(left[0], (H, W))
+    assert np.all(np.abs(amp[3][lmask] - 200 * T / 2) <= tol[lmask]) and np.all(amp[3][~lmask] <= tol[~lmask])
+    assert np.all(np.abs(amp[7][~lmask] - 120 * T / 2) <= tol[~lmask]) and np.all(amp[7][lmask] <= tol[lmask])
+
+
 def test_full_size_diffuse_scene_sampled():
     """1024 x 1024 uint16 (12-bit), 1024 frames: the benchmark's launch, sampled
     pixels checked by the oracle one by one; statistics against torch's sums."""

@@ -266,6 +266,37 @@ def test_frame_window_matches_cycle_window_and_reset():
         assert with_reset[f][2] == fresh[f - r][2]
 
 
+def test_lockin_ratio_quarter_is_the_integer_lockin():
+    # p/q = 1/4 with t0 = phase0 reduces to the four-sample QLD: X = I - iQ.
+    rng = np.random.default_rng(21)
+    st = rng.integers(0, 4096, size=(23, 3, 5)).astype(np.uint16)
+    for p0 in range(4):
+        I, Q = oracle.qld(st, p0)
+        X = oracle.lockin_ratio(st, 1, 4, p0)
+        assert np.allclose(X.real, I, atol=1e-9) and np.allclose(X.imag, -Q, atol=1e-9)
+        X5 = oracle.lockin_ratio(st, 5, 4, p0)            # p is taken mod q
+        assert np.allclose(X5, X, atol=1e-9)
+
+
+def test_lockin_ratio_matches_fft_and_rejects_other_frequencies():
+    rng = np.random.default_rng(22)
+    T = 60
+    st = rng.integers(0, 255, size=(T, 2, 3)).astype(np.uint8)
+    F = np.fft.fft(st.astype(np.float64), axis=0)
+    for k in (0, 1, 7, 15, 59):                           # q = T: the DFT bin k
+        assert np.allclose(oracle.lockin_ratio(st, k, T), F[k], atol=1e-8)
+    # A source at 3/20 of the sampling rate, seen at 7/20 over 60 frames (three
+    # whole beat periods): nothing; at its own frequency: amplitude A T / 2.
+    A, t = 50.0, np.arange(T)
+    src = np.rint(100 + A * np.cos(2 * np.pi * 3 * t / 20)).astype(np.uint16)
+    seq = stack_from_series(src)
+    own = oracle.lockin_ratio(seq, 3, 20)[0, 0]
+    other = oracle.lockin_ratio(seq, 7, 20)[0, 0]
+    resid = src - (100 + A * np.cos(2 * np.pi * 3 * t / 20))  # rounding of the samples
+    bound = np.abs(resid).sum()
+    assert abs(abs(own) - A * T / 2) <= bound and abs(other) <= bound
+
+
 def test_cnr_surround_matches_paper_example():
     g = read_kv("surround_fig_s.txt")
     src, surr = judges.square_masks((g["frame_h"], g["frame_w"]), 4, 4, g["source_side"])
