@@ -232,6 +232,43 @@ def bench_streaming(qld, torch, seconds, fps, M=64):
             "unpaced_launches": unpaced_batches, "wall_s": round(wall, 2)}
 
 
+def bench_bank(qld, torch, frames, dft_ms, F=32, reps=5):
+    """Bank of F lock-ins (bins 240..271 of the 1024-frame stack) on the fp32
+    matrix cores, against F single-frequency passes and a full FFT along time."""
+    q = T
+    ps = list(range(T // 4 - F // 2, T // 4 + F // 2))
+    re = torch.empty((F, H, W), dtype=torch.float32, device="cuda")
+    im = torch.empty_like(re)
+    qld.lockin_bank(frames, ps, q, re, im, bits=12)
+    timers = [qld.KernelTimer() for _ in range(reps)]
+    for k in range(reps):
+        timers[k].arm()
+        qld.lockin_bank(frames, ps, q, re, im, bits=12)
+    torch.cuda.synchronize()
+    ms = sum(t.ms() for t in timers) / reps
+    flop = 2.0 * 2 * F * T * H * W
+    del re, im
+    # Full spectrum of every pixel's series with the vendor FFT (float32 copy of the stack first).
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    xf = frames.view(T, H * W).float().t().contiguous()        # [pixel][time], transforms contiguous
+    e1.record()
+    spec = torch.fft.rfft(xf, dim=1)
+    e2.record()
+    torch.cuda.synchronize()
+    fft = {"convert_transpose_ms": round(e0.elapsed_time(e1), 3), "rfft_ms": round(e1.elapsed_time(e2), 3),
+           "bins": int(spec.shape[1]), "library": "torch.fft.rfft (vendor FFT), float32, pixel-major copy"}
+    del xf, spec
+    torch.cuda.empty_cache()
+    return {"workload": "1024x1024 uint16 (12-bit), 1024 frames, %d frequencies (bins %d..%d of 1024)" % (F, ps[0], ps[-1]),
+            "kernel": "bank_kernel (v_mfma_f32_16x16x4_f32)", "kernel_ms": round(ms, 4),
+            "tflops": round(flop / (ms * 1e-3) / 1e12, 1), "fp32_mfma_peak_tflops": 157.3,
+            "frac": round(flop / (ms * 1e-3) / 157.3e12, 4),
+            "single_frequency_x%d_ms" % F: round(F * dft_ms, 3),
+            "speedup_vs_single_frequency": round(F * dft_ms / ms, 1),
+            "full_fft": fft}
+
+
 def bench_frame_window(qld, torch, M=64, n=400):
     """Per-frame sliding window on one 1024 x 1024 uint16 camera: the window of
     the last 4M frames refreshed, and its amplitude written, for every frame."""
@@ -490,6 +527,9 @@ def main():
            "pxf_per_s": round(pxf / (d_avg * 1e-3)), "achieved_gbs": round(kern_bytes / (d_avg * 1e-3) / 1e9, 1),
            "ms_per_call": round(d_el / max(5, args.steps // 2) * 1e3, 4)}
 
+    log("lock-in bank")
+    bank = bench_bank(qld, torch, frames, d_avg)
+
     calib = copy_calibration(torch) if args.copy_calibration else None
 
     cpu = None
@@ -543,6 +583,7 @@ def main():
         "learned": learned,
         "learned_serving": learned_serving,
         "frame_window": frame_window,
+        "lockin_bank": bank,
         "library": qld.version(),
     }
     if calib is not None:

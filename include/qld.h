@@ -138,6 +138,21 @@ qld_status dft_bin_baseline(const void *frames, const qld_frame_desc *d, int32_t
 qld_status qld_lockin_ratio(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t p,
                             int32_t q, int32_t t0, float *re, float *im, qld_hip_stream stream);
 
+/*
+ * qld_lockin_bank -- a bank of n_freq lock-ins at once (the paper's
+ * multi-frequency images, Fig. 1, sources at several modulation frequencies;
+ * Methods, Fourier map as a series of lock-ins): for f < n_freq
+ *     X_f = sum_{t < n} S_t exp(-2 pi i ((p_f (t0 + t)) mod q) / q) = I_f - i Q_f,
+ * each equal to qld_lockin_ratio(p_f, q, t0), computed as one contraction on
+ * the matrix cores in fp32 (same tolerance as the single-frequency path).
+ *   p_host  HOST int32 [n_freq], any integers (reduced mod q)
+ *   re, im  device float [n_freq][H][W] (dense, overwritten)
+ * QLD_E_INVAL for q < 1, t0 < 0 or a NULL p_host; QLD_E_SHAPE for n_frames < 1.
+ */
+qld_status qld_lockin_bank(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t n_freq,
+                           const int32_t *p_host, int32_t q, int32_t t0, float *re, float *im,
+                           qld_hip_stream stream);
+
 /* ------------------------------------------------------------------------ */
 /* Sliding window (Supplementary: sliding sequence of N frames, buffer N n^2) */
 /* ------------------------------------------------------------------------ */
@@ -442,11 +457,13 @@ qld_status qld_denoiser_adam(qld_denoiser *d, float lr, float beta1, float beta2
 const char *qld_status_str(qld_status st);
 const char *qld_last_error(void);
 /* Device timing of the main kernel alone: start_event / stop_event are
- * hipEvent_t handles created by the caller.  The next qld_accumulate or
- * dft_bin_baseline call made by this thread records start_event on its
- * stream right before its main kernel (qld_accum_kernel / dft_bin_kernel) and
- * stop_event right after it, excluding the helper kernels (statistics
- * reduction, twiddle table, chunk reduction).  Both NULL cancels. */
+ * hipEvent_t handles created by the caller.  The next qld_accumulate,
+ * dft_bin_baseline, qld_lockin_ratio, qld_lockin_bank or qld_denoiser_forward
+ * call made by this thread records start_event on its stream right before its
+ * main kernel (qld_accum_kernel / dft_bin_kernel / the first bank_kernel / the
+ * four convolution kernels) and stop_event right after it, excluding the
+ * helper kernels (statistics reduction, twiddle table, chunk reduction,
+ * input conversion, pooling).  Both NULL cancels. */
 qld_status qld_time_next_kernel(void *start_event, void *stop_event);
 /* Library build string (compiler, target). */
 const char *qld_version(void);

@@ -180,6 +180,12 @@ def lockin_ratio(frames, p: int, q: int, t0: int = 0, n_threads: int | None = No
     return re + 1j * im
 
 
+def lockin_bank(frames, p_list, q: int, t0: int = 0):
+    """Lock-ins at ratios p_f / q for every f (the bank is one lock-in per
+    frequency), complex128 [F][H][W]."""
+    return np.stack([lockin_ratio(frames, p, q, t0) for p in p_list], axis=0)
+
+
 def frame_window_series(frames, M: int, phase0: int = 0, resets=None):
     """Per-frame sliding window (Supplementary, sliding sequence): after frame
     f the window holds frames max(r, f - 4M + 1) .. f, r the latest reset at or

@@ -32,7 +32,7 @@ MODE_PLAIN, MODE_LEARNED = 0, 1
 
 # Every entry point the header declares (checked by the tests).
 EXPORTS = (
-    "qld_accumulate", "qld_amplitude", "dft_bin_baseline", "qld_lockin_ratio",
+    "qld_accumulate", "qld_amplitude", "dft_bin_baseline", "qld_lockin_ratio", "qld_lockin_bank",
     "qld_window_bytes", "qld_window_create", "qld_window_update", "qld_window_reset",
     "qld_window_destroy", "qld_window_info", "qld_window_save", "qld_window_load",
     "qld_fwindow_bytes", "qld_fwindow_create", "qld_fwindow_update", "qld_fwindow_reset", "qld_fwindow_info",
@@ -89,6 +89,7 @@ _sig("qld_window_destroy", ctypes.c_int, _vp)
 _sig("qld_window_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64))
 _sig("qld_window_save", ctypes.c_int, _vp, ctypes.c_char_p)
 _sig("qld_lockin_ratio", ctypes.c_int, _vp, _dp, _i32, _i32, _i32, _i32, _vp, _vp, _vp)
+_sig("qld_lockin_bank", ctypes.c_int, _vp, _dp, _i32, _i32, ctypes.POINTER(_i32), _i32, _i32, _vp, _vp, _vp)
 _sig("qld_fwindow_bytes", _sz, _dp, _i32)
 _sig("qld_fwindow_create", ctypes.c_int, _dp, _i32, _i32, ctypes.POINTER(_vp))
 _sig("qld_fwindow_update", ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _vp)
@@ -139,7 +140,8 @@ lib = _lib
 
 class KernelTimer:
     """HIP events (from the HIP runtime, on the launch stream) around the main
-    kernel of the next qld_accumulate / dft_bin_baseline call of this thread."""
+    kernel of the next qld_accumulate / dft_bin_baseline / qld_lockin_ratio /
+    qld_lockin_bank / qld_denoiser_forward call of this thread."""
 
     _hip = None
 
@@ -230,6 +232,20 @@ def lockin_ratio(frames, p, q, re, im, t0=0, bits=None, stream=None):
     n = frames.shape[0] if frames.dim() == 3 else 1
     _check(_lib.qld_lockin_ratio(_ptr(frames), ctypes.byref(d), int(n), int(p), int(q), int(t0), _ptr(re), _ptr(im),
                                  _stream(stream)), "qld_lockin_ratio")
+
+
+def lockin_bank(frames, p_list, q, re=None, im=None, t0=0, bits=None, stream=None):
+    """Bank of lock-ins at ratios p_f/q (frames [T][H][W]); returns re, im float [F][H][W]."""
+    d = frame_desc(frames, bits)
+    n = frames.shape[0] if frames.dim() == 3 else 1
+    F = len(p_list)
+    if re is None:
+        re = torch.empty((F, d.H, d.W), dtype=torch.float32, device=frames.device)
+        im = torch.empty_like(re)
+    arr = (_i32 * max(F, 1))(*[int(v) for v in p_list])
+    _check(_lib.qld_lockin_bank(_ptr(frames), ctypes.byref(d), int(n), int(F), arr, int(q), int(t0), _ptr(re),
+                                _ptr(im), _stream(stream)), "qld_lockin_bank")
+    return re, im
 
 
 def dft_bin_baseline(frames, k, re, im, bits=None, stream=None):

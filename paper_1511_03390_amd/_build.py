@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("QLD_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["capi.cpp", "accumulate.hip", "dft.hip", "window.hip", "server.cpp", "gen.hip", "denoise.hip", "judges.hip",
-           "serve_learned.hip", "frame_window.hip"]
+           "serve_learned.hip", "frame_window.hip", "bank.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

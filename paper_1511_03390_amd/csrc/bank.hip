@@ -1,0 +1,191 @@
+// Multi-frequency lock-in bank: F lock-ins of every pixel's series at once.
+//
+// The paper obtains its multi-source images (Fig. 1: sources at 20, 23, 26
+// and 29 Hz) by running the lock-in at each frequency, and compares the
+// lock-in against a full Fourier transform of the series (Methods, Fourier
+// map; "Processing Time and Speedup").  For F frequencies p_f / q of the frame
+// rate the bank is one contraction
+//     X[f][px] = sum_t S_t[px] (cos th_ft - i sin th_ft),
+//     th_ft = 2 pi ((p_f (t0 + t)) mod q) / q,
+// i.e. C[px][2F] = S^T[px][T] . B[T][2F] with B[t][2f] = cos, B[t][2f+1] = -sin.
+// It runs on the matrix cores in fp32 (v_mfma_f32_16x16x4_f32: fp32 products
+// and accumulation, the arithmetic of the single-frequency float path):
+//   * A operand (16 pixels x 4 frames): lane (m, kb) holds sample (frame kb,
+//     pixel m), read straight from the time-major stack (16 consecutive
+//     pixels of a frame per 16 lanes);
+//   * B operand (4 frames x 16 columns): from the table, staged in LDS in
+//     chunks of 32 frames and shared by the work-group's four waves;
+//   * a wave owns 64 pixels (4 row blocks) x all 2F columns (F <= 32 per
+//     launch; larger banks are split into groups of 32 frequencies).
+// The table is built per call in double from the exact integer angle and
+// rounded to float, like the single-frequency path.
+#include <vector>
+
+#include "qld_internal.hpp"
+
+namespace qld {
+namespace {
+
+typedef float f32x4b __attribute__((ext_vector_type(4)));
+
+constexpr int kBankBlock = 256;     // 4 waves x 64 pixels
+constexpr int kMaxF = 32;           // frequencies per launch
+constexpr int kTChunk = 32;         // frames per staged table chunk
+constexpr int kTabStride = 80;      // floats per staged table row: the 4 rows a wave reads fall in different banks
+
+// tab[t][2f] = cos, tab[t][2f+1] = -sin of 2 pi r / q, r = (p_f (t0 + t)) mod q; columns padded to ncol.
+__global__ __launch_bounds__(256) void bank_table_kernel(const int32_t *__restrict__ p, int32_t F, int32_t q,
+                                                         int32_t t0, int32_t T, int32_t ncol, float *__restrict__ tab) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)T * ncol) return;
+    const int64_t t = i / ncol;
+    const int n = (int)(i % ncol), f = n >> 1;
+    float v = 0.f;
+    if (f < F) {
+        const int64_t r = (((int64_t)p[f] * ((int64_t)t0 + t)) % q + q) % q;
+        double s, c;
+        sincospi(2.0 * (double)r / (double)q, &s, &c);
+        v = (n & 1) ? (float)(-s) : (float)c;
+    }
+    tab[i] = v;
+}
+
+template <typename T, int NCB>
+__global__ __launch_bounds__(kBankBlock) void bank_kernel(const T *__restrict__ frames, int64_t row_pitch,
+                                                          int64_t frame_stride, int H, int W, int n_frames,
+                                                          const float *__restrict__ tab, int F,
+                                                          float *__restrict__ re, float *__restrict__ im) {
+    constexpr int NCOL = NCB * 16;
+    __shared__ float tl[kTChunk][kTabStride];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
+    const int64_t npx = (int64_t)H * W;
+    const int64_t px0 = (int64_t)blockIdx.x * kBankBlock + wave * 64;
+    // The four pixels this lane loads (one per 16-row block) and their offsets.
+    int64_t off[4];
+    bool ok[4];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+        const int64_t p = px0 + pb * 16 + m;
+        ok[pb] = p < npx;
+        const int64_t pc = ok[pb] ? p : 0;
+        off[pb] = (pc / W) * row_pitch + pc % W;
+    }
+    f32x4b acc[4][NCB];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = f32x4b{0.f, 0.f, 0.f, 0.f};
+
+    for (int tc = 0; tc < n_frames; tc += kTChunk) {
+        __syncthreads();                                  // the previous chunk's readers are done
+        for (int i = t; i < kTChunk * NCOL; i += kBankBlock) {
+            const int tt = i / NCOL, n = i % NCOL;
+            tl[tt][n] = tc + tt < n_frames ? tab[(int64_t)(tc + tt) * NCOL + n] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll 2   // measured: deeper unrolling (8) is slower at 32 frequencies
+        for (int ks = 0; ks < kTChunk; ks += 4) {
+            const int tf = tc + ks + kb;                  // this lane's frame
+            const bool in_t = tf < n_frames;
+            const T *fp = frames + (int64_t)(in_t ? tf : 0) * frame_stride;
+            float a[4];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) a[pb] = (in_t && ok[pb]) ? (float)fp[off[pb]] : 0.f;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const float b = tl[ks + kb][cb * 16 + m];
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb)
+                    acc[pb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[pb], b, acc[pb][cb], 0, 0, 0);
+            }
+        }
+    }
+    // D[row = 4 kb + i][col = m]: pixel px0 + 16 pb + 4 kb + i, column 16 cb + m.
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int n = cb * 16 + m, f = n >> 1;
+            if (f >= F) continue;
+            float *dst = (n & 1) ? im : re;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t p = px0 + pb * 16 + 4 * kb + i;
+                if (p < npx) dst[(int64_t)f * npx + p] = acc[pb][cb][i];
+            }
+        }
+}
+
+template <typename T>
+hipError_t launch_bank(int ncb, const T *frames, int64_t rp, int64_t fs, int H, int W, int n, const float *tab, int F,
+                       float *re, float *im, hipStream_t s) {
+    const int64_t npx = (int64_t)H * W;
+    const dim3 grid((unsigned)ceil_div(npx, kBankBlock));
+    switch (ncb) {
+        case 1: hipLaunchKernelGGL((bank_kernel<T, 1>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab, F, re, im); break;
+        case 2: hipLaunchKernelGGL((bank_kernel<T, 2>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab, F, re, im); break;
+        case 3: hipLaunchKernelGGL((bank_kernel<T, 3>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab, F, re, im); break;
+        default: hipLaunchKernelGGL((bank_kernel<T, 4>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab, F, re, im); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace qld
+
+using namespace qld;
+
+extern "C" qld_status qld_lockin_bank(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t n_freq,
+                                      const int32_t *p_host, int32_t q, int32_t t0, float *re, float *im,
+                                      qld_hip_stream stream) {
+    clear_error();
+    int eb = 0;
+    QLD_TRY(check_desc(d, &eb));
+    if (n_frames < 1 || n_freq < 0) {
+        set_error("qld_lockin_bank needs n_frames >= 1 and n_freq >= 0 (got %d, %d)", n_frames, n_freq);
+        return QLD_E_SHAPE;
+    }
+    if (q < 1 || t0 < 0 || (n_freq > 0 && !p_host)) {
+        set_error("qld_lockin_bank needs q >= 1, t0 >= 0 and the frequencies (got q=%d, t0=%d)", q, t0);
+        return QLD_E_INVAL;
+    }
+    const int64_t npx = (int64_t)d->H * d->W;
+    if (npx == 0 || n_freq == 0) return QLD_OK;
+    if (!frames || !re || !im) {
+        set_error("frames, re and im must be non-NULL");
+        return QLD_E_INVAL;
+    }
+    if (ceil_div(npx, kBankBlock) > 0x7fffffff) {
+        set_error("image too large");
+        return QLD_E_SHAPE;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int32_t f0 = 0; f0 < n_freq; f0 += kMaxF) {
+        const int F = std::min<int32_t>(kMaxF, n_freq - f0);
+        const int ncb = (int)ceil_div(2 * F, 16);
+        const int ncol = ncb * 16;
+        const size_t tab_b = ((sizeof(float) * (size_t)n_frames * ncol + 255) / 256) * 256;
+        char *ws = static_cast<char *>(stream_workspace(s, tab_b + 256));
+        if (!ws) return QLD_E_NOMEM;
+        float *tab = reinterpret_cast<float *>(ws);
+        int32_t *pd = reinterpret_cast<int32_t *>(ws + tab_b);
+        QLD_TRY(check_hip(hipMemcpyAsync(pd, p_host + f0, sizeof(int32_t) * F, hipMemcpyHostToDevice, s),
+                          "frequency upload"));
+        hipLaunchKernelGGL(bank_table_kernel, dim3((unsigned)ceil_div((int64_t)n_frames * ncol, 256)), dim3(256), 0, s,
+                           pd, F, q, t0, n_frames, ncol, tab);
+        QLD_TRY(check_hip(hipGetLastError(), "bank_table_kernel launch"));
+        hipEvent_t ev0, ev1;
+        take_kernel_timer(&ev0, &ev1);
+        if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
+        hipError_t e;
+        if (eb == 2)
+            e = launch_bank(ncb, static_cast<const uint16_t *>(frames), d->row_pitch, d->frame_stride, d->H, d->W,
+                            n_frames, tab, F, re + (int64_t)f0 * npx, im + (int64_t)f0 * npx, s);
+        else
+            e = launch_bank(ncb, static_cast<const uint8_t *>(frames), d->row_pitch, d->frame_stride, d->H, d->W,
+                            n_frames, tab, F, re + (int64_t)f0 * npx, im + (int64_t)f0 * npx, s);
+        QLD_TRY(check_hip(e, "bank_kernel launch"));
+        if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
+    }
+    return QLD_OK;
+}

@@ -214,6 +214,50 @@ def test_lockin_ratio_rejects_another_frequency():
     assert np.all(np.abs(amp[7][~lmask] - 120 * T / 2) <= tol[~lmask]) and np.all(amp[7][lmask] <= tol[lmask])
 
 
+@pytest.mark.parametrize("T,H,W,F,q,t0,dt", [(64, 9, 40, 1, 64, 0, np.uint16), (100, 13, 37, 5, 100, 3, np.uint16),
+                                              (77, 5, 130, 17, 20, 1, np.uint8), (256, 16, 64, 32, 256, 0, np.uint16),
+                                              (33, 3, 70, 40, 33, 7, np.uint16)])
+def test_lockin_bank(T, H, W, F, q, t0, dt):
+    """Bank of F lock-ins (fp32 matrix cores) against the oracle's lock-in at
+    each frequency, within the float accumulation bound."""
+    need_gpu()
+    rng = np.random.default_rng(T * F + W)
+    bits = 12 if dt == np.uint16 else 8
+    f = rng.integers(0, (1 << bits), size=(T, H, W)).astype(dt)
+    ps = [int(v) for v in rng.integers(-q, 2 * q, size=F)]
+    re, im = qld.lockin_bank(to_dev(f), ps, q, t0=t0, bits=bits)
+    torch.cuda.synchronize()
+    X = oracle.lockin_bank(f, ps, q, t0)
+    bound = dft_bound(f, T)[None]
+    err_r = np.abs(re.cpu().numpy() - X.real)
+    err_i = np.abs(im.cpu().numpy() - X.imag)
+    say("bank F", F, "max err", err_r.max(), err_i.max(), "bound", bound.min())
+    assert (err_r <= bound).all() and (err_i <= bound).all()
+
+
+def test_lockin_bank_separates_four_sources():
+    """Four sources modulated at 20, 23, 26 and 29 Hz seen at 100 frames/s (the
+    paper's Fig. 1 frequencies): over whole beat periods each image of the bank
+    shows its own source only."""
+    need_gpu()
+    T, H, W = 500, 4, 64
+    t = np.arange(T)[:, None, None]
+    x = np.arange(W)[None, None, :]
+    freqs = [20, 23, 26, 29]
+    sig = np.full((T, 1, W), 1500.0)
+    for j, fq in enumerate(freqs):
+        sig = sig + np.where(x // 16 == j, 300 * np.cos(2 * np.pi * fq * t / 100 + 0.3 * j), 0.0)
+    f = np.broadcast_to(np.rint(sig), (T, H, W)).astype(np.uint16)
+    re, im = qld.lockin_bank(to_dev(f), freqs, 100, bits=12)
+    torch.cuda.synchronize()
+    amp = np.hypot(re.cpu().numpy(), im.cpu().numpy())
+    tol = np.abs(np.rint(sig) - sig).sum(axis=0) + dft_bound(f, T)   # sample rounding + float bound
+    for j in range(4):
+        own = np.broadcast_to((x // 16 == j)[0], (H, W))
+        assert np.all(np.abs(amp[j][own] - 300 * T / 2) <= tol[own]), j
+        assert np.all(amp[j][~own] <= tol[~own]), j
+
+
 def test_full_size_diffuse_scene_sampled():
     """1024 x 1024 uint16 (12-bit), 1024 frames: the benchmark's launch, sampled
     pixels checked by the oracle one by one; statistics against torch's sums."""

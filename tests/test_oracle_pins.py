@@ -297,6 +297,14 @@ def test_lockin_ratio_matches_fft_and_rejects_other_frequencies():
     assert abs(abs(own) - A * T / 2) <= bound and abs(other) <= bound
 
 
+def test_lockin_bank_is_the_full_fft_when_every_bin_is_asked():
+    rng = np.random.default_rng(23)
+    T = 24
+    st = rng.integers(0, 4096, size=(T, 2, 3)).astype(np.uint16)
+    X = oracle.lockin_bank(st, list(range(T)), T)
+    assert np.allclose(X, np.fft.fft(st.astype(np.float64), axis=0), atol=1e-7)
+
+
 def test_cnr_surround_matches_paper_example():
     g = read_kv("surround_fig_s.txt")
     src, surr = judges.square_masks((g["frame_h"], g["frame_w"]), 4, 4, g["source_side"])
