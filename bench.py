@@ -269,6 +269,52 @@ def bench_bank(qld, torch, frames, dft_ms, F=32, reps=5):
             "full_fft": fft}
 
 
+def fig1_labels(np, boxes, n, m, which):
+    """CNR labels of source `which`: 1 on its m x m box, 2 on the m-wide square
+    ring around it (8 m^2 pixels), 0 elsewhere."""
+    lab = np.zeros((n, n), dtype=np.uint8)
+    y0, x0 = boxes[which]
+    lab[max(0, y0 - m):y0 + 2 * m, max(0, x0 - m):x0 + 2 * m] = 2
+    lab[y0:y0 + m, x0:x0 + m] = 1
+    return lab
+
+
+def bench_fig1(qld, torch, seeds=16):
+    """Synthetic analog of the paper's numerical example (five sources, four at
+    20/23/26/29 Hz, 100 frames/s, uniform noise U[0, X]): CNR of the 23 Hz
+    source in the QLD image (exact ratio 23/100) and in the FFT map |F|^2 at
+    the nearest bin, on N = 82 and N/2 = 41 frames, and at the wrong
+    frequency 31 Hz; means over seeded repetitions."""
+    import numpy as np
+    import scenes
+    res = {}
+    for X in (2.0, 5.0, 10.0):
+        for N in (41, 82):
+            acc = {k: [] for k in ("qld", "fft_power", "fft_amplitude", "qld_31hz", "fft_power_31hz")}
+            for sd in range(seeds):
+                fr, boxes, meta = scenes.fig1_analog(scenes.seed_for(6, 1000 * int(X) + sd), N, X)
+                n, m = meta["n"], meta["m"]
+                dev = torch.from_numpy(fr.view(np.int16)).cuda()
+                lab = torch.from_numpy(fig1_labels(np, boxes, n, m, 1)).cuda()[None]
+                re = torch.empty((n, n), dtype=torch.float32, device="cuda")
+                im = torch.empty_like(re)
+
+                def cnr(img):
+                    return float(qld.judge_cnr(img.reshape(1, n, n).contiguous(), lab).item())
+
+                for f_hz, tag in ((23, ""), (31, "_31hz")):
+                    qld.lockin_ratio(dev, f_hz, 100, re, im, t0=1, bits=12)
+                    acc["qld" + tag].append(cnr(torch.hypot(re, im)))
+                    qld.dft_bin_baseline(dev, int(round(f_hz * N / 100)), re, im, bits=12)
+                    acc["fft_power" + tag].append(cnr(re * re + im * im))
+                    if not tag:
+                        acc["fft_amplitude"].append(cnr(torch.hypot(re, im)))
+            res["X=%g,N=%d" % (X, N)] = {k: round(float(np.mean(v)), 2) for k, v in acc.items()}
+    return {"workload": "64x64 frames, five 8x8 sources (20/23/26/29 Hz and one constant), 100 frames/s, "
+                        "U[0, X] noise, 23 Hz source judged, %d seeds per point" % seeds,
+            "mean_cnr": res}
+
+
 def bench_frame_window(qld, torch, M=64, n=400):
     """Per-frame sliding window on one 1024 x 1024 uint16 camera: the window of
     the last 4M frames refreshed, and its amplitude written, for every frame."""
@@ -529,6 +575,8 @@ def main():
 
     log("lock-in bank")
     bank = bench_bank(qld, torch, frames, d_avg)
+    log("synthetic Fig. 1 analog")
+    fig1 = bench_fig1(qld, torch)
 
     calib = copy_calibration(torch) if args.copy_calibration else None
 
@@ -584,6 +632,7 @@ def main():
         "learned_serving": learned_serving,
         "frame_window": frame_window,
         "lockin_bank": bank,
+        "fig1_analog": fig1,
         "library": qld.version(),
     }
     if calib is not None:

@@ -388,3 +388,45 @@ class ClutterMotionScene:
         d2 = (yy - cy) ** 2 + (xx - cx) ** 2
         out.append(("disk", d2 <= r * r, (d2 > r * r) & (d2 <= 9 * r * r)))
         return out
+
+
+FIG1_FREQS = (20.0, 23.0, 26.0, 29.0)           # Hz, the paper's Fig. 1 modulation frequencies
+
+
+def fig1_analog(seed, N, X=5.0, n=64, m=8, fs=100.0, freqs=FIG1_FREQS, scale=100.0, pedestal=0.5,
+                constant=0.5, polarised=None):
+    """Synthetic analog of the paper's numerical example (Methods, numerical
+    simulations; Fig. 1): an n x n frame with five non-overlapping m x m
+    sources, four with intensity 0.5 + sin(2 pi f_i t_s) and one constant,
+    frames at t_s = s / fs for s = 1..N, and a uniform U[0, X] number added
+    to every pixel of every frame (diffuse and ambient light).  Samples are
+    round(scale * (pedestal + intensity + noise)) as uint16 (the pedestal
+    keeps them non-negative; it is constant in time).
+
+    polarised=(f_p, ballistic, depolarised): instead of intensity modulation,
+    source 0's light has its linear polarisation rotating at f_p and is seen
+    through a fixed analyser: ballistic * cos^2(2 pi f_p t_s) + depolarised / 2
+    (modulated at 2 f_p); the other sources are off.
+
+    Returns (frames [N][n][n] uint16, sources [(y0, x0)] of the m x m boxes,
+    meta dict)."""
+    rng = np.random.default_rng(seed)
+    q = n // 8
+    boxes = [(q, q), (q, n - q - m), (n - q - m, q), (n - q - m, n - q - m), (n // 2 - m // 2, n // 2 - m // 2)]
+    t = np.arange(1, N + 1, dtype=np.float64) / fs
+    base = np.full((N, n, n), pedestal)
+    for i, (y0, x0) in enumerate(boxes):
+        if polarised is not None:
+            if i == 0:
+                fp, ball, depol = polarised
+                inten = ball * np.cos(2 * np.pi * fp * t) ** 2 + depol / 2
+            else:
+                continue
+        elif i < len(freqs):
+            inten = 0.5 + np.sin(2 * np.pi * freqs[i] * t)
+        else:
+            inten = np.full(N, constant)
+        base[:, y0:y0 + m, x0:x0 + m] += inten[:, None, None]
+    noisy = base + rng.uniform(0.0, X, size=base.shape)
+    frames = np.clip(np.rint(scale * noisy), 0, 65535).astype(np.uint16)
+    return frames, boxes, dict(fs=fs, freqs=freqs, m=m, n=n, X=X, N=N, scale=scale)
