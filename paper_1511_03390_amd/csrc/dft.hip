@@ -19,10 +19,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;
-// Four work-groups per CU hide the latency of the FMA chain best (measured
-// at 1024 frames of 1024 x 1024 uint16: 69% of HBM peak versus 44% at two).
+// With four frames in flight per wave, two work-groups per CU stream best
+// (measured at 1024 frames of 1024 x 1024 uint16: 75-79% of HBM peak versus
+// 67-68% at three or four).
 #ifndef QLD_DFT_BLOCKS_PER_CU
-#define QLD_DFT_BLOCKS_PER_CU 4
+#define QLD_DFT_BLOCKS_PER_CU 2
 #endif
 
 struct DftArgs {
@@ -48,37 +49,78 @@ __global__ __launch_bounds__(256) void dft_twiddle_kernel(int32_t n_frames, int3
     tw[n] = make_float2((float)c, (float)s);
 }
 
-template <int ELEM, int VPX, bool VEC>
-__device__ __forceinline__ void load_f(const uint8_t *p, bool full, int nvalid, float (&v)[VPX]) {
-    if constexpr (VEC) {
-        if (full) {
-            const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-            const uint32_t w[4] = {q[0], q[1], q[2], q[3]};
-            if constexpr (ELEM == 2) {
+// A lane's VPX samples of one frame as floats: one 16-byte load (VECLOAD), or
+// element by element for the row-tail lane and unaligned stacks.
+template <int ELEM, int VPX, bool VECLOAD>
+__device__ __forceinline__ void load_f(const uint8_t *p, int nvalid, float (&v)[VPX]) {
+    if constexpr (VECLOAD) {
+        const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        const uint32_t w[4] = {q[0], q[1], q[2], q[3]};
+        if constexpr (ELEM == 2) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    v[2 * j] = (float)(w[j] & 0xffffu);
-                    v[2 * j + 1] = (float)(w[j] >> 16);
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    v[4 * j] = (float)(w[j] & 0xffu);
-                    v[4 * j + 1] = (float)((w[j] >> 8) & 0xffu);
-                    v[4 * j + 2] = (float)((w[j] >> 16) & 0xffu);
-                    v[4 * j + 3] = (float)(w[j] >> 24);
-                }
+            for (int j = 0; j < 4; ++j) {
+                v[2 * j] = (float)(w[j] & 0xffffu);
+                v[2 * j + 1] = (float)(w[j] >> 16);
             }
-            return;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[4 * j] = (float)(w[j] & 0xffu);
+                v[4 * j + 1] = (float)((w[j] >> 8) & 0xffu);
+                v[4 * j + 2] = (float)((w[j] >> 16) & 0xffu);
+                v[4 * j + 3] = (float)(w[j] >> 24);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < VPX; ++j) {
+            if (j < nvalid) {
+                if constexpr (ELEM == 2) v[j] = (float)reinterpret_cast<const uint16_t *>(p)[j];
+                else v[j] = (float)p[j];
+            } else {
+                v[j] = 0.f;
+            }
         }
     }
+}
+
+// Frames t0 .. t1-1 of one lane into (re, im) += S_t (cos, sin).  With vector
+// loads the four loads of an iteration are kept together ahead of the
+// arithmetic, so a wave has four frames in flight.
+template <int ELEM, int VPX, bool VECLOAD>
+__device__ __forceinline__ void dft_frames(const float2 *__restrict__ tw, const uint8_t *p, int64_t fs, int64_t t0,
+                                           int64_t t1, int nvalid, float (&re)[VPX], float (&im)[VPX]) {
+    int64_t t = t0;
+    for (; t + 4 <= t1; t += 4) {
+        float v0[VPX], v1[VPX], v2[VPX], v3[VPX];
+        load_f<ELEM, VPX, VECLOAD>(p, nvalid, v0);
+        load_f<ELEM, VPX, VECLOAD>(p + fs, nvalid, v1);
+        load_f<ELEM, VPX, VECLOAD>(p + 2 * fs, nvalid, v2);
+        load_f<ELEM, VPX, VECLOAD>(p + 3 * fs, nvalid, v3);
+        if constexpr (VECLOAD) __builtin_amdgcn_sched_barrier(0);
+        p += 4 * fs;
+        const float2 w0 = tw[t], w1 = tw[t + 1], w2 = tw[t + 2], w3 = tw[t + 3];
 #pragma unroll
-    for (int j = 0; j < VPX; ++j) {
-        if (j < nvalid) {
-            if constexpr (ELEM == 2) v[j] = (float)reinterpret_cast<const uint16_t *>(p)[j];
-            else v[j] = (float)p[j];
-        } else {
-            v[j] = 0.f;
+        for (int j = 0; j < VPX; ++j) {
+            re[j] = __builtin_fmaf(v0[j], w0.x, re[j]);
+            im[j] = __builtin_fmaf(v0[j], w0.y, im[j]);
+            re[j] = __builtin_fmaf(v1[j], w1.x, re[j]);
+            im[j] = __builtin_fmaf(v1[j], w1.y, im[j]);
+            re[j] = __builtin_fmaf(v2[j], w2.x, re[j]);
+            im[j] = __builtin_fmaf(v2[j], w2.y, im[j]);
+            re[j] = __builtin_fmaf(v3[j], w3.x, re[j]);
+            im[j] = __builtin_fmaf(v3[j], w3.y, im[j]);
+        }
+    }
+    for (; t < t1; ++t) {
+        float v[VPX];
+        load_f<ELEM, VPX, VECLOAD>(p, nvalid, v);
+        p += fs;
+        const float2 w = tw[t];
+#pragma unroll
+        for (int j = 0; j < VPX; ++j) {
+            re[j] = __builtin_fmaf(v[j], w.x, re[j]);
+            im[j] = __builtin_fmaf(v[j], w.y, im[j]);
         }
     }
 }
@@ -108,37 +150,13 @@ __global__ __launch_bounds__(kBlock) void dft_bin_kernel(DftArgs a) {
 #pragma unroll
     for (int j = 0; j < VPX; ++j) re[j] = im[j] = 0.f;
 
-    int64_t t = t0;
-    for (; t + 4 <= t1; t += 4) {
-        float v0[VPX], v1[VPX], v2[VPX], v3[VPX];
-        load_f<ELEM, VPX, VEC>(p, full, nvalid, v0);
-        load_f<ELEM, VPX, VEC>(p + fs, full, nvalid, v1);
-        load_f<ELEM, VPX, VEC>(p + 2 * fs, full, nvalid, v2);
-        load_f<ELEM, VPX, VEC>(p + 3 * fs, full, nvalid, v3);
-        p += 4 * fs;
-        const float2 w0 = a.tw[t], w1 = a.tw[t + 1], w2 = a.tw[t + 2], w3 = a.tw[t + 3];
-#pragma unroll
-        for (int j = 0; j < VPX; ++j) {
-            re[j] = __builtin_fmaf(v0[j], w0.x, re[j]);
-            im[j] = __builtin_fmaf(v0[j], w0.y, im[j]);
-            re[j] = __builtin_fmaf(v1[j], w1.x, re[j]);
-            im[j] = __builtin_fmaf(v1[j], w1.y, im[j]);
-            re[j] = __builtin_fmaf(v2[j], w2.x, re[j]);
-            im[j] = __builtin_fmaf(v2[j], w2.y, im[j]);
-            re[j] = __builtin_fmaf(v3[j], w3.x, re[j]);
-            im[j] = __builtin_fmaf(v3[j], w3.y, im[j]);
-        }
-    }
-    for (; t < t1; ++t) {
-        float v[VPX];
-        load_f<ELEM, VPX, VEC>(p, full, nvalid, v);
-        p += fs;
-        const float2 w = a.tw[t];
-#pragma unroll
-        for (int j = 0; j < VPX; ++j) {
-            re[j] = __builtin_fmaf(v[j], w.x, re[j]);
-            im[j] = __builtin_fmaf(v[j], w.y, im[j]);
-        }
+    // Full lanes stream with vector loads; only the lane at a row's ragged end
+    // (or an unaligned stack) reads element by element.
+    if constexpr (VEC) {
+        if (full) dft_frames<ELEM, VPX, true>(a.tw, p, fs, t0, t1, nvalid, re, im);
+        else dft_frames<ELEM, VPX, false>(a.tw, p, fs, t0, t1, nvalid, re, im);
+    } else {
+        dft_frames<ELEM, VPX, false>(a.tw, p, fs, t0, t1, nvalid, re, im);
     }
 
     const int64_t npx = (int64_t)a.H * a.W;
