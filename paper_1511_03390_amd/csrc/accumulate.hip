@@ -521,18 +521,22 @@ __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
 }
 
 // frame_sum[t] += sum over waves of part_sum[w][t] (and the same for counts).
-// Grid: (ceil(T/64), ceil(n_waves/kRowsPerBlock)), one wave per work-group.
-constexpr int kRowsPerBlock = 32;
+// Grid: (ceil(T/256), ceil(n_waves/kRowsPerBlock)), 256 lanes per work-group.
+constexpr int kRowsPerBlock = 16;
 
-__global__ __launch_bounds__(64) void qld_stats_reduce_kernel(const uint32_t *ps, const uint32_t *pc,
-                                                              int64_t n_waves, int32_t T,
-                                                              uint64_t *frame_sum, uint32_t *frame_sat) {
-    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+// Folds the per-wave partials: work-group (frames 256 bx .. +256, waves
+// kRowsPerBlock by .. +kRowsPerBlock); the rows are read with many loads in
+// flight per lane, and the integer sums combined with order-free atomics.
+__global__ __launch_bounds__(256) void qld_stats_reduce_kernel(const uint32_t *ps, const uint32_t *pc,
+                                                               int64_t n_waves, int32_t T,
+                                                               uint64_t *frame_sum, uint32_t *frame_sat) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= T) return;
     const int64_t w0 = (int64_t)blockIdx.y * kRowsPerBlock;
     const int64_t w1 = min(n_waves, w0 + kRowsPerBlock);
     uint64_t s = 0;
     uint32_t c = 0;
+#pragma unroll 16
     for (int64_t w = w0; w < w1; ++w) {
         s += ps[w * T + t];
         c += pc[w * T + t];
@@ -684,8 +688,8 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
         QLD_TRY(check_hip(e, "qld_accum_scalar_kernel launch"));
     }
     if (stats) {
-        dim3 g2((unsigned)ceil_div(n_frames, 64), (unsigned)ceil_div(n_waves, kRowsPerBlock));
-        hipLaunchKernelGGL(qld_stats_reduce_kernel, g2, dim3(64), 0, s, av.part_sum, av.part_sat, n_waves,
+        dim3 g2((unsigned)ceil_div(n_frames, 256), (unsigned)ceil_div(n_waves, kRowsPerBlock));
+        hipLaunchKernelGGL(qld_stats_reduce_kernel, g2, dim3(256), 0, s, av.part_sum, av.part_sat, n_waves,
                            n_frames, frame_sum, frame_sat);
         QLD_TRY(check_hip(hipGetLastError(), "qld_stats_reduce_kernel launch"));
     }
