@@ -4,9 +4,9 @@
 Workload (one step = one pass of the batch path over one stack already in HBM):
 1024 x 1024 uint16 frames (12-bit values), 1024 frames (M = 256 cycles) of the
 seeded diffuse scene -- Poisson background ~2000 counts with a linear +-50
-ambient drift and a weak modulated mask of 5 rectangles.  A step zeroes I/Q
-and the statistics, runs qld_accumulate (I/Q plus per-frame sum / saturation
-count) and qld_amplitude.
+ambient drift and a weak modulated mask of 5 rectangles.  A step is one
+qld_lockin_image call: I/Q, the amplitude image and the per-frame sum /
+saturation count of the stack, in one pass over the frames.
 
 Printed: one JSON line with the pixel-frames/s of the step, the roofline of
 the dominant kernel (qld_accum_kernel, timed alone with HIP events on its
@@ -60,22 +60,17 @@ def measured_traffic(kernel_src):
 
 def bench_batch(qld, torch, frames, steps, warmup):
     dev = frames.device
-    I = torch.zeros((H, W), dtype=torch.int32, device=dev)
-    Q = torch.zeros_like(I)
-    fsum = torch.zeros(T, dtype=torch.int64, device=dev)
-    fsat = torch.zeros(T, dtype=torch.int32, device=dev)
+    I = torch.empty((H, W), dtype=torch.int32, device=dev)
+    Q = torch.empty_like(I)
+    fsum = torch.empty(T, dtype=torch.int64, device=dev)
+    fsat = torch.empty(T, dtype=torch.int32, device=dev)
     amp = torch.empty((H, W), dtype=torch.float32, device=dev)
     timers = [qld.KernelTimer() for _ in range(steps)]
 
     def step(timer=None):
-        I.zero_()
-        Q.zero_()
-        fsum.zero_()
-        fsat.zero_()
         if timer is not None:
             timer.arm()
-        qld.accumulate(frames, I, Q, 0, 12, fsum, fsat)
-        qld.amplitude(I, Q, amp)
+        qld.lockin_image(frames, I, Q, amp, 0, 12, fsum, fsat)
 
     for _ in range(warmup):
         step()
@@ -561,9 +556,9 @@ def main():
     pxf = H * W * T
     value = pxf * args.steps / elapsed
     kern_avg = sum(kern_ms) / len(kern_ms)
-    kern_bytes = H * W * T * 2 + H * W * 8          # frames read + I/Q written
+    kern_bytes = H * W * T * 2 + H * W * 12         # frames read + I/Q and amplitude written
     achieved = kern_bytes / (kern_avg * 1e-3) / 1e9
-    step_bytes = H * W * (T * 2 + 12)
+    step_bytes = H * W * (T * 2 + 12)                # the step is that kernel plus the statistics fold
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(("accumulate.hip",)),

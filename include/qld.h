@@ -110,6 +110,19 @@ qld_status qld_amplitude(const int32_t *I, const int32_t *Q, int64_t n_pixels, f
                          qld_hip_stream stream);
 
 /*
+ * qld_lockin_image -- one image from a stack in a single pass (a1-a4 fused):
+ * I, Q = the stack's quadrature sums (overwritten, not added), amp =
+ * (I^2 + Q^2)^(1/2) as qld_amplitude computes it (may be NULL), frame_sum /
+ * frame_sat the per-frame statistics (each may be NULL; overwritten).  The
+ * same as clearing the outputs, qld_accumulate and qld_amplitude, without
+ * the separate clears and the second pass over I/Q.  Arguments and errors as
+ * qld_accumulate, plus QLD_E_SHAPE for n_frames < 1.
+ */
+qld_status qld_lockin_image(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t phase0,
+                            int32_t *I, int32_t *Q, float *amp, uint64_t *frame_sum, uint32_t *frame_sat,
+                            qld_hip_stream stream);
+
+/*
  * dft_bin_baseline -- the Fourier alternative at one frequency (Methods,
  * Fourier map |F(omega)|^2 of each pixel's series):
  *     X_k = sum_{n < N} S_n exp(-2 pi i ((k n) mod N) / N),   N = n_frames

@@ -32,7 +32,7 @@ MODE_PLAIN, MODE_LEARNED = 0, 1
 
 # Every entry point the header declares (checked by the tests).
 EXPORTS = (
-    "qld_accumulate", "qld_amplitude", "dft_bin_baseline", "qld_lockin_ratio", "qld_lockin_bank",
+    "qld_accumulate", "qld_lockin_image", "qld_amplitude", "dft_bin_baseline", "qld_lockin_ratio", "qld_lockin_bank",
     "qld_window_bytes", "qld_window_create", "qld_window_update", "qld_window_reset",
     "qld_window_destroy", "qld_window_info", "qld_window_save", "qld_window_load",
     "qld_fwindow_bytes", "qld_fwindow_create", "qld_fwindow_update", "qld_fwindow_reset", "qld_fwindow_info",
@@ -79,6 +79,7 @@ def _sig(name, res, *args):
 
 
 _sig("qld_accumulate", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp, _vp, _vp)
+_sig("qld_lockin_image", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("qld_amplitude", ctypes.c_int, _vp, _vp, _i64, _vp, _vp)
 _sig("dft_bin_baseline", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp)
 _sig("qld_window_bytes", _sz, _dp, _i32)
@@ -222,6 +223,15 @@ def accumulate(frames, I, Q, phase0=0, bits=None, frame_sum=None, frame_sat=None
                                _ptr(frame_sum), _ptr(frame_sat), _stream(stream)), "qld_accumulate")
 
 
+def lockin_image(frames, I, Q, amp=None, phase0=0, bits=None, frame_sum=None, frame_sat=None, stream=None):
+    """One image of a [T][H][W] device stack in one pass: I, Q (and amp, the
+    statistics) overwritten."""
+    d = frame_desc(frames, bits)
+    n = frames.shape[0] if frames.dim() == 3 else 1
+    _check(_lib.qld_lockin_image(_ptr(frames), ctypes.byref(d), int(n), int(phase0), _ptr(I), _ptr(Q), _ptr(amp),
+                                 _ptr(frame_sum), _ptr(frame_sat), _stream(stream)), "qld_lockin_image")
+
+
 def amplitude(I, Q, amp, stream=None):
     _check(_lib.qld_amplitude(_ptr(I), _ptr(Q), int(I.numel()), _ptr(amp), _stream(stream)), "qld_amplitude")
 
@@ -256,16 +266,15 @@ def dft_bin_baseline(frames, k, re, im, bits=None, stream=None):
 
 
 def lockin(frames, phase0=0, bits=None, stats=False, stream=None):
-    """Convenience: fresh I, Q, amplitude (and per-frame stats) of a device stack."""
+    """Convenience: fresh I, Q, amplitude (and per-frame stats) of a device stack (qld_lockin_image)."""
     T, H, W = frames.shape
     dev = frames.device
-    I = torch.zeros((H, W), dtype=torch.int32, device=dev)
-    Q = torch.zeros((H, W), dtype=torch.int32, device=dev)
-    fsum = torch.zeros(T, dtype=torch.int64, device=dev) if stats else None
-    fsat = torch.zeros(T, dtype=torch.int32, device=dev) if stats else None
-    accumulate(frames, I, Q, phase0, bits, fsum, fsat, stream)
+    I = torch.empty((H, W), dtype=torch.int32, device=dev)
+    Q = torch.empty((H, W), dtype=torch.int32, device=dev)
+    fsum = torch.empty(T, dtype=torch.int64, device=dev) if stats else None
+    fsat = torch.empty(T, dtype=torch.int32, device=dev) if stats else None
     amp = torch.empty((H, W), dtype=torch.float32, device=dev)
-    amplitude(I, Q, amp, stream)
+    lockin_image(frames, I, Q, amp, phase0, bits, fsum, fsat, stream)
     return (I, Q, amp, fsum, fsat) if stats else (I, Q, amp)
 
 

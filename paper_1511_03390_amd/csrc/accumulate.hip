@@ -65,7 +65,31 @@ struct AccumArgs {
     int32_t *Q;
     uint32_t *part_sum;    // [waves][n_frames]
     uint32_t *part_sat;
+    // One-shot image (qld_lockin_image): I/Q written, not added (single pass
+    // over the frames only), the amplitude written from the final sums, and
+    // the frame statistics cleared by work-group 0 before the reduction adds.
+    int32_t overwrite;
+    float *amp;
+    uint64_t *clear_sum;
+    uint32_t *clear_sat;
+    int32_t clear_n;
 };
+
+// R = (I^2 + Q^2)^(1/2): the sum of squares exact in uint64 (|I|, |Q| < 2^31),
+// one double square root, rounded to float.
+__device__ __forceinline__ float amp_exact(int32_t i, int32_t q) {
+    const int64_t a = i, b = q;
+    return (float)__builtin_sqrt((double)((uint64_t)(a * a) + (uint64_t)(b * b)));
+}
+
+// Work-group 0 of the launch clears the statistics a one-shot image reports.
+__device__ __forceinline__ void clear_stats_once(const AccumArgs &a) {
+    if (a.clear_n == 0 || blockIdx.x != 0) return;
+    for (int t = threadIdx.x; t < a.clear_n; t += blockDim.x) {
+        if (a.clear_sum) a.clear_sum[t] = 0;
+        if (a.clear_sat) a.clear_sat[t] = 0;
+    }
+}
 
 // Sum of a 32-bit value over the 64 lanes of the wave, valid in lane 63:
 // inclusive shifts inside each 16-lane row, then row broadcasts 15 and 31.
@@ -421,8 +445,10 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
             atomicAdd(Ip + k, oi);
             atomicAdd(Qp + k, oq);
         } else {
-            Ip[k] += oi;
-            Qp[k] += oq;
+            const int32_t ni = a.overwrite ? oi : Ip[k] + oi, nq = a.overwrite ? oq : Qp[k] + oq;
+            Ip[k] = ni;
+            Qp[k] = nq;
+            if (a.amp) a.amp[y * a.W + x0 + k] = amp_exact(ni, nq);
         }
     }
 }
@@ -438,6 +464,7 @@ __device__ __forceinline__ void tile_and_split(const AccumArgs &a, int &tile, in
 
 template <int ELEM, bool STATS, bool PACKED>
 __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
+    clear_stats_once(a);
     int tile, split;
     tile_and_split(a, tile, split);
     if (tile >= a.n_tiles) return;
@@ -456,6 +483,7 @@ __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
 // ---------------------------------------------------------------------------
 template <int ELEM, bool STATS>
 __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
+    clear_stats_once(a);
     int tile, split;
     tile_and_split(a, tile, split);
     if (tile >= a.n_tiles) return;
@@ -515,8 +543,11 @@ __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
         atomicAdd(a.I + y * a.W + x, oi);
         atomicAdd(a.Q + y * a.W + x, oq);
     } else {
-        a.I[y * a.W + x] += oi;
-        a.Q[y * a.W + x] += oq;
+        const int64_t o = y * a.W + x;
+        const int32_t ni = a.overwrite ? oi : a.I[o] + oi, nq = a.overwrite ? oq : a.Q[o] + oq;
+        a.I[o] = ni;
+        a.Q[o] = nq;
+        if (a.amp) a.amp[o] = amp_exact(ni, nq);
     }
 }
 
@@ -549,11 +580,7 @@ __global__ __launch_bounds__(256) void qld_amplitude_kernel(const int32_t *__res
                                                             const int32_t *__restrict__ Q, int64_t n,
                                                             float *__restrict__ amp) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int64_t a = I[i], q = Q[i];
-        const uint64_t ss = (uint64_t)(a * a) + (uint64_t)(q * q);   // exact: |I|, |Q| < 2^31
-        amp[i] = (float)__builtin_sqrt((double)ss);
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) amp[i] = amp_exact(I[i], Q[i]);
 }
 
 template <int ELEM, bool STATS>
@@ -589,10 +616,20 @@ int32_t choose_split(int64_t n_tiles, int32_t n_frames) {
 
 using namespace qld;
 
-extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d, int32_t n_frames,
-                                     int32_t phase0, int32_t *I, int32_t *Q, uint64_t *frame_sum,
-                                     uint32_t *frame_sat, qld_hip_stream stream) {
-    clear_error();
+namespace {
+
+__global__ void zero_iq_kernel(int32_t *I, int32_t *Q, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) I[i] = Q[i] = 0;
+}
+
+// overwrite = false: (I, Q) += the stack's sums, frame statistics added.
+// overwrite = true: one image: I/Q and the statistics replaced, amp (may be
+// NULL) written.  Without a frame split all of it happens in the accumulation
+// kernel's epilogue; with one, I/Q are cleared first and the amplitude follows.
+qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t phase0,
+                           int32_t *I, int32_t *Q, float *amp, uint64_t *frame_sum, uint32_t *frame_sat,
+                           bool overwrite, qld_hip_stream stream) {
     int eb = 0;
     QLD_TRY(check_desc(d, &eb));
     if (n_frames < 0) {
@@ -630,6 +667,11 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
     a.top = (uint32_t)top;
     a.I = I;
     a.Q = Q;
+    a.overwrite = overwrite ? 1 : 0;
+    if (overwrite) {
+        a.clear_sum = frame_sum;
+        a.clear_sat = frame_sat;
+    }
 
     AccumArgs av = a, as = a;
     const int64_t vt = vcols ? ceil_div((int64_t)(vcols / lw) * d->H, kBlock) : 0;
@@ -648,8 +690,14 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
     as.wave_base = (int32_t)(vt * kWavesPerBlock);
     av.n_split = choose_split(vt + st, n_frames);
     as.n_split = av.n_split;
-    if (av.n_split > 1) {
-        // Chunks accumulate with atomics; other callers' I/Q contents are kept (+=).
+    // With a frame split the chunks add with atomics (I/Q contents are kept:
+    // +=); a one-shot image clears them first and computes amp afterwards.
+    const bool split = av.n_split > 1;
+    if (!split) av.amp = as.amp = amp;
+    // Only the first kernel launched clears the statistics.
+    if (overwrite && (frame_sum || frame_sat)) {
+        if (vt > 0) av.clear_n = n_frames;
+        else as.clear_n = n_frames;
     }
 
     const bool stats = frame_sum || frame_sat;
@@ -672,6 +720,11 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
         return QLD_E_SHAPE;
     }
 
+    if (overwrite && split) {
+        hipLaunchKernelGGL(zero_iq_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(npx, 256), 4096)), dim3(256), 0, s,
+                           I, Q, npx);
+        QLD_TRY(check_hip(hipGetLastError(), "zero_iq_kernel launch"));
+    }
     hipEvent_t ev0, ev1;
     take_kernel_timer(&ev0, &ev1);
     if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
@@ -693,7 +746,32 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
                            n_frames, frame_sum, frame_sat);
         QLD_TRY(check_hip(hipGetLastError(), "qld_stats_reduce_kernel launch"));
     }
+    if (overwrite && split && amp) {
+        const int64_t blocks = std::min<int64_t>(ceil_div(npx, 256), 16ll * device_cu_count());
+        hipLaunchKernelGGL(qld_amplitude_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I, Q, npx, amp);
+        QLD_TRY(check_hip(hipGetLastError(), "qld_amplitude_kernel launch"));
+    }
     return QLD_OK;
+}
+
+}  // namespace
+
+extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d, int32_t n_frames,
+                                     int32_t phase0, int32_t *I, int32_t *Q, uint64_t *frame_sum,
+                                     uint32_t *frame_sat, qld_hip_stream stream) {
+    clear_error();
+    return accumulate_impl(frames, d, n_frames, phase0, I, Q, nullptr, frame_sum, frame_sat, false, stream);
+}
+
+extern "C" qld_status qld_lockin_image(const void *frames, const qld_frame_desc *d, int32_t n_frames,
+                                       int32_t phase0, int32_t *I, int32_t *Q, float *amp, uint64_t *frame_sum,
+                                       uint32_t *frame_sat, qld_hip_stream stream) {
+    clear_error();
+    if (n_frames < 1) {
+        set_error("qld_lockin_image needs n_frames >= 1 (got %d)", n_frames);
+        return QLD_E_SHAPE;
+    }
+    return accumulate_impl(frames, d, n_frames, phase0, I, Q, amp, frame_sum, frame_sat, true, stream);
 }
 
 extern "C" qld_status qld_amplitude(const int32_t *I, const int32_t *Q, int64_t n_pixels, float *amp,

@@ -116,6 +116,40 @@ def test_full_range_16bit_and_overflow_edge():
     assert e.value.status == qld.E_OVERFLOW
 
 
+@pytest.mark.parametrize("T,H,W,bits,phase0", [(64, 17, 40, 12, 1), (4096, 16, 16, 12, 0), (9, 5, 1003, 16, 3),
+                                               (1024, 64, 64, 12, 2)])
+def test_lockin_image_overwrites_and_matches_accumulate(T, H, W, bits, phase0):
+    """qld_lockin_image (one pass: I/Q, amplitude and statistics overwritten)
+    on garbage-filled outputs equals clearing them, qld_accumulate and
+    qld_amplitude, and the oracle; frame-split grids and row tails included."""
+    need_gpu()
+    rng = np.random.default_rng(T + H + W)
+    f = rng.integers(0, 1 << bits, size=(T, H, W)).astype(np.uint16)
+    f[:, ::7, ::3] = (1 << bits) - 1
+    dev = to_dev(f)
+    I = torch.full((H, W), 123456, dtype=torch.int32, device="cuda")
+    Q = torch.full_like(I, -98765)
+    amp = torch.full((H, W), 7.5, dtype=torch.float32, device="cuda")
+    fsum = torch.full((T,), 99, dtype=torch.int64, device="cuda")
+    fsat = torch.full((T,), 77, dtype=torch.int32, device="cuda")
+    qld.lockin_image(dev, I, Q, amp, phase0=phase0, bits=bits, frame_sum=fsum, frame_sat=fsat)
+    I2 = torch.zeros_like(I)
+    Q2 = torch.zeros_like(Q)
+    s2 = torch.zeros_like(fsum)
+    c2 = torch.zeros_like(fsat)
+    a2 = torch.empty_like(amp)
+    qld.accumulate(dev, I2, Q2, phase0, bits, s2, c2)
+    qld.amplitude(I2, Q2, a2)
+    torch.cuda.synchronize()
+    for x, y in ((I, I2), (Q, Q2), (amp, a2), (fsum, s2), (fsat, c2)):
+        assert torch.equal(x, y)
+    check_against_oracle(f, I.cpu().numpy(), Q.cpu().numpy(), amp.cpu().numpy(), fsum.cpu().numpy(),
+                         fsat.cpu().numpy(), phase0, bits)
+    with pytest.raises(qld.QldError) as e:
+        qld.lockin_image(dev[:0], I, Q, amp, bits=bits)
+    assert e.value.status == qld.E_SHAPE
+
+
 def test_amplitude_extremes():
     need_gpu()
     rng = np.random.default_rng(4)
