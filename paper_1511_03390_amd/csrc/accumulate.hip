@@ -20,10 +20,11 @@
 //     which stay in VGPRs across the whole frame loop;
 //   * when the image alone does not fill the GPU, the cycles are dealt
 //     round-robin to S work-groups per pixel tile (cycle c to split c mod S),
-//     so the whole grid still sweeps the stack as one front; their partials
-//     are combined with int32 atomics (exact, order-free).  The splits of one
-//     tile sit on the same XCD (work-group ids are dealt round-robin over the
-//     8 XCDs), so their atomics meet in one L2;
+//     so the whole grid still sweeps the stack as one front.  Each split
+//     stores its I/Q partial with plain coalesced stores and a small kernel
+//     adds the S partials of a pixel in split order (int32, exact).  Measured
+//     on MI355X: int32 atomics into I/Q from the splits cost 20-30% of the
+//     kernel's bandwidth at 256x256 and 512x512;
 //   * per-frame statistics: each lane's sum of its samples (v_dot2_u32_u16 /
 //     v_sad_u8) goes to LDS, one row per frame; every 64 frames lane j adds up
 //     row j, which transposes the cross-lane reduction into plain adds, and
@@ -63,6 +64,7 @@ struct AccumArgs {
     uint32_t top;          // 2^bits - 1
     int32_t *I;
     int32_t *Q;
+    int32_t *part_iq;      // n_split > 1: [n_split][2][H*W] I/Q partials, indexed like I/Q
     uint32_t *part_sum;    // [waves][n_frames]
     uint32_t *part_sat;
     // One-shot image (qld_lockin_image): I/Q written, not added (single pass
@@ -435,15 +437,16 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
     }
 
     if (!valid) return;
-    int32_t *Ip = a.I + y * a.W + x0;
-    int32_t *Qp = a.Q + y * a.W + x0;
+    const int64_t npx = (int64_t)a.H * a.W;
+    int32_t *Ip = a.n_split > 1 ? a.part_iq + 2 * npx * split + y * a.W + x0 : a.I + y * a.W + x0;
+    int32_t *Qp = a.n_split > 1 ? Ip + npx : a.Q + y * a.W + x0;
 #pragma unroll
     for (int k = 0; k < kPx; ++k) {
         int32_t oi, oq;
         rotate_iq(a.rot, acc.I[k], acc.Q[k], oi, oq);
         if (a.n_split > 1) {
-            atomicAdd(Ip + k, oi);
-            atomicAdd(Qp + k, oq);
+            Ip[k] = oi;
+            Qp[k] = oq;
         } else {
             const int32_t ni = a.overwrite ? oi : Ip[k] + oi, nq = a.overwrite ? oq : Qp[k] + oq;
             Ip[k] = ni;
@@ -540,8 +543,10 @@ __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
     int32_t oi, oq;
     rotate_iq(a.rot, I, Q, oi, oq);
     if (a.n_split > 1) {
-        atomicAdd(a.I + y * a.W + x, oi);
-        atomicAdd(a.Q + y * a.W + x, oq);
+        const int64_t npx = (int64_t)a.H * a.W;
+        int32_t *Ip = a.part_iq + 2 * npx * split + y * a.W + x;
+        Ip[0] = oi;
+        Ip[npx] = oq;
     } else {
         const int64_t o = y * a.W + x;
         const int32_t ni = a.overwrite ? oi : a.I[o] + oi, nq = a.overwrite ? oq : a.Q[o] + oq;
@@ -574,6 +579,29 @@ __global__ __launch_bounds__(256) void qld_stats_reduce_kernel(const uint32_t *p
     }
     if (frame_sum) atomicAdd(reinterpret_cast<unsigned long long *>(frame_sum + t), (unsigned long long)s);
     if (frame_sat) atomicAdd(frame_sat + t, c);
+}
+
+// Frame-split images: per pixel, the S split partials added in split order,
+// then I/Q replaced (overwrite) or added to, and the amplitude written when
+// amp is non-NULL.  part: [S][2][npx].
+__global__ __launch_bounds__(256) void qld_iq_reduce_kernel(const int32_t *__restrict__ part, int32_t S, int64_t npx,
+                                                            int32_t overwrite, int32_t *__restrict__ I,
+                                                            int32_t *__restrict__ Q, float *__restrict__ amp) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
+        int32_t si = 0, sq = 0;
+        for (int32_t k = 0; k < S; ++k) {
+            si += part[2 * npx * k + p];
+            sq += part[2 * npx * k + npx + p];
+        }
+        if (!overwrite) {
+            si += I[p];
+            sq += Q[p];
+        }
+        I[p] = si;
+        Q[p] = sq;
+        if (amp) amp[p] = amp_exact(si, sq);
+    }
 }
 
 __global__ __launch_bounds__(256) void qld_amplitude_kernel(const int32_t *__restrict__ I,
@@ -618,15 +646,11 @@ using namespace qld;
 
 namespace {
 
-__global__ void zero_iq_kernel(int32_t *I, int32_t *Q, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) I[i] = Q[i] = 0;
-}
-
 // overwrite = false: (I, Q) += the stack's sums, frame statistics added.
 // overwrite = true: one image: I/Q and the statistics replaced, amp (may be
 // NULL) written.  Without a frame split all of it happens in the accumulation
-// kernel's epilogue; with one, I/Q are cleared first and the amplitude follows.
+// kernel's epilogue; with one, qld_iq_reduce_kernel adds the splits' partials
+// into I/Q (or replaces them) and writes the amplitude.
 qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t phase0,
                            int32_t *I, int32_t *Q, float *amp, uint64_t *frame_sum, uint32_t *frame_sat,
                            bool overwrite, qld_hip_stream stream) {
@@ -690,8 +714,9 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     as.wave_base = (int32_t)(vt * kWavesPerBlock);
     av.n_split = choose_split(vt + st, n_frames);
     as.n_split = av.n_split;
-    // With a frame split the chunks add with atomics (I/Q contents are kept:
-    // +=); a one-shot image clears them first and computes amp afterwards.
+    // With a frame split the splits store I/Q partials and
+    // qld_iq_reduce_kernel adds them (and writes amp); without one the
+    // accumulation kernel's epilogue does both.
     const bool split = av.n_split > 1;
     if (!split) av.amp = as.amp = amp;
     // Only the first kernel launched clears the statistics.
@@ -702,14 +727,17 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
 
     const bool stats = frame_sum || frame_sat;
     const int64_t n_waves = (vt + st) * kWavesPerBlock;
-    if (stats) {
-        size_t need = sizeof(uint32_t) * 2 * (size_t)n_waves * (size_t)n_frames;
-        void *ws = stream_workspace(s, need);
+    const size_t stats_b = stats ? ((sizeof(uint32_t) * 2 * (size_t)n_waves * (size_t)n_frames + 255) / 256) * 256 : 0;
+    const size_t iq_b = split ? sizeof(int32_t) * 2 * (size_t)av.n_split * (size_t)npx : 0;
+    if (stats_b + iq_b > 0) {
+        char *ws = static_cast<char *>(stream_workspace(s, stats_b + iq_b));
         if (!ws) return QLD_E_NOMEM;
-        uint32_t *ps = static_cast<uint32_t *>(ws);
-        uint32_t *pc = ps + (size_t)n_waves * n_frames;
-        av.part_sum = as.part_sum = ps;
-        av.part_sat = as.part_sat = pc;
+        if (stats) {
+            uint32_t *ps = reinterpret_cast<uint32_t *>(ws);
+            av.part_sum = as.part_sum = ps;
+            av.part_sat = as.part_sat = ps + (size_t)n_waves * n_frames;
+        }
+        if (split) av.part_iq = as.part_iq = reinterpret_cast<int32_t *>(ws + stats_b);
     }
     // 16-bit partial sums hold at least two cycles for data of up to 14 bits.
     const bool packed = eb == 1 || top <= 16383;
@@ -720,11 +748,6 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
         return QLD_E_SHAPE;
     }
 
-    if (overwrite && split) {
-        hipLaunchKernelGGL(zero_iq_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(npx, 256), 4096)), dim3(256), 0, s,
-                           I, Q, npx);
-        QLD_TRY(check_hip(hipGetLastError(), "zero_iq_kernel launch"));
-    }
     hipEvent_t ev0, ev1;
     take_kernel_timer(&ev0, &ev1);
     if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
@@ -746,10 +769,11 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
                            n_frames, frame_sum, frame_sat);
         QLD_TRY(check_hip(hipGetLastError(), "qld_stats_reduce_kernel launch"));
     }
-    if (overwrite && split && amp) {
+    if (split) {
         const int64_t blocks = std::min<int64_t>(ceil_div(npx, 256), 16ll * device_cu_count());
-        hipLaunchKernelGGL(qld_amplitude_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I, Q, npx, amp);
-        QLD_TRY(check_hip(hipGetLastError(), "qld_amplitude_kernel launch"));
+        hipLaunchKernelGGL(qld_iq_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, av.part_iq, av.n_split, npx,
+                           overwrite ? 1 : 0, I, Q, overwrite ? amp : nullptr);
+        QLD_TRY(check_hip(hipGetLastError(), "qld_iq_reduce_kernel launch"));
     }
     return QLD_OK;
 }
