@@ -24,6 +24,12 @@
  *     Frame t is sampled at lock-in phase (phase0 + t) mod 4.
  *   - The caller owns every buffer it passes; libqld owns the handles it
  *     creates (qld_window, qld_server) and the device memory behind them.
+ *   - Batch calls that need scratch memory (per-wave frame statistics, the
+ *     I/Q partials of a frame-split grid, twiddle and reference tables) take
+ *     it from a device workspace that libqld keeps per (device, stream) and
+ *     grows on demand (hipMalloc; a grow first synchronises that stream).
+ *     Calls on one stream therefore run in order over one workspace; calls on
+ *     different streams never share it.  It lives until the process ends.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the legacy default
  *     stream) and is asynchronous: outputs are valid once the stream reaches
  *     the call.  Argument errors are detected synchronously, before anything
@@ -110,7 +116,7 @@ qld_status qld_amplitude(const int32_t *I, const int32_t *Q, int64_t n_pixels, f
                          qld_hip_stream stream);
 
 /*
- * qld_lockin_image -- one image from a stack in a single pass (a1-a4 fused):
+ * qld_lockin_image -- one image from a stack in a single pass over it:
  * I, Q = the stack's quadrature sums (overwritten, not added), amp =
  * (I^2 + Q^2)^(1/2) as qld_amplitude computes it (may be NULL), frame_sum /
  * frame_sat the per-frame statistics (each may be NULL; overwritten).  The
