@@ -6,7 +6,9 @@ Workload (one step = one pass of the batch path over one stack already in HBM):
 seeded diffuse scene -- Poisson background ~2000 counts with a linear +-50
 ambient drift and a weak modulated mask of 5 rectangles.  A step is one
 qld_lockin_image call: I/Q, the amplitude image and the per-frame sum /
-saturation count of the stack, in one pass over the frames.
+saturation count of the stack, in one pass over the frames.  The stack is
+laid out with the frame stride qld_frame_stride_hint gives (a 256-byte gap
+after each 2 MiB frame; --dense for frame stride H*W).
 
 Printed: one JSON line with the pixel-frames/s of the step, the roofline of
 the dominant kernel (qld_accum_kernel, timed alone with HIP events on its
@@ -532,6 +534,8 @@ def main():
     ap.add_argument("--no-learned-serving", action="store_true")
     ap.add_argument("--serving-train-steps", type=int, default=300)
     ap.add_argument("--serving-cycles", type=int, default=160)
+    ap.add_argument("--dense", action="store_true",
+                    help="lay the stack out with frame stride H*W instead of qld_frame_stride_hint")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -545,8 +549,9 @@ def main():
     import scenes
 
     torch.cuda.set_device(0)
-    log("generating the 1024x1024x1024 uint16 stack on the GPU")
-    st = scenes.diffuse_scene_u16(device="cuda")
+    fstride = H * W if args.dense else qld.frame_stride_hint(H, W)
+    log("generating the 1024x1024x1024 uint16 stack on the GPU (frame stride %d elements)" % fstride)
+    st = scenes.diffuse_scene_u16(device="cuda", frame_stride=fstride)
     frames = st.frames
     torch.cuda.synchronize()
 
@@ -624,7 +629,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "batch QLD, 1024x1024 uint16 (12-bit) frames, 1024 frames (M=256 cycles), "
                                "diffuse Poisson scene with drift and 5-rectangle modulated mask",
-                   "H": H, "W": W, "frames": T, "bits": 12, "stats": True, "parallelism": "single GPU"},
+                   "H": H, "W": W, "frames": T, "bits": 12, "stats": True, "frame_stride": fstride,
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "dft_baseline": dft,

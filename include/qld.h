@@ -84,6 +84,21 @@ typedef struct {
 /* ------------------------------------------------------------------------ */
 
 /*
+ * qld_frame_stride_hint -- host-side helper: the frame stride (in ELEMENTS)
+ * to allocate a [T][H][row_pitch] stack with, for frames of H rows of
+ * row_pitch elements of `dtype`.  It is the frame size rounded up to 256
+ * bytes, plus 256 bytes when that size is a multiple of 64 KiB: with such
+ * sizes (1024 x 1024 uint16 frames are 2 MiB) the same pixel of consecutive
+ * frames falls on the same HBM bank, and the batch kernels, which read four
+ * consecutive frames of a pixel at once, measured 2-5% slower on MI355X.
+ * Any stride >= the frame size works with every call; this one is faster.
+ * Returns 0 for invalid arguments (H or W < 0, row_pitch < W, unknown dtype)
+ * and for empty frames (H = 0 or row_pitch = 0), which need no stride.
+ * Touches no device.
+ */
+int64_t qld_frame_stride_hint(int32_t H, int32_t W, int64_t row_pitch, qld_dtype dtype);
+
+/*
  * qld_accumulate -- quadrature sums of a frame stack (Methods, R(j,k);
  * Supplementary, each frame multiplied by sin and cos and accumulated into
  * two 2-D arrays).

@@ -159,6 +159,17 @@ qld_status qld_time_next_kernel(void *start_event, void *stop_event) {
     return QLD_OK;
 }
 
+int64_t qld_frame_stride_hint(int32_t H, int32_t W, int64_t row_pitch, qld_dtype dtype) {
+    const int64_t eb = dtype == QLD_U16 ? 2 : (dtype == QLD_U8 ? 1 : 0);
+    if (eb == 0 || H < 0 || W < 0 || row_pitch < W) return 0;
+    int64_t bytes = (int64_t)H * row_pitch * eb;
+    bytes = (bytes + 255) / 256 * 256;
+    // Frames whose size is a multiple of 64 KiB put the same pixel of
+    // consecutive frames on the same HBM bank; a 256-byte gap moves them apart.
+    if (bytes > 0 && bytes % 65536 == 0) bytes += 256;
+    return bytes / eb;
+}
+
 const char *qld_version(void) {
     return "libqld 0.1 (HIP, gfx950, " __VERSION__ ")";
 }

@@ -118,13 +118,15 @@ def diffuse_scene_params(seed=None, H=1024, W=1024, T=1024, background=2000.0,
                 ballistic=ballistic)
 
 
-def diffuse_scene_u16(seed=None, H=1024, W=1024, T=1024, device="cpu", chunk=64, **kw):
+def diffuse_scene_u16(seed=None, H=1024, W=1024, T=1024, device="cpu", chunk=64, frame_stride=None, **kw):
     """Poisson frames of the diffuse scene as a torch int16 tensor holding uint16 bits.
 
     Drawn with ``torch.poisson`` from a seeded ``torch.Generator`` on ``device``
     (the same seed on CPU and GPU gives different, equally valid stacks), then
     clipped to the 12-bit range.  Generated ``chunk`` frames at a time to bound
-    memory.  Returns a :class:`Stack` whose ``frames`` is a torch tensor.
+    memory.  ``frame_stride`` (elements, >= H*W) lays the frames out with gaps
+    between them (a [T][H][W] view of a larger buffer); the values do not
+    depend on it.  Returns a :class:`Stack` whose ``frames`` is a torch tensor.
     """
     import torch
 
@@ -133,7 +135,13 @@ def diffuse_scene_u16(seed=None, H=1024, W=1024, T=1024, device="cpu", chunk=64,
     g = torch.Generator(device=dev)
     g.manual_seed(int(p["seed"]))
     mask = torch.from_numpy(p["mask"].astype(np.float32)).to(dev)
-    out = torch.empty((T, H, W), dtype=torch.int16, device=dev)
+    fs = H * W if frame_stride is None else int(frame_stride)
+    if fs < H * W:
+        raise ValueError("frame_stride %d < H*W = %d" % (fs, H * W))
+    if fs == H * W:
+        out = torch.empty((T, H, W), dtype=torch.int16, device=dev)
+    else:
+        out = torch.zeros(T * fs, dtype=torch.int16, device=dev).as_strided((T, H, W), (fs, W, 1))
     maxv = float((1 << p["bits"]) - 1)
     for t0 in range(0, T, chunk):
         t1 = min(T, t0 + chunk)

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "qld.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+char\s*\*|qld_status|size_t|int32_t)\s*(\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+char\s*\*|qld_status|size_t|int32_t|int64_t)\s*(\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -59,6 +59,25 @@ def test_accumulate_argument_errors():
     assert acc(desc(bits=16), n=4 * 32769) == q.E_OVERFLOW
     assert acc(desc(bits=12), n=4 * 524417) == q.E_OVERFLOW
     assert b"overflow" in q.lib.qld_last_error()
+
+
+def test_frame_stride_hint():
+    # 1024 x 1024 uint16 frames are 2 MiB, a multiple of 64 KiB: a 256-byte gap.
+    assert q.frame_stride_hint(1024, 1024) == 1024 * 1024 + 128
+    assert q.frame_stride_hint(256, 256) == 256 * 256 + 128
+    assert q.frame_stride_hint(1024, 1024, dtype=q.U8) == 1024 * 1024 + 256
+    # Other sizes: rounded up to 256 bytes only.
+    assert q.frame_stride_hint(2160, 2160) == 2160 * 2160          # 9 331 200 B, a multiple of 256
+    assert q.frame_stride_hint(7, 13) == 128                        # 182 B -> 256 B
+    assert q.frame_stride_hint(7, 13, row_pitch=16, dtype=q.U8) == 256
+    assert q.frame_stride_hint(0, 5) == 0                           # empty frames need no stride
+    for H, W, rp, dt in ((1024, 1024, 1024, q.U16), (480, 640, 704, q.U16), (33, 7, 7, q.U8)):
+        fs = q.frame_stride_hint(H, W, row_pitch=rp, dtype=dt)
+        eb = 2 if dt == q.U16 else 1
+        assert fs >= H * rp and (fs * eb) % 256 == 0 and (fs * eb) % 65536 != 0
+    assert q.frame_stride_hint(-1, 4) == 0
+    assert q.frame_stride_hint(4, 4, row_pitch=3) == 0
+    assert q.frame_stride_hint(4, 4, dtype=7) == 0
 
 
 def test_empty_inputs_are_noops():

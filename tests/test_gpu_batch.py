@@ -150,6 +150,33 @@ def test_lockin_image_overwrites_and_matches_accumulate(T, H, W, bits, phase0):
     assert e.value.status == qld.E_SHAPE
 
 
+def test_hinted_frame_stride_gives_the_same_image():
+    # A stack laid out with qld_frame_stride_hint (gaps between frames) gives
+    # the same I/Q, amplitude and statistics as the dense layout.
+    need_gpu()
+    T, H, W = 64, 256, 256
+    fs = qld.frame_stride_hint(H, W)
+    assert fs > H * W
+    rng = np.random.default_rng(11)
+    f = rng.integers(0, 4096, size=(T, H, W)).astype(np.uint16)
+    dense = to_dev(f)
+    padded = torch.full((T * fs,), -1, dtype=torch.int16, device="cuda").as_strided((T, H, W), (fs, W, 1))
+    padded.copy_(dense)
+    outs = []
+    for stack in (dense, padded):
+        I = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        Q = torch.empty_like(I)
+        amp = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        fsum = torch.empty(T, dtype=torch.int64, device="cuda")
+        fsat = torch.empty(T, dtype=torch.int32, device="cuda")
+        qld.lockin_image(stack, I, Q, amp, 1, 12, fsum, fsat)
+        outs.append([x.cpu() for x in (I, Q, amp, fsum, fsat)])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+    I, Q, amp, fsum, fsat = (x.numpy() for x in outs[1])
+    check_against_oracle(f, I, Q, amp, fsum, fsat, 1, 12)
+
+
 def test_amplitude_extremes():
     need_gpu()
     rng = np.random.default_rng(4)
