@@ -17,6 +17,13 @@
 //     chunks of 32 frames and shared by the work-group's four waves;
 //   * a wave owns 64 pixels (4 row blocks) x all 2F columns (F <= 32 per
 //     launch; larger banks are split into groups of 32 frequencies).
+// Frame operand, fast path (uint16, 16-byte aligned, W, row pitch and frame
+// stride multiples of 8): a wave loads its 64 pixels x 32 frames per chunk
+// with four 16-byte loads per lane (a 4 KiB tile), issued one chunk ahead,
+// converts them to float into a padded per-wave LDS tile and the MFMAs read
+// the A operand from there.  Otherwise each lane gathers its samples with
+// 2-byte loads.  Measured on MI355X: the gathers bound the kernel (with the
+// frame loads taken out it ran twice as fast).
 // The table is built per call in double from the exact integer angle and
 // rounded to float, like the single-frequency path.
 #include <vector>
@@ -116,6 +123,128 @@ __global__ __launch_bounds__(kBankBlock) void bank_kernel(const T *__restrict__ 
         }
 }
 
+constexpr int kXStride = 80;        // floats per staged frame row of a wave's tile (64 pixels + padding)
+
+typedef uint32_t u32x4b __attribute__((ext_vector_type(4)));
+typedef float f32x4s __attribute__((ext_vector_type(4)));
+
+template <int NCB>
+__global__ __launch_bounds__(kBankBlock) void bank_vec_kernel(const uint16_t *__restrict__ frames, int64_t row_pitch,
+                                                              int64_t frame_stride, int H, int W, int n_frames,
+                                                              const float *__restrict__ tab, int F,
+                                                              float *__restrict__ re, float *__restrict__ im) {
+    constexpr int NCOL = NCB * 16;
+    __shared__ __attribute__((aligned(16))) float tl[kTChunk][kTabStride];
+    __shared__ __attribute__((aligned(16))) float xa[kBankBlock / 64][kTChunk][kXStride];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
+    const int64_t npx = (int64_t)H * W;
+    const int64_t px0 = (int64_t)blockIdx.x * kBankBlock + wave * 64;
+    // Tile loads: lane (fr, c) reads pixels px0 + 8c .. +7 of frames fr, fr + 8, fr + 16, fr + 24 of
+    // the chunk.  W is a multiple of 8, so a group of 8 never crosses a row and is all in or all out.
+    const int c = lane & 7, fr = lane >> 3;
+    const int64_t pc = px0 + 8 * c;
+    const bool okc = pc < npx;
+    const int64_t offc = okc ? (pc / W) * row_pitch + pc % W : 0;
+    float(*tile)[kXStride] = xa[wave];
+
+    u32x4b v[4];
+    auto load_chunk = [&](int tc) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = tc + fr + 8 * i;
+            const bool ok = okc && f < n_frames;
+            const uint16_t *src = frames + (int64_t)(ok ? f : 0) * frame_stride + offc;
+            u32x4b d = __builtin_nontemporal_load(reinterpret_cast<const u32x4b *>(src));
+            v[i] = ok ? d : u32x4b{0u, 0u, 0u, 0u};
+        }
+    };
+    f32x4b acc[4][NCB];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = f32x4b{0.f, 0.f, 0.f, 0.f};
+
+    // The chunk's table rows, also fetched one chunk ahead: element t + 256 j of the chunk.
+    constexpr int kTabPer = kTChunk * NCOL / kBankBlock;
+    float tv[kTabPer];
+    auto load_tab = [&](int tc) {
+#pragma unroll
+        for (int j = 0; j < kTabPer; ++j) {
+            const int i = t + kBankBlock * j, tt = i / NCOL;
+            tv[j] = tc + tt < n_frames ? tab[(int64_t)(tc + tt) * NCOL + i % NCOL] : 0.f;
+        }
+    };
+
+    load_chunk(0);
+    load_tab(0);
+    for (int tc = 0; tc < n_frames; tc += kTChunk) {
+        __syncthreads();                                  // the previous chunk's readers are done
+#pragma unroll
+        for (int j = 0; j < kTabPer; ++j) {
+            const int i = t + kBankBlock * j;
+            tl[i / NCOL][i % NCOL] = tv[j];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f32x4s lo, hi;
+            lo[0] = (float)(v[i][0] & 0xffffu);
+            lo[1] = (float)(v[i][0] >> 16);
+            lo[2] = (float)(v[i][1] & 0xffffu);
+            lo[3] = (float)(v[i][1] >> 16);
+            hi[0] = (float)(v[i][2] & 0xffffu);
+            hi[1] = (float)(v[i][2] >> 16);
+            hi[2] = (float)(v[i][3] & 0xffffu);
+            hi[3] = (float)(v[i][3] >> 16);
+            *reinterpret_cast<f32x4s *>(&tile[fr + 8 * i][8 * c]) = lo;
+            *reinterpret_cast<f32x4s *>(&tile[fr + 8 * i][8 * c + 4]) = hi;
+        }
+        if (tc + kTChunk < n_frames) {                    // next chunk in flight during the MFMAs
+            load_chunk(tc + kTChunk);
+            load_tab(tc + kTChunk);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kTChunk; ks += 4) {
+            float a[4];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) a[pb] = tile[ks + kb][pb * 16 + m];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const float b = tl[ks + kb][cb * 16 + m];
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb)
+                    acc[pb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[pb], b, acc[pb][cb], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int n = cb * 16 + m, f = n >> 1;
+            if (f >= F) continue;
+            float *dst = (n & 1) ? im : re;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t p = px0 + pb * 16 + 4 * kb + i;
+                if (p < npx) dst[(int64_t)f * npx + p] = acc[pb][cb][i];
+            }
+        }
+}
+
+hipError_t launch_bank_vec(int ncb, const uint16_t *frames, int64_t rp, int64_t fs, int H, int W, int n,
+                           const float *tab, int F, float *re, float *im, hipStream_t s) {
+    const int64_t npx = (int64_t)H * W;
+    const dim3 grid((unsigned)ceil_div(npx, kBankBlock));
+    switch (ncb) {
+        case 1: hipLaunchKernelGGL((bank_vec_kernel<1>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab, F, re, im); break;
+        case 2: hipLaunchKernelGGL((bank_vec_kernel<2>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab, F, re, im); break;
+        case 3: hipLaunchKernelGGL((bank_vec_kernel<3>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab, F, re, im); break;
+        default: hipLaunchKernelGGL((bank_vec_kernel<4>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab, F, re, im); break;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_bank(int ncb, const T *frames, int64_t rp, int64_t fs, int H, int W, int n, const float *tab, int F,
                        float *re, float *im, hipStream_t s) {
@@ -160,6 +289,8 @@ extern "C" qld_status qld_lockin_bank(const void *frames, const qld_frame_desc *
         return QLD_E_SHAPE;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const bool vec = eb == 2 && reinterpret_cast<uintptr_t>(frames) % 16 == 0 && d->W % 8 == 0 &&
+                     d->row_pitch % 8 == 0 && d->frame_stride % 8 == 0;
     for (int32_t f0 = 0; f0 < n_freq; f0 += kMaxF) {
         const int F = std::min<int32_t>(kMaxF, n_freq - f0);
         const int ncb = (int)ceil_div(2 * F, 16);
@@ -178,7 +309,10 @@ extern "C" qld_status qld_lockin_bank(const void *frames, const qld_frame_desc *
         take_kernel_timer(&ev0, &ev1);
         if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
         hipError_t e;
-        if (eb == 2)
+        if (vec)
+            e = launch_bank_vec(ncb, static_cast<const uint16_t *>(frames), d->row_pitch, d->frame_stride, d->H,
+                                d->W, n_frames, tab, F, re + (int64_t)f0 * npx, im + (int64_t)f0 * npx, s);
+        else if (eb == 2)
             e = launch_bank(ncb, static_cast<const uint16_t *>(frames), d->row_pitch, d->frame_stride, d->H, d->W,
                             n_frames, tab, F, re + (int64_t)f0 * npx, im + (int64_t)f0 * npx, s);
         else

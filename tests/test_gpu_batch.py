@@ -277,7 +277,8 @@ def test_lockin_ratio_rejects_another_frequency():
 
 @pytest.mark.parametrize("T,H,W,F,q,t0,dt", [(64, 9, 40, 1, 64, 0, np.uint16), (100, 13, 37, 5, 100, 3, np.uint16),
                                               (77, 5, 130, 17, 20, 1, np.uint8), (256, 16, 64, 32, 256, 0, np.uint16),
-                                              (33, 3, 70, 40, 33, 7, np.uint16)])
+                                              (33, 3, 70, 40, 33, 7, np.uint16), (45, 7, 24, 33, 45, 2, np.uint16),
+                                              (70, 11, 48, 9, 35, 5, np.uint16)])
 def test_lockin_bank(T, H, W, F, q, t0, dt):
     """Bank of F lock-ins (fp32 matrix cores) against the oracle's lock-in at
     each frequency, within the float accumulation bound."""
@@ -286,7 +287,15 @@ def test_lockin_bank(T, H, W, F, q, t0, dt):
     bits = 12 if dt == np.uint16 else 8
     f = rng.integers(0, (1 << bits), size=(T, H, W)).astype(dt)
     ps = [int(v) for v in rng.integers(-q, 2 * q, size=F)]
-    re, im = qld.lockin_bank(to_dev(f), ps, q, t0=t0, bits=bits)
+    dev = to_dev(f)
+    if W == 48:
+        # Padded rows and frames (pitch 56, frame stride from the hint): the 16-byte tile path.
+        fs = qld.frame_stride_hint(H, W, row_pitch=56)
+        buf = torch.full((T * fs,), 0x5A5A, dtype=torch.int16, device="cuda")
+        view = buf.as_strided((T, H, W), (fs, 56, 1))
+        view.copy_(dev)
+        dev = view
+    re, im = qld.lockin_bank(dev, ps, q, t0=t0, bits=bits)
     torch.cuda.synchronize()
     X = oracle.lockin_bank(f, ps, q, t0)
     bound = dft_bound(f, T)[None]
