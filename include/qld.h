@@ -178,7 +178,14 @@ qld_status qld_lockin_ratio(const void *frames, const qld_frame_desc *d, int32_t
  * Methods, Fourier map as a series of lock-ins): for f < n_freq
  *     X_f = sum_{t < n} S_t exp(-2 pi i ((p_f (t0 + t)) mod q) / q) = I_f - i Q_f,
  * each equal to qld_lockin_ratio(p_f, q, t0), computed as one contraction on
- * the matrix cores in fp32 (same tolerance as the single-frequency path).
+ * the matrix cores, frequencies in groups of 32.  Arithmetic by path:
+ *   - uint16 stacks with a 16-byte aligned base and W, row pitch and frame
+ *     stride multiples of 8, groups of more than 8 frequencies: bf16 MFMA with
+ *     exact operand splitting (sample = (x & 0xff00) + (x & 0xff), twiddle =
+ *     3 bf16 terms of the float table value; 6 exact products per frame,
+ *     fp32 accumulation): error <= (6 N + 2) * 1.01 * 2^-24 * sum_t |S_t|;
+ *   - otherwise fp32 MFMA on the float table: error <= (N + 2) * 2^-24 *
+ *     sum_t |S_t|, the single-frequency path's bound.
  *   p_host  HOST int32 [n_freq], any integers (reduced mod q)
  *   re, im  device float [n_freq][H][W] (dense, overwritten)
  * QLD_E_INVAL for q < 1, t0 < 0 or a NULL p_host; QLD_E_SHAPE for n_frames < 1.

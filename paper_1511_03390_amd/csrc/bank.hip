@@ -127,6 +127,7 @@ constexpr int kXStride = 80;        // floats per staged frame row of a wave's t
 
 typedef uint32_t u32x4b __attribute__((ext_vector_type(4)));
 typedef float f32x4s __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8b __attribute__((ext_vector_type(8)));
 
 template <int NCB>
 __global__ __launch_bounds__(kBankBlock) void bank_vec_kernel(const uint16_t *__restrict__ frames, int64_t row_pitch,
@@ -232,6 +233,174 @@ __global__ __launch_bounds__(kBankBlock) void bank_vec_kernel(const uint16_t *__
         }
 }
 
+// ---------------------------------------------------------------------------
+// bf16 matrix-core path with exact operand splitting (uint16 fast path).
+//   * a sample x < 2^16 is x = xh + xl with xh = x & 0xff00, xl = x & 0xff:
+//     8 significant bits each, so both are exact in bf16;
+//   * a twiddle (the float table value Bf) is b1 + b2 + b3, b_i = bf16 of the
+//     remaining residual (round to nearest even): 24 significant bits in all;
+//   * products of bf16 values are exact in fp32, so every MFMA term xh b_i and
+//     xl b_i is exact; all six per frame are accumulated in fp32.
+// v_mfma_f32_16x16x32_bf16: A = 16 pixels x 32 frames (lane (m, kb) holds
+// pixel m, frames 8 kb .. 8 kb + 7), B = 32 frames x 16 columns; one chunk of
+// 32 frames is one k-step.  LDS rows are 32 frames + 8 padding (80 bytes).
+// ---------------------------------------------------------------------------
+constexpr int kBRow = 40;           // uint16 per LDS row: 32 frames + padding
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// tab3[chunk][part][ncol][32]: part i of the split of the float twiddle of frame 32 chunk + tt, column n.
+__global__ __launch_bounds__(256) void bank_table3_kernel(const int32_t *__restrict__ p, int32_t F, int32_t q,
+                                                          int32_t t0, int32_t T, int32_t ncol, int32_t n_chunks,
+                                                          uint16_t *__restrict__ tab3) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_chunks * 32 * ncol) return;
+    const int64_t t = i / ncol;
+    const int n = (int)(i % ncol), f = n >> 1;
+    float bf = 0.f;
+    if (f < F && t < T) {
+        const int64_t r = (((int64_t)p[f] * ((int64_t)t0 + t)) % q + q) % q;
+        double s, c;
+        sincospi(2.0 * (double)r / (double)q, &s, &c);
+        bf = (n & 1) ? (float)(-s) : (float)c;
+    }
+    const uint16_t b1 = bf16_rne(bf);
+    const float r1 = bf - bf16_val(b1);
+    const uint16_t b2 = bf16_rne(r1);
+    const uint16_t b3 = bf16_rne(r1 - bf16_val(b2));
+    const int64_t ch = t / 32, tt = t % 32;
+    uint16_t *dst = tab3 + ch * 3 * ncol * 32 + (int64_t)n * 32 + tt;
+    dst[0] = b1;
+    dst[(int64_t)ncol * 32] = b2;
+    dst[(int64_t)2 * ncol * 32] = b3;
+}
+
+template <int NCB>
+__global__ __launch_bounds__(kBankBlock) void bank_bf16_kernel(const uint16_t *__restrict__ frames, int64_t row_pitch,
+                                                               int64_t frame_stride, int H, int W, int n_frames,
+                                                               const uint16_t *__restrict__ tab3, int F,
+                                                               float *__restrict__ re, float *__restrict__ im) {
+    constexpr int NCOL = NCB * 16;
+    constexpr int kPieces = 3 * NCOL * 4;                    // 16-byte pieces of a chunk's table
+    constexpr int kPiecesPer = (kPieces + kBankBlock - 1) / kBankBlock;
+    __shared__ __attribute__((aligned(16))) uint16_t tb[3][NCOL][kBRow];
+    __shared__ __attribute__((aligned(16))) uint16_t xa[kBankBlock / 64][2][64][kBRow];   // [wave][xl, xh][px]
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
+    const int64_t npx = (int64_t)H * W;
+    const int64_t px0 = (int64_t)blockIdx.x * kBankBlock + wave * 64;
+    // Tile loads: lane (fr, c) reads pixels px0 + 8c .. +7 of frames 4 fr .. 4 fr + 3 of the chunk.
+    const int c = lane & 7, fr = lane >> 3;
+    const int64_t pc = px0 + 8 * c;
+    const bool okc = pc < npx;
+    const int64_t offc = okc ? (pc / W) * row_pitch + pc % W : 0;
+    const int n_chunks = (n_frames + kTChunk - 1) / kTChunk;
+
+    // The next chunk's frames and table are in flight while this one is multiplied
+    // (measured: two chunks ahead was 5% slower).
+    u32x4b v[4], tv[kPiecesPer];
+    auto load = [&](int ch) {
+        const int tc = ch * kTChunk;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = tc + 4 * fr + i;
+            const bool ok = okc && f < n_frames;
+            const uint16_t *src = frames + (int64_t)(ok ? f : 0) * frame_stride + offc;
+            u32x4b d = __builtin_nontemporal_load(reinterpret_cast<const u32x4b *>(src));
+            v[i] = ok ? d : u32x4b{0u, 0u, 0u, 0u};
+        }
+        const u32x4b *src = reinterpret_cast<const u32x4b *>(tab3 + (int64_t)ch * 3 * NCOL * 32);
+#pragma unroll
+        for (int j = 0; j < kPiecesPer; ++j) {
+            const int i = t + kBankBlock * j;
+            if (i < kPieces) tv[j] = src[i];
+        }
+    };
+    f32x4b acc[4][NCB];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = f32x4b{0.f, 0.f, 0.f, 0.f};
+
+    load(0);
+    for (int ch = 0; ch < n_chunks; ++ch) {
+        __syncthreads();                                  // the previous chunk's readers are done
+#pragma unroll
+        for (int j = 0; j < kPiecesPer; ++j) {
+            const int i = t + kBankBlock * j;
+            if (i < kPieces) {
+                const int part = i / (NCOL * 4), col = (i / 4) % NCOL, qq = i % 4;
+                *reinterpret_cast<u32x4b *>(&tb[part][col][8 * qq]) = tv[j];
+            }
+        }
+        // Pixel 8c + j of frames 4 fr .. 4 fr + 3: xl and xh as bf16, two frames per word.
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = j >> 1, sh = (j & 1) * 16;
+            uint32_t lo[4], hi[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                lo[i] = __float_as_uint((float)((v[i][k] >> sh) & 0xffu)) >> 16;
+                hi[i] = __float_as_uint((float)((v[i][k] >> sh) & 0xff00u)) >> 16;
+            }
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            const u32x2 wl = {lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16)};
+            const u32x2 wh = {hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16)};
+            *reinterpret_cast<u32x2 *>(&xa[wave][0][8 * c + j][4 * fr]) = wl;
+            *reinterpret_cast<u32x2 *>(&xa[wave][1][8 * c + j][4 * fr]) = wh;
+        }
+        if (ch + 1 < n_chunks) load(ch + 1);
+        __syncthreads();
+        bf16x8b ah[4], al[4];
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+            al[pb] = __builtin_bit_cast(bf16x8b, *reinterpret_cast<const u32x4b *>(&xa[wave][0][16 * pb + m][8 * kb]));
+            ah[pb] = __builtin_bit_cast(bf16x8b, *reinterpret_cast<const u32x4b *>(&xa[wave][1][16 * pb + m][8 * kb]));
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+            for (int bi = 0; bi < 3; ++bi) {
+                const bf16x8b b = __builtin_bit_cast(bf16x8b, *reinterpret_cast<const u32x4b *>(&tb[bi][16 * cb + m][8 * kb]));
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) {
+                    acc[pb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[pb], b, acc[pb][cb], 0, 0, 0);
+                    acc[pb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[pb], b, acc[pb][cb], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int n = cb * 16 + m, f = n >> 1;
+            if (f >= F) continue;
+            float *dst = (n & 1) ? im : re;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t p = px0 + pb * 16 + 4 * kb + i;
+                if (p < npx) dst[(int64_t)f * npx + p] = acc[pb][cb][i];
+            }
+        }
+}
+
+hipError_t launch_bank_bf16(int ncb, const uint16_t *frames, int64_t rp, int64_t fs, int H, int W, int n,
+                            const uint16_t *tab3, int F, float *re, float *im, hipStream_t s) {
+    const int64_t npx = (int64_t)H * W;
+    const dim3 grid((unsigned)ceil_div(npx, kBankBlock));
+    switch (ncb) {
+        case 1: hipLaunchKernelGGL((bank_bf16_kernel<1>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab3, F, re, im); break;
+        case 2: hipLaunchKernelGGL((bank_bf16_kernel<2>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab3, F, re, im); break;
+        case 3: hipLaunchKernelGGL((bank_bf16_kernel<3>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab3, F, re, im); break;
+        default: hipLaunchKernelGGL((bank_bf16_kernel<4>), grid, dim3(kBankBlock), 0, s, frames, rp, fs, H, W, n, tab3, F, re, im); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_bank_vec(int ncb, const uint16_t *frames, int64_t rp, int64_t fs, int H, int W, int n,
                            const float *tab, int F, float *re, float *im, hipStream_t s) {
     const int64_t npx = (int64_t)H * W;
@@ -295,21 +464,36 @@ extern "C" qld_status qld_lockin_bank(const void *frames, const qld_frame_desc *
         const int F = std::min<int32_t>(kMaxF, n_freq - f0);
         const int ncb = (int)ceil_div(2 * F, 16);
         const int ncol = ncb * 16;
-        const size_t tab_b = ((sizeof(float) * (size_t)n_frames * ncol + 255) / 256) * 256;
+        const int64_t n_chunks = ceil_div(n_frames, kTChunk);
+        // Groups of more than 8 frequencies take the bf16 path; at 8 or fewer the frame staging
+        // bounds both fast kernels and the fp32 one measured faster.
+        const bool bf16 = vec && F > 8;
+        // Float table [T][ncol], or the bf16 split table [chunk][3][ncol][32].
+        const size_t tab_raw = bf16 ? sizeof(uint16_t) * (size_t)n_chunks * 3 * ncol * kTChunk
+                                    : sizeof(float) * (size_t)n_frames * ncol;
+        const size_t tab_b = ((tab_raw + 255) / 256) * 256;
         char *ws = static_cast<char *>(stream_workspace(s, tab_b + 256));
         if (!ws) return QLD_E_NOMEM;
-        float *tab = reinterpret_cast<float *>(ws);
         int32_t *pd = reinterpret_cast<int32_t *>(ws + tab_b);
         QLD_TRY(check_hip(hipMemcpyAsync(pd, p_host + f0, sizeof(int32_t) * F, hipMemcpyHostToDevice, s),
                           "frequency upload"));
-        hipLaunchKernelGGL(bank_table_kernel, dim3((unsigned)ceil_div((int64_t)n_frames * ncol, 256)), dim3(256), 0, s,
-                           pd, F, q, t0, n_frames, ncol, tab);
-        QLD_TRY(check_hip(hipGetLastError(), "bank_table_kernel launch"));
+        float *tab = reinterpret_cast<float *>(ws);
+        uint16_t *tab3 = reinterpret_cast<uint16_t *>(ws);
+        if (bf16)
+            hipLaunchKernelGGL(bank_table3_kernel, dim3((unsigned)ceil_div(n_chunks * kTChunk * ncol, 256)), dim3(256),
+                               0, s, pd, F, q, t0, n_frames, ncol, (int32_t)n_chunks, tab3);
+        else
+            hipLaunchKernelGGL(bank_table_kernel, dim3((unsigned)ceil_div((int64_t)n_frames * ncol, 256)), dim3(256),
+                               0, s, pd, F, q, t0, n_frames, ncol, tab);
+        QLD_TRY(check_hip(hipGetLastError(), "bank table kernel launch"));
         hipEvent_t ev0, ev1;
         take_kernel_timer(&ev0, &ev1);
         if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
         hipError_t e;
-        if (vec)
+        if (bf16)
+            e = launch_bank_bf16(ncb, static_cast<const uint16_t *>(frames), d->row_pitch, d->frame_stride, d->H,
+                                 d->W, n_frames, tab3, F, re + (int64_t)f0 * npx, im + (int64_t)f0 * npx, s);
+        else if (vec)
             e = launch_bank_vec(ncb, static_cast<const uint16_t *>(frames), d->row_pitch, d->frame_stride, d->H,
                                 d->W, n_frames, tab, F, re + (int64_t)f0 * npx, im + (int64_t)f0 * npx, s);
         else if (eb == 2)
