@@ -303,10 +303,13 @@ def test_lockin_ratio_rejects_another_frequency():
 @pytest.mark.parametrize("T,H,W,F,q,t0,dt", [(64, 9, 40, 1, 64, 0, np.uint16), (100, 13, 37, 5, 100, 3, np.uint16),
                                               (77, 5, 130, 17, 20, 1, np.uint8), (256, 16, 64, 32, 256, 0, np.uint16),
                                               (33, 3, 70, 40, 33, 7, np.uint16), (45, 7, 24, 33, 45, 2, np.uint16),
-                                              (70, 11, 48, 9, 35, 5, np.uint16), (50, 6, 32, 20, 50, 1, np.uint16)])
+                                              (70, 11, 48, 9, 35, 5, np.uint16), (50, 6, 32, 20, 50, 1, np.uint16),
+                                              (1, 8, 64, 32, 97, 5, np.uint16), (2, 4, 40, 12, 13, 0, np.uint16)])
 def test_lockin_bank(T, H, W, F, q, t0, dt):
-    """Bank of F lock-ins (fp32 matrix cores) against the oracle's lock-in at
-    each frequency, within the float accumulation bound."""
+    """Bank of F lock-ins against the oracle's lock-in at each frequency, within
+    the bound of the path each group of 32 frequencies takes.  With one or two
+    frames the bf16 bound (6N + 2)·1.01·2^-24·x is far below what dropping a
+    twiddle's third bf16 term would cost (up to 2^-16 x)."""
     need_gpu()
     rng = np.random.default_rng(T * F + W)
     bits = 12 if dt == np.uint16 else 8
@@ -358,16 +361,31 @@ def test_lockin_bank_separates_four_sources():
 
 
 def test_full_size_diffuse_scene_sampled():
-    """1024 x 1024 uint16 (12-bit), 1024 frames: the benchmark's launch, sampled
-    pixels checked by the oracle one by one; statistics against torch's sums."""
+    """1024 x 1024 uint16 (12-bit), 1024 frames in the benchmark's layout (frame
+    stride from the hint) and launches (qld_lockin_image into uninitialised
+    outputs, the single-bin DFT, the 32-frequency bank at bins 240..271):
+    sampled pixels checked by the oracle one by one; statistics against
+    torch's sums."""
     need_gpu()
-    st = scenes.diffuse_scene_u16(device="cuda")
+    fs = qld.frame_stride_hint(1024, 1024)
+    st = scenes.diffuse_scene_u16(device="cuda", frame_stride=fs)
     frames = st.frames
-    say("full-size stack", tuple(frames.shape))
-    I, Q, amp, fsum, fsat = qld.lockin(frames, bits=12, stats=True)
+    assert frames.stride(0) == fs
+    say("full-size stack", tuple(frames.shape), "frame stride", fs)
+    I = torch.empty((1024, 1024), dtype=torch.int32, device="cuda")
+    Q = torch.empty_like(I)
+    amp = torch.empty((1024, 1024), dtype=torch.float32, device="cuda")
+    fsum = torch.empty(1024, dtype=torch.int64, device="cuda")
+    fsat = torch.empty(1024, dtype=torch.int32, device="cuda")
+    qld.lockin_image(frames, I, Q, amp, 0, 12, fsum, fsat)
     re = torch.empty((1024, 1024), dtype=torch.float32, device="cuda")
     im = torch.empty_like(re)
     qld.dft_bin_baseline(frames, 256, re, im, bits=12)
+    ps = list(range(240, 272))
+    bre = torch.empty((32, 1024, 1024), dtype=torch.float32, device="cuda")
+    bim = torch.empty_like(bre)
+    qld.lockin_bank(frames, ps, 1024, bre, bim, bits=12)
+    assert bank_fast_path(frames)
     torch.cuda.synchronize()
     rng = np.random.default_rng(77)
     ys = np.concatenate([[0, 1023, 511], rng.integers(0, 1024, 61)])
@@ -382,6 +400,13 @@ def test_full_size_diffuse_scene_sampled():
     bound = dft_bound(sub_h, 1024)
     assert (np.abs(re.cpu().numpy()[np.ix_(ys, xs)] - X.real) <= bound).all()
     assert (np.abs(im.cpu().numpy()[np.ix_(ys, xs)] - X.imag) <= bound).all()
+    XB = oracle.lockin_bank(sub_h, ps, 1024)                    # [32][64][64]
+    bb = bank_bound(sub_h, 1024, bank_bf16_freqs(32, True))
+    gre = bre.cpu().numpy()[:, ys][:, :, xs]
+    gim = bim.cpu().numpy()[:, ys][:, :, xs]
+    say("bank max err", np.abs(gre - XB.real).max(), "bound", bb.min())
+    assert (np.abs(gre - XB.real) <= bb).all() and (np.abs(gim - XB.imag) <= bb).all()
+    del bre, bim
     # Per-frame statistics of the whole stack against torch's own reductions.
     ref_sum = frames.to(torch.int64).sum(dim=(1, 2))
     ref_sat = (frames == 4095).sum(dim=(1, 2))
