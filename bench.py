@@ -102,6 +102,95 @@ def bench_dft(qld, torch, frames, steps, warmup):
     return elapsed, [t.ms() for t in timers]
 
 
+def bench_read_peak(qld, torch, frames, reps=5):
+    """Achievable read bandwidth on this device: qld_read_probe over the whole
+    storage of the benchmark stack (a plain streaming read)."""
+    flat = frames.as_strided((frames.shape[0] * frames.stride(0),), (1,))
+    qld.read_probe(flat)
+    timers = [qld.KernelTimer() for _ in range(reps)]
+    for t in timers:
+        t.arm()
+        qld.read_probe(flat)
+    torch.cuda.synchronize()
+    ms = sum(t.ms() for t in timers) / reps
+    nbytes = flat.numel() * flat.element_size()
+    return {"kernel": "read_probe_kernel (a contiguous range per work-group, eight 16-byte nontemporal loads per lane in flight)", "bytes": nbytes,
+            "ms": round(ms, 4), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def bench_small_batch(qld, torch, reps=200):
+    """The 64x64x64 uint8 disk scene (one small image): one qld_lockin_image
+    call per image, launch- and latency-bound (the stack is 256 KiB)."""
+    import scenes
+    st = scenes.disk_scene_u8()
+    dev = torch.from_numpy(st.frames).cuda()
+    t_, h_, w_ = dev.shape
+    I = torch.empty((h_, w_), dtype=torch.int32, device="cuda")
+    Q = torch.empty_like(I)
+    amp = torch.empty((h_, w_), dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        qld.lockin_image(dev, I, Q, amp, 0, 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        qld.lockin_image(dev, I, Q, amp, 0, 8)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) / reps * 1e6
+    timers = [qld.KernelTimer() for _ in range(20)]
+    for t in timers:
+        t.arm()
+        qld.lockin_image(dev, I, Q, amp, 0, 8)
+    torch.cuda.synchronize()
+    kus = sum(t.ms() for t in timers) / len(timers) * 1e3
+    return {"workload": "64x64 uint8, 64 frames (M=16), disk scene, I/Q + amplitude", "us_per_call": round(us, 2),
+            "kernel_us": round(kus, 2), "pxf_per_s": round(t_ * h_ * w_ / (us * 1e-6)),
+            "note": "launch-bound; the 256 KiB stack stays in cache"}
+
+
+def bench_paper_shape(qld, torch, steps=5):
+    """The paper's timing workload: 800 frames of 2160 x 2160 uint16 (12-bit
+    values here, uniform random), one image per call, in the hinted layout."""
+    Tp, Hp, Wp = 800, 2160, 2160
+    fs = qld.frame_stride_hint(Hp, Wp)
+    buf = torch.randint(0, 4096, (Tp * fs,), dtype=torch.int16, device="cuda")
+    st = buf.as_strided((Tp, Hp, Wp), (fs, Wp, 1))
+    I = torch.empty((Hp, Wp), dtype=torch.int32, device="cuda")
+    Q = torch.empty_like(I)
+    amp = torch.empty((Hp, Wp), dtype=torch.float32, device="cuda")
+    qld.lockin_image(st, I, Q, amp, 0, 12)
+    timers = [qld.KernelTimer() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in timers:
+        t.arm()
+        qld.lockin_image(st, I, Q, amp, 0, 12)
+    torch.cuda.synchronize()
+    call_ms = (time.perf_counter() - t0) / steps * 1e3
+    ms = sum(t.ms() for t in timers) / steps
+    nbytes = Hp * Wp * (Tp * 2 + 12)
+    del buf, st
+    torch.cuda.empty_cache()
+    return {"workload": "800 frames of 2160x2160 uint16 (12-bit, uniform random), qld_lockin_image",
+            "kernel_ms": round(ms, 4), "ms_per_call": round(call_ms, 4),
+            "pxf_per_s": round(Tp * Hp * Wp / (call_ms * 1e-3)),
+            "achieved_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "paper_context": {"gpu_ms": 20.0, "multi_cpu_s": 14.0, "single_cpu_s": 38.7,
+                              "hardware": "Quadro 2000 GPU; Xeon 4-core 3.4 GHz desktop; FP64; the GPU figure "
+                                          "implies ~373 GB/s of input on a ~42 GB/s board",
+                              "speedup_vs_paper_gpu": round(20.0 / call_ms, 1),
+                              "speedup_vs_paper_single_cpu": round(38.7e3 / call_ms)}}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(oracle, frames, target_s, qld_I, torch):
     """Time the oracle (OpenMP over rows, all host cores it is given) on the
     same stack: the first n frames if the whole stack takes longer than
@@ -132,9 +221,24 @@ def cpu_baseline(oracle, frames, target_s, qld_I, torch):
     torch.cuda.synchronize()
     agree = bool(np.array_equal(I.cpu().numpy(), oI) and np.array_equal(Q.cpu().numpy(), oQ))
     what = ("first %d of the %d frames" % (n, T)) if n < T else ("all %d frames, %d passes" % (T, reps))
+    # One thread, on a bounded sample of about 3 s.
+    t0 = time.perf_counter()
+    oracle.qld(probe, 0, n_threads=1)
+    r1 = probe.size / max(time.perf_counter() - t0, 1e-6)
+    n1 = int(min(T, max(4, (r1 * 3.0) // (H * W))))
+    n1 -= n1 % 4
+    s1 = frames[:n1].cpu().numpy().view(np.uint16)
+    t0 = time.perf_counter()
+    oracle.qld(s1, 0, n_threads=1)
+    d1 = time.perf_counter() - t0
     return {"value": sample.size * reps / dt, "unit": "pixel-frames/s", "cores": threads, "kind": "oracle",
             "sample": "%s (1024x1024 uint16), I/Q by the C oracle, %.1f s; "
-                      "GPU I/Q on the same frames identical: %s" % (what, dt, agree)}
+                      "GPU I/Q on the same frames identical: %s" % (what, dt, agree),
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(s1.size / d1), "unit": "pixel-frames/s",
+                              "sample": "first %d frames (1024x1024 uint16), %.1f s" % (n1, d1)},
+            "paper_cpu_context": {"single_core_pxf_per_s": 9.6e7, "four_core_pxf_per_s": 2.7e8,
+                                  "hardware": "Xeon 4-core 3.4 GHz (8 threads), FP64"}}
 
 
 def bench_streaming(qld, torch, seconds, fps, M=64):
@@ -576,6 +680,11 @@ def main():
             "algorithmic_bytes_per_launch": kern_bytes,
             "step_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1)}
 
+    log("read probe")
+    read_peak = bench_read_peak(qld, torch, frames)
+    roof["measured_read_peak_gbs"] = read_peak["gbs"]
+    roof["frac_of_measured_read_peak"] = round(achieved / read_peak["gbs"], 4)
+
     log("DFT baseline")
     d_el, d_ms = bench_dft(qld, torch, frames, max(5, args.steps // 2), 2)
     d_avg = sum(d_ms) / len(d_ms)
@@ -587,6 +696,8 @@ def main():
     bank = bench_bank(qld, torch, frames, d_avg)
     log("synthetic Fig. 1 analog")
     fig1 = bench_fig1(qld, torch)
+    log("small batch (64x64x64 uint8)")
+    small = bench_small_batch(qld, torch)
 
     calib = copy_calibration(torch) if args.copy_calibration else None
 
@@ -596,11 +707,14 @@ def main():
         log("CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
         cpu = cpu_baseline(oracle, frames, args.cpu_seconds, None, torch)
 
+    del frames
+    st = None
+    torch.cuda.empty_cache()
+    log("paper-shape run (800 x 2160 x 2160)")
+    paper_shape = bench_paper_shape(qld, torch)
+
     streaming = None
     if not args.no_streaming:
-        del frames
-        st = None
-        torch.cuda.empty_cache()
         log("streaming: 3 cameras at %.0f fps for %.0f s" % (args.stream_fps, args.stream_seconds))
         streaming = bench_streaming(qld, torch, args.stream_seconds, args.stream_fps)
 
@@ -644,6 +758,9 @@ def main():
         "frame_window": frame_window,
         "lockin_bank": bank,
         "fig1_analog": fig1,
+        "read_peak": read_peak,
+        "small_batch": small,
+        "paper_shape": paper_shape,
         "library": qld.version(),
     }
     if calib is not None:

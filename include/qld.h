@@ -506,6 +506,17 @@ const char *qld_last_error(void);
  * helper kernels (statistics reduction, twiddle table, chunk reduction,
  * input conversion, pooling).  Both NULL cancels. */
 qld_status qld_time_next_kernel(void *start_event, void *stop_event);
+/*
+ * qld_read_probe -- measurement helper, not part of the method: a plain
+ * streaming read of n_bytes of device memory at p (16-byte nontemporal loads),
+ * the yardstick for the HBM fraction the batch kernels reach on a given
+ * device.  *out (device uint64) = XOR of every 8-byte word of the buffer, so
+ * the read cannot be optimised away and its result can be checked.  Timed by
+ * qld_time_next_kernel like the batch calls.  QLD_E_ALIGN unless p is 16-byte
+ * aligned and n_bytes a multiple of 16; QLD_E_INVAL for a NULL out (or p with
+ * n_bytes > 0).
+ */
+qld_status qld_read_probe(const void *p, int64_t n_bytes, uint64_t *out, qld_hip_stream stream);
 /* Library build string (compiler, target). */
 const char *qld_version(void);
 

@@ -40,7 +40,7 @@ EXPORTS = (
     "qld_server_create", "qld_server_stream_bytes", "qld_stream_open", "qld_stream_state",
     "qld_stream_set_denoiser", "qld_stream_submit", "qld_stream_poll", "qld_stream_result_iq", "qld_server_drain",
     "qld_stream_close", "qld_server_destroy", "qld_server_stats",
-    "qld_status_str", "qld_last_error", "qld_version", "qld_time_next_kernel", "qld_frame_stride_hint",
+    "qld_status_str", "qld_last_error", "qld_version", "qld_time_next_kernel", "qld_frame_stride_hint", "qld_read_probe",
     "qld_gen_pairs", "qld_denoise_prepare", "qld_denoise_target", "qld_clean_amplitude",
     "qld_judge_nrmse", "qld_judge_cnr", "qld_denoiser_param_count", "qld_denoiser_create",
     "qld_denoiser_info", "qld_denoiser_destroy", "qld_denoiser_set_params", "qld_denoiser_get_params", "qld_denoiser_get_grads",
@@ -118,6 +118,7 @@ _sig("qld_last_error", ctypes.c_char_p)
 _sig("qld_version", ctypes.c_char_p)
 _sig("qld_time_next_kernel", ctypes.c_int, _vp, _vp)
 _sig("qld_frame_stride_hint", _i64, _i32, _i32, _i64, ctypes.c_int)
+_sig("qld_read_probe", ctypes.c_int, _vp, _i64, _vp, _vp)
 _fp = ctypes.POINTER(ctypes.c_float)
 _sig("qld_gen_pairs", ctypes.c_int, _vp, _vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_uint32, ctypes.c_uint64, _i32,
      _vp, _vp, _vp, _vp, _vp, _vp, _vp)
@@ -219,6 +220,15 @@ def frame_desc(frames: torch.Tensor, bits: int | None = None) -> FrameDesc:
 def frame_stride_hint(H, W, row_pitch=None, dtype=U16):
     """Frame stride (elements) to allocate an [T][H][row_pitch] stack with (qld_frame_stride_hint)."""
     return int(_lib.qld_frame_stride_hint(int(H), int(W), int(W if row_pitch is None else row_pitch), int(dtype)))
+
+
+def read_probe(buf, out=None, stream=None):
+    """XOR of every 8-byte word of a device tensor's bytes (a plain streaming read; qld_read_probe)."""
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=buf.device)
+    _check(_lib.qld_read_probe(_ptr(buf), int(buf.numel() * buf.element_size()), _ptr(out), _stream(stream)),
+           "qld_read_probe")
+    return out
 
 
 def accumulate(frames, I, Q, phase0=0, bits=None, frame_sum=None, frame_sat=None, stream=None):

@@ -80,6 +80,15 @@ def test_frame_stride_hint():
     assert q.frame_stride_hint(4, 4, dtype=7) == 0
 
 
+def test_read_probe_argument_errors():
+    out = ctypes.c_void_p(1 << 20)
+    assert q.lib.qld_read_probe(ctypes.c_void_p(1 << 20 | 8), 64, out, None) == q.E_ALIGN
+    assert q.lib.qld_read_probe(ctypes.c_void_p(1 << 20), 65, out, None) == q.E_ALIGN
+    assert q.lib.qld_read_probe(ctypes.c_void_p(1 << 20), -16, out, None) == q.E_ALIGN
+    assert q.lib.qld_read_probe(ctypes.c_void_p(1 << 20), 64, None, None) == q.E_INVAL
+    assert q.lib.qld_read_probe(None, 64, out, None) == q.E_INVAL
+
+
 def test_empty_inputs_are_noops():
     assert acc(desc(), n=0, frames=0, I=0, Q=0) == q.OK
     assert acc(desc(H=0), frames=0, I=0, Q=0) == q.OK

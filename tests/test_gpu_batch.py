@@ -177,6 +177,18 @@ def test_hinted_frame_stride_gives_the_same_image():
     check_against_oracle(f, I, Q, amp, fsum, fsat, 1, 12)
 
 
+def test_read_probe_xor_of_every_word():
+    need_gpu()
+    rng = np.random.default_rng(3)
+    for nbytes in (16, 4096 + 48, (3 << 20) + 16 * 7):
+        h = rng.integers(0, 256, size=nbytes, dtype=np.uint8)
+        dev = torch.from_numpy(h).cuda()
+        out = qld.read_probe(dev)
+        torch.cuda.synchronize()
+        ref = np.bitwise_xor.reduce(h.view(np.uint64))
+        assert int(out.cpu().numpy().view(np.uint64)[0]) == int(ref), nbytes
+
+
 def test_amplitude_extremes():
     need_gpu()
     rng = np.random.default_rng(4)
