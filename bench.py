@@ -692,6 +692,20 @@ def main():
            "pxf_per_s": round(pxf / (d_avg * 1e-3)), "achieved_gbs": round(kern_bytes / (d_avg * 1e-3) / 1e9, 1),
            "ms_per_call": round(d_el / max(5, args.steps // 2) * 1e3, 4)}
 
+    log("DFT baseline in double precision")
+    re64 = torch.empty((H, W), dtype=torch.float64, device="cuda")
+    im64 = torch.empty_like(re64)
+    qld.dft_bin_baseline_f64(frames, T // 4, re64, im64, bits=12)
+    t64 = [qld.KernelTimer() for _ in range(5)]
+    for tm in t64:
+        tm.arm()
+        qld.dft_bin_baseline_f64(frames, T // 4, re64, im64, bits=12)
+    torch.cuda.synchronize()
+    d64 = sum(tm.ms() for tm in t64) / len(t64)
+    dft["f64"] = {"kernel_ms_avg": round(d64, 4), "achieved_gbs": round((H * W * T * 2 + H * W * 16) / (d64 * 1e-3) / 1e9, 1),
+                  "note": "twiddles and multiply-adds in double, the paper's precision"}
+    del re64, im64
+
     log("lock-in bank")
     bank = bench_bank(qld, torch, frames, d_avg)
     log("synthetic Fig. 1 analog")

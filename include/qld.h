@@ -156,6 +156,18 @@ qld_status dft_bin_baseline(const void *frames, const qld_frame_desc *d, int32_t
                             int32_t k_bin, float *re, float *im, qld_hip_stream stream);
 
 /*
+ * dft_bin_baseline_f64 -- the same single-bin DFT in double precision, the
+ * precision the paper computes in (Methods, computations in double): twiddles
+ * from the exact integer angle rounded to double, multiply-adds in double.
+ *   re, im     device double [H][W] (dense, overwritten)
+ * Error <= (N + 2) * 2^-53 * sum_n |S_n| per component.  The sample read is
+ * the same as the float path's, so on MI355X it streams at the same rate.
+ * Arguments and errors as dft_bin_baseline.
+ */
+qld_status dft_bin_baseline_f64(const void *frames, const qld_frame_desc *d, int32_t n_frames,
+                                int32_t k_bin, double *re, double *im, qld_hip_stream stream);
+
+/*
  * qld_lockin_ratio -- lock-in at a general frequency ratio f_mod / f_s = p / q
  * (Methods, R(j,k) with reference tables of any frequency, precomputed once):
  *     X = sum_{t < n} S_t exp(-2 pi i ((p (t0 + t)) mod q) / q) = I - iQ,

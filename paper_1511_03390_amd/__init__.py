@@ -32,7 +32,7 @@ MODE_PLAIN, MODE_LEARNED = 0, 1
 
 # Every entry point the header declares (checked by the tests).
 EXPORTS = (
-    "qld_accumulate", "qld_lockin_image", "qld_amplitude", "dft_bin_baseline", "qld_lockin_ratio", "qld_lockin_bank",
+    "qld_accumulate", "qld_lockin_image", "qld_amplitude", "dft_bin_baseline", "dft_bin_baseline_f64", "qld_lockin_ratio", "qld_lockin_bank",
     "qld_window_bytes", "qld_window_create", "qld_window_update", "qld_window_reset",
     "qld_window_destroy", "qld_window_info", "qld_window_save", "qld_window_load",
     "qld_fwindow_bytes", "qld_fwindow_create", "qld_fwindow_update", "qld_fwindow_reset", "qld_fwindow_info",
@@ -82,6 +82,7 @@ _sig("qld_accumulate", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp, _vp, _
 _sig("qld_lockin_image", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("qld_amplitude", ctypes.c_int, _vp, _vp, _i64, _vp, _vp)
 _sig("dft_bin_baseline", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp)
+_sig("dft_bin_baseline_f64", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp)
 _sig("qld_window_bytes", _sz, _dp, _i32)
 _sig("qld_window_create", ctypes.c_int, _dp, _i32, ctypes.POINTER(_vp))
 _sig("qld_window_update", ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _vp)
@@ -279,6 +280,16 @@ def dft_bin_baseline(frames, k, re, im, bits=None, stream=None):
     n = frames.shape[0] if frames.dim() == 3 else 1
     _check(_lib.dft_bin_baseline(_ptr(frames), ctypes.byref(d), int(n), int(k), _ptr(re), _ptr(im),
                                  _stream(stream)), "dft_bin_baseline")
+
+
+def dft_bin_baseline_f64(frames, k, re, im, bits=None, stream=None):
+    """The single-bin DFT in double precision; re, im float64 [H][W]."""
+    if re.dtype != torch.float64 or im.dtype != torch.float64:
+        raise TypeError("re and im must be float64")
+    d = frame_desc(frames, bits)
+    n = frames.shape[0] if frames.dim() == 3 else 1
+    _check(_lib.dft_bin_baseline_f64(_ptr(frames), ctypes.byref(d), int(n), int(k), _ptr(re), _ptr(im),
+                                     _stream(stream)), "dft_bin_baseline_f64")
 
 
 def lockin(frames, phase0=0, bits=None, stats=False, stream=None):

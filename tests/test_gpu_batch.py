@@ -238,6 +238,33 @@ def bank_bound(frames_host, N, bf16):
 
 
 @pytest.mark.parametrize("T,H,W,k,dt", [(64, 33, 40, 16, np.uint16), (1024, 16, 64, 256, np.uint16),
+                                        (37, 5, 9, 3, np.uint8), (300, 4, 24, -5, np.uint8),
+                                        (2048, 3, 20, 777, np.uint16)])
+def test_dft_bin_baseline_f64(T, H, W, k, dt):
+    """The double-precision DFT against the oracle's double DFT.  GPU: one
+    rounding per fused multiply-add, twiddles from sincospi of the exact
+    integer angle: within (N + 8) 2^-53 sum|x| of the exact value.  Oracle:
+    a rounded product and a rounded sum per term, twiddles from cos/sin of
+    2 pi r / N formed in double (about 20 units of 2^-53): within
+    (2N + 24) 2^-53 sum|x|.  So they agree within (3N + 48) 2^-53 sum|x|."""
+    need_gpu()
+    rng = np.random.default_rng(T + W)
+    bits = 12 if dt == np.uint16 else 8
+    f = rng.integers(0, 1 << bits, size=(T, H, W)).astype(dt)
+    re = torch.empty((H, W), dtype=torch.float64, device="cuda")
+    im = torch.empty_like(re)
+    qld.dft_bin_baseline_f64(to_dev(f), k, re, im, bits=bits)
+    torch.cuda.synchronize()
+    X = oracle.dft_bin(f, k)
+    bound = (3 * T + 48) * 2.0 ** -53 * np.abs(f.astype(np.float64)).sum(axis=0)
+    er, ei = np.abs(re.cpu().numpy() - X.real), np.abs(im.cpu().numpy() - X.imag)
+    say("dft f64 max err", er.max(), ei.max(), "bound", bound.min())
+    assert (er <= bound).all() and (ei <= bound).all()
+    # Orders of magnitude closer than the float path can be.
+    assert er.max() <= 2.0 ** -24 * np.abs(f.astype(np.float64)).sum(axis=0).min()
+
+
+@pytest.mark.parametrize("T,H,W,k,dt", [(64, 33, 40, 16, np.uint16), (1024, 16, 64, 256, np.uint16),
                                         (37, 5, 9, 3, np.uint8), (256, 8, 8, 7, np.uint16),
                                         (300, 4, 24, -5, np.uint8)])
 def test_dft_bin_baseline(T, H, W, k, dt):
