@@ -231,7 +231,23 @@ def cpu_baseline(oracle, frames, target_s, qld_I, torch):
     t0 = time.perf_counter()
     oracle.qld(s1, 0, n_threads=1)
     d1 = time.perf_counter() - t0
+    # The oracle's double-precision DFT (k = 256), timed separately on a bounded sample.
+    t0 = time.perf_counter()
+    oracle.dft_bin(probe, 256, n_threads=threads)
+    rd = probe.size / max(time.perf_counter() - t0, 1e-6)
+    nd = int(min(T, max(4, (rd * 3.0) // (H * W))))
+    sd = frames[:nd].cpu().numpy().view(np.uint16)
+    dreps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.dft_bin(sd, 256, n_threads=threads)
+        dreps += 1
+        dd = time.perf_counter() - t0
+        if dd >= 2.5 or nd < T:
+            break
     return {"value": sample.size * reps / dt, "unit": "pixel-frames/s", "cores": threads, "kind": "oracle",
+            "dft_f64": {"value": round(sd.size * dreps / dd), "unit": "pixel-frames/s",
+                        "sample": "first %d frames, k = 256, %d passes, %.1f s" % (nd, dreps, dd)},
             "sample": "%s (1024x1024 uint16), I/Q by the C oracle, %.1f s; "
                       "GPU I/Q on the same frames identical: %s" % (what, dt, agree),
             "cpu_model": cpu_model(),
@@ -450,6 +466,36 @@ def bench_frame_window(qld, torch, M=64, n=400):
     return {"workload": "1024x1024 uint16 (12-bit), window of %d frames (M=%d cycles), amplitude every frame" % (4 * M, M),
             "update_ms": round(ms, 4), "frames_per_s": round(1e3 / ms), "bytes_per_px_frame": per_px,
             "achieved_gbs": round(per_px * Hf * Wf / (ms * 1e-3) / 1e9, 1)}
+
+
+def bench_window_device(qld, torch, M=64, n=200):
+    """qld_window_update on one 2048 x 2048 uint16 camera (12-bit) with its
+    cycles already in HBM: the sliding window's kernel at its roofline
+    (36 B per pixel per cycle: 8 frames, 4 + 4 ring, 16 I/Q, 4 amplitude)."""
+    Hf = Wf = 2048
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1511033903)
+    bank = torch.randint(0, 4096, (16, 4, Hf, Wf), generator=g, device="cuda", dtype=torch.int32).to(torch.int16)
+    win = qld.Window(Hf, Wf, M, bits=12)
+    amp = torch.empty((Hf, Wf), dtype=torch.float32, device="cuda")
+    for c in range(M + 4):                      # fill the window
+        win.update(bank[c % 16], amp_out=amp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for c in range(n):
+        win.update(bank[c % 16], amp_out=amp)   # the image only (I/Q stay in the window's state)
+    e1.record()
+    torch.cuda.synchronize()
+    win.close()
+    ms = e0.elapsed_time(e1) / n
+    per_px = 8 + 4 + 4 + 16 + 4
+    gbs = per_px * Hf * Wf / (ms * 1e-3) / 1e9
+    del bank
+    return {"workload": "2048x2048 uint16 (12-bit), M=%d cycles, cycles resident in HBM, amplitude every cycle" % M,
+            "update_ms": round(ms, 4), "cycles_per_s": round(1e3 / ms),
+            "pxf_per_s": round(4 * Hf * Wf / (ms * 1e-3)), "bytes_per_px_cycle": per_px,
+            "achieved_gbs": round(gbs, 1), "frac_of_8tbs": round(gbs / 8000.0, 4)}
 
 
 def copy_calibration(torch, gib=1):
@@ -739,6 +785,8 @@ def main():
 
     log("per-frame window")
     frame_window = bench_frame_window(qld, torch)
+    log("cycle window, device-resident frames")
+    window_device = bench_window_device(qld, torch)
 
     learned_serving = None
     if not args.no_learned_serving:
@@ -770,6 +818,7 @@ def main():
         "learned": learned,
         "learned_serving": learned_serving,
         "frame_window": frame_window,
+        "window_device": window_device,
         "lockin_bank": bank,
         "fig1_analog": fig1,
         "read_peak": read_peak,

@@ -132,6 +132,40 @@ __device__ __forceinline__ void state_store(int32_t *p, const int32_t (&v)[VPX])
     }
 }
 
+__device__ __forceinline__ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// VPX 4-byte values to a 16-byte aligned address.
+template <typename T, int VPX>
+__device__ __forceinline__ void store16(T *p, const T (&v)[VPX]) {
+    static_assert(sizeof(T) == 4 && VPX % 4 == 0, "4-byte values, whole 16-byte groups");
+#pragma unroll
+    for (int k = 0; k < VPX; k += 4) {
+        u32x4 q;
+        q[0] = __builtin_bit_cast(uint32_t, v[k]);
+        q[1] = __builtin_bit_cast(uint32_t, v[k + 1]);
+        q[2] = __builtin_bit_cast(uint32_t, v[k + 2]);
+        q[3] = __builtin_bit_cast(uint32_t, v[k + 3]);
+        *reinterpret_cast<u32x4 *>(p + k) = q;
+    }
+}
+
+template <int VPX>
+__device__ __forceinline__ void out_iq(int32_t *io, int32_t *qo, const int32_t (&I)[VPX], const int32_t (&Q)[VPX],
+                                       bool full, int nvalid) {
+    if (full && aligned16(io) && aligned16(qo)) {
+        store16<int32_t, VPX>(io, I);
+        store16<int32_t, VPX>(qo, Q);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VPX; ++k) {
+            if (k < nvalid) {
+                io[k] = I[k];
+                qo[k] = Q[k];
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ float amp_of(int32_t i, int32_t q) {
     const int64_t a = i, b = q;
     return (float)__builtin_sqrt((double)((uint64_t)(a * a) + (uint64_t)(b * b)));
@@ -220,20 +254,22 @@ __global__ __launch_bounds__(kBlock) void window_batch_kernel(WinBatch bt) {
         ring_store<RT, VPX>(rs, di, dq);
 
         const int64_t oslot = (int64_t)((J.out0 + ci) % J.out_slots) * npx + y * J.W + x0;
+        // Outputs: 16-byte stores where the lane's pixels are all in the row and
+        // that output's address is 16-byte aligned, else element by element.
+        if (J.amp) {
+            if (full && aligned16(J.amp + oslot)) {
+                float av[VPX];
 #pragma unroll
-        for (int k = 0; k < VPX; ++k) {
-            if (k < nvalid) {
-                if (J.amp) J.amp[oslot + k] = amp_of(I[k], Q[k]);
-                if (J.Io) {
-                    J.Io[oslot + k] = I[k];
-                    J.Qo[oslot + k] = Q[k];
-                }
-                if (J.Iso) {
-                    J.Iso[oslot + k] = Is[k];
-                    J.Qso[oslot + k] = Qs[k];
-                }
+                for (int k = 0; k < VPX; ++k) av[k] = amp_of(I[k], Q[k]);
+                store16<float, VPX>(J.amp + oslot, av);
+            } else {
+#pragma unroll
+                for (int k = 0; k < VPX; ++k)
+                    if (k < nvalid) J.amp[oslot + k] = amp_of(I[k], Q[k]);
             }
         }
+        if (J.Io) out_iq<VPX>(J.Io + oslot, J.Qo + oslot, I, Q, full, nvalid);
+        if (J.Iso) out_iq<VPX>(J.Iso + oslot, J.Qso + oslot, Is, Qs, full, nvalid);
     }
     state_store<VPX>(J.I + sidx, I);
     state_store<VPX>(J.Q + sidx, Q);
