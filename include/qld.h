@@ -511,12 +511,15 @@ const char *qld_status_str(qld_status st);
 const char *qld_last_error(void);
 /* Device timing of the main kernel alone: start_event / stop_event are
  * hipEvent_t handles created by the caller.  The next qld_accumulate,
- * dft_bin_baseline, qld_lockin_ratio, qld_lockin_bank or qld_denoiser_forward
- * call made by this thread records start_event on its stream right before its
- * main kernel (qld_accum_kernel / dft_bin_kernel / the first bank_kernel / the
- * four convolution kernels) and stop_event right after it, excluding the
- * helper kernels (statistics reduction, twiddle table, chunk reduction,
- * input conversion, pooling).  Both NULL cancels. */
+ * qld_lockin_image, dft_bin_baseline(_f64), qld_lockin_ratio,
+ * qld_lockin_bank, qld_window_update, qld_fwindow_update, qld_read_probe or
+ * qld_denoiser_forward call made by this thread records start_event on its
+ * stream right before its main kernel (qld_accum_kernel / dft_bin_kernel /
+ * the first bank kernel / window_batch_kernel / the frame-window kernel /
+ * read_probe_kernel / the four convolution kernels) and stop_event right
+ * after it, excluding the helper kernels (statistics and frame-split
+ * reductions, twiddle tables, input conversion, pooling).  Both NULL
+ * cancels. */
 qld_status qld_time_next_kernel(void *start_event, void *stop_event);
 /*
  * qld_read_probe -- measurement helper, not part of the method: a plain

@@ -13,8 +13,13 @@
 // R = (I^2 + Q^2)^(1/2) does not rotate from frame to frame.
 //
 // Layout: ring [4M][H][W] samples (uint8 / uint16), I/Q state [H][W] int32.
-// One lane per pixel; per frame and pixel 2 B read (new), 2 B read + 2 B
-// written (ring), 8 B read + 8 B written (I/Q), optional I/Q/amplitude out.
+// Exactly one of c(t), s(t) is non-zero, so a frame changes only one of I, Q:
+// the other is read only when the amplitude or the I/Q outputs need it.
+// Vector kernel (W, row pitch and base in whole groups of 4 pixels): a lane
+// owns 4 pixels, with 4- or 8-byte sample accesses and 16-byte I/Q and
+// amplitude accesses; per frame and pixel (uint16, amplitude out) 2 B read
+// (new), 2 + 2 B (ring), 8 B read + 4 B written (I/Q), 4 B written
+// (amplitude).  Otherwise one lane per pixel.
 #include <new>
 
 #include "qld_internal.hpp"
@@ -59,6 +64,91 @@ __global__ __launch_bounds__(kFBlock) void fwindow_kernel(const T *__restrict__ 
         if (amp_out) {
             const int64_t a = i, b = q;
             amp_out[p] = (float)__builtin_sqrt((double)((uint64_t)(a * a) + (uint64_t)(b * b)));
+        }
+    }
+}
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<uint16_t> {
+    typedef uint32_t raw __attribute__((ext_vector_type(2)));
+    __device__ static void unpack(raw r, int32_t (&v)[4]) {
+        v[0] = (int32_t)(r[0] & 0xffffu);
+        v[1] = (int32_t)(r[0] >> 16);
+        v[2] = (int32_t)(r[1] & 0xffffu);
+        v[3] = (int32_t)(r[1] >> 16);
+    }
+    __device__ static raw pack(const int32_t (&v)[4]) {
+        return raw{((uint32_t)v[0] & 0xffffu) | ((uint32_t)v[1] << 16), ((uint32_t)v[2] & 0xffffu) | ((uint32_t)v[3] << 16)};
+    }
+};
+template <>
+struct Vec4<uint8_t> {
+    typedef uint32_t raw;
+    __device__ static void unpack(raw r, int32_t (&v)[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = (int32_t)((r >> (8 * k)) & 0xffu);
+    }
+    __device__ static raw pack(const int32_t (&v)[4]) {
+        return ((uint32_t)v[0] & 0xffu) | (((uint32_t)v[1] & 0xffu) << 8) | (((uint32_t)v[2] & 0xffu) << 16) |
+               ((uint32_t)v[3] << 24);
+    }
+};
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4w __attribute__((ext_vector_type(4)));
+
+// The vector kernel: W % 4 == 0, row pitch % 4 == 0, frame base aligned to 4
+// samples, outputs 16-byte aligned (checked on the host).
+template <typename T>
+__global__ __launch_bounds__(kFBlock) void fwindow_vec_kernel(const T *__restrict__ frame, int64_t row_pitch, int H,
+                                                              int W, T *__restrict__ ring_slot, int use_old, int ci,
+                                                              int cq, int fresh, int32_t *__restrict__ I,
+                                                              int32_t *__restrict__ Q, int32_t *__restrict__ I_out,
+                                                              int32_t *__restrict__ Q_out,
+                                                              float *__restrict__ amp_out) {
+    typedef typename Vec4<T>::raw raw;
+    const int64_t n4 = (int64_t)H * W / 4;
+    const bool need_both = amp_out || I_out;
+    for (int64_t g = (int64_t)blockIdx.x * kFBlock + threadIdx.x; g < n4; g += (int64_t)gridDim.x * kFBlock) {
+        const int64_t p = 4 * g, y = p / W, x = p % W;
+        int32_t sv[4], ov[4] = {0, 0, 0, 0};
+        Vec4<T>::unpack(__builtin_nontemporal_load(reinterpret_cast<const raw *>(frame + y * row_pitch + x)), sv);
+        raw *rp = reinterpret_cast<raw *>(ring_slot) + g;
+        if (use_old) Vec4<T>::unpack(*rp, ov);
+        *rp = Vec4<T>::pack(sv);
+        i32x4 d, iv, qv;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = sv[k] - ov[k];
+        i32x4 *Ip = reinterpret_cast<i32x4 *>(I) + g;
+        i32x4 *Qp = reinterpret_cast<i32x4 *>(Q) + g;
+        if (fresh) {
+            iv = ci * d;
+            qv = cq * d;
+            *Ip = iv;
+            *Qp = qv;
+        } else if (ci != 0) {
+            iv = *Ip + ci * d;
+            *Ip = iv;
+            if (need_both) qv = *Qp;
+        } else {
+            qv = *Qp + cq * d;
+            *Qp = qv;
+            if (need_both) iv = *Ip;
+        }
+        if (I_out) {
+            reinterpret_cast<i32x4 *>(I_out)[g] = iv;
+            reinterpret_cast<i32x4 *>(Q_out)[g] = qv;
+        }
+        if (amp_out) {
+            f32x4w a;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t u = iv[k], v = qv[k];
+                a[k] = (float)__builtin_sqrt((double)((uint64_t)(u * u) + (uint64_t)(v * v)));
+            }
+            reinterpret_cast<f32x4w *>(amp_out)[g] = a;
         }
     }
 }
@@ -140,7 +230,25 @@ extern "C" qld_status qld_fwindow_update(qld_fwindow *w, const void *frame, int3
         const int use_old = w->t >= n_ring ? 1 : 0;
         const int fresh = w->t == 0 ? 1 : 0;
         const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(npx, kFBlock), 8192);
-        if (w->eb == 2) {
+        hipEvent_t ev0, ev1;
+        take_kernel_timer(&ev0, &ev1);
+        if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
+        auto al = [](const void *q, uintptr_t a) { return q == nullptr || reinterpret_cast<uintptr_t>(q) % a == 0; };
+        const bool vec = d.W % 4 == 0 && d.row_pitch % 4 == 0 && al(frame, 4 * (uintptr_t)w->eb) && al(I_out, 16) &&
+                         al(Q_out, 16) && al(amp_out, 16);
+        if (vec) {
+            const unsigned g4 = (unsigned)std::min<int64_t>(ceil_div(npx / 4, kFBlock), 8192);
+            if (w->eb == 2)
+                hipLaunchKernelGGL(fwindow_vec_kernel<uint16_t>, dim3(g4), dim3(kFBlock), 0, s,
+                                   static_cast<const uint16_t *>(frame), d.row_pitch, d.H, d.W,
+                                   static_cast<uint16_t *>(w->ring) + slot * npx, use_old, kC[ph], kS[ph], fresh, w->I,
+                                   w->Q, I_out, Q_out, amp_out);
+            else
+                hipLaunchKernelGGL(fwindow_vec_kernel<uint8_t>, dim3(g4), dim3(kFBlock), 0, s,
+                                   static_cast<const uint8_t *>(frame), d.row_pitch, d.H, d.W,
+                                   static_cast<uint8_t *>(w->ring) + slot * npx, use_old, kC[ph], kS[ph], fresh, w->I,
+                                   w->Q, I_out, Q_out, amp_out);
+        } else if (w->eb == 2) {
             hipLaunchKernelGGL(fwindow_kernel<uint16_t>, dim3(grid), dim3(kFBlock), 0, s,
                                static_cast<const uint16_t *>(frame), d.row_pitch, d.H, d.W,
                                static_cast<uint16_t *>(w->ring) + slot * npx, use_old, kC[ph], kS[ph], fresh, w->I,
@@ -152,6 +260,7 @@ extern "C" qld_status qld_fwindow_update(qld_fwindow *w, const void *frame, int3
                                w->Q, I_out, Q_out, amp_out);
         }
         QLD_TRY(check_hip(hipGetLastError(), "fwindow_kernel launch"));
+        if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
     }
     w->t += 1;
     w->last_stream = s;

@@ -452,7 +452,11 @@ extern "C" qld_status qld_window_update(qld_window *w, const void *cycle_frames,
             set_error("I_out and Q_out must be both NULL or both set");
             return QLD_E_INVAL;
         }
+        hipEvent_t ev0, ev1;
+        take_kernel_timer(&ev0, &ev1);
+        if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
         QLD_TRY(check_hip(launch_window_batch(b, w->eb, w->wide, vec, s), "window_batch_kernel launch"));
+        if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
     }
     w->c += 1;
     w->last_stream = s;

@@ -53,6 +53,37 @@ def test_frame_window_matches_brute_force_every_frame(H, W, M, bits, dt, n, phas
         assert amp_ulps(amp, oracle.amplitude(oI, oQ)).max() <= 2.0, f
 
 
+@pytest.mark.parametrize("H,W,dt,bits", [(16, 64, np.uint16, 12), (6, 40, np.uint8, 8), (5, 13, np.uint16, 12)])
+def test_frame_window_outputs_on_some_frames_only(H, W, dt, bits):
+    """Updates without outputs keep only the quadrature that changes; the
+    images asked for later still equal the oracle's re-summed window (vector
+    and per-pixel kernels)."""
+    need_gpu()
+    M, n = 2, 29
+    rng = np.random.default_rng(H + W)
+    frames = [rng.integers(0, 1 << bits, size=(H, W)).astype(dt) for _ in range(n)]
+    fw = qld.FrameWindow(H, W, M, phase0=1, dtype=torch.uint8 if dt == np.uint8 else torch.int16, bits=bits)
+    I = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    Q = torch.empty_like(I)
+    amp = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    want = {f for f in range(n) if f % 5 == 4 or f == n - 1}
+    got = {}
+    for f, fr in enumerate(frames):
+        if f in want:
+            fw.update(to_dev(fr), I, Q, amp)
+            torch.cuda.synchronize()
+            got[f] = (I.cpu().numpy().copy(), Q.cpu().numpy().copy(), amp.cpu().numpy().copy())
+        elif f % 5 == 2:
+            fw.update(to_dev(fr), None, None, amp)        # the image only
+        else:
+            fw.update(to_dev(fr))                          # no output at all
+    fw.close()
+    for f, (oI, oQ, _) in enumerate(oracle.frame_window_series(frames, M, 1)):
+        if f in got:
+            assert np.array_equal(got[f][0], oI) and np.array_equal(got[f][1], oQ), f
+            assert amp_ulps(got[f][2], oracle.amplitude(oI, oQ)).max() <= 2.0, f
+
+
 def test_frame_window_reset_and_cycle_alignment():
     need_gpu()
     H, W, M = 12, 20, 2
