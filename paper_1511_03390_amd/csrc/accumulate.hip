@@ -77,6 +77,10 @@ struct AccumArgs {
     int32_t clear_n;
 };
 
+// x + y in two's complement, wrapping like the hardware add (no signed
+// overflow in C++): the caller's running sums plus a stack's sums.
+__device__ __forceinline__ int32_t add_wrap(int32_t x, int32_t y) { return (int32_t)((uint32_t)x + (uint32_t)y); }
+
 // R = (I^2 + Q^2)^(1/2): the sum of squares exact in uint64 (|I|, |Q| < 2^31),
 // one double square root, rounded to float.
 __device__ __forceinline__ float amp_exact(int32_t i, int32_t q) {
@@ -448,7 +452,7 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
             Ip[k] = oi;
             Qp[k] = oq;
         } else {
-            const int32_t ni = a.overwrite ? oi : Ip[k] + oi, nq = a.overwrite ? oq : Qp[k] + oq;
+            const int32_t ni = a.overwrite ? oi : add_wrap(Ip[k], oi), nq = a.overwrite ? oq : add_wrap(Qp[k], oq);
             Ip[k] = ni;
             Qp[k] = nq;
             if (a.amp) a.amp[y * a.W + x0 + k] = amp_exact(ni, nq);
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
         Ip[npx] = oq;
     } else {
         const int64_t o = y * a.W + x;
-        const int32_t ni = a.overwrite ? oi : a.I[o] + oi, nq = a.overwrite ? oq : a.Q[o] + oq;
+        const int32_t ni = a.overwrite ? oi : add_wrap(a.I[o], oi), nq = a.overwrite ? oq : add_wrap(a.Q[o], oq);
         a.I[o] = ni;
         a.Q[o] = nq;
         if (a.amp) a.amp[o] = amp_exact(ni, nq);
@@ -595,8 +599,8 @@ __global__ __launch_bounds__(256) void qld_iq_reduce_kernel(const int32_t *__res
             sq += part[2 * npx * k + npx + p];
         }
         if (!overwrite) {
-            si += I[p];
-            sq += Q[p];
+            si = add_wrap(si, I[p]);
+            sq = add_wrap(sq, Q[p]);
         }
         I[p] = si;
         Q[p] = sq;
