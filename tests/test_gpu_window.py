@@ -152,6 +152,60 @@ def test_server_alone_vs_mix_and_oracle():
             assert amp_ulps(amp, oracle.amplitude(ref[c][0], ref[c][1])).max() <= 2.0
 
 
+def test_server_full_size_three_cameras_sampled():
+    """The benchmark's streaming configuration at full size: 640x512,
+    1280x1024 and 2048x2048 uint16 cameras in one server (M = 64, 16 output
+    slots), 8 distinct cycles per camera replayed, 70 cycles so the ring wraps.
+    64 sampled pixels per stream checked against the oracle's re-summing window
+    at cycles 0, 31, 63, 64 and 69."""
+    need_gpu()
+    M, n, bank = 64, 70, 8
+    check = {0, 31, 63, 64, 69}
+    srv = qld.Server(1 << 36, out_slots=16, keep_iq=True)
+    rng = np.random.default_rng(303)
+    ids, banks, picks = [], [], []
+    for k, (h, w) in enumerate(scenes.STREAM_SHAPES):
+        sid, ok = srv.open(h, w, M, bits=16)
+        assert ok
+        ids.append(sid)
+        cam = scenes.CameraStream(h, w, scenes.seed_for(3, k), bits=16, bank=8)
+        banks.append([cam.cycle(c) for c in range(bank)])
+        picks.append((rng.integers(0, h, 64), rng.integers(0, w, 64)))
+    say("full-size streams", scenes.STREAM_SHAPES)
+    got = {sid: {} for sid in ids}
+
+    def collect():
+        for r in srv.poll():
+            if r.cycle not in check:
+                continue
+            k = ids.index(r.stream_id)
+            ys, xs = picks[k]
+            pI, pQ, _, _ = srv.result_iq(r)
+            I = qld.device_view(pI, (r.H, r.W), torch.int32).cpu().numpy()[ys, xs]
+            Q = qld.device_view(pQ, (r.H, r.W), torch.int32).cpu().numpy()[ys, xs]
+            amp = qld.device_view(r.amp, (r.H, r.W), torch.float32).cpu().numpy()[ys, xs]
+            got[r.stream_id][r.cycle] = (I, Q, amp)
+
+    for c in range(n):
+        for j in range(4):
+            for k, sid in enumerate(ids):
+                assert srv.submit(sid, banks[k][c % bank][j], 4 * c + j, time.monotonic_ns()) == qld.OK
+        if c % 4 == 3:
+            srv.drain()
+            collect()
+    srv.drain()
+    collect()
+    srv.close()
+    for k, sid in enumerate(ids):
+        ys, xs = picks[k]
+        series = [np.ascontiguousarray(np.asarray(banks[k][c % bank])[:, ys, xs][:, None, :]) for c in range(n)]  # [4][1][64]
+        ref = list(oracle.window_series(series, M))
+        for c in sorted(check):
+            I, Q, amp = got[sid][c]
+            assert np.array_equal(I, ref[c][0][0]) and np.array_equal(Q, ref[c][1][0]), (k, c)
+            assert amp_ulps(amp, oracle.amplitude(ref[c][0][0], ref[c][1][0])).max() <= 2.0, (k, c)
+
+
 def test_server_short_window_shares_ring():
     need_gpu()
     M, Ms, n = 8, 3, 14
