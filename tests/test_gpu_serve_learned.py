@@ -134,6 +134,63 @@ def test_learned_stream_serves_denoiser_output(H, W, M, Ms, n, drain_each):
     dn.close()
 
 
+def test_learned_stream_full_size_sampled():
+    """The clutter-and-motion serving configuration's shape: one LEARNED
+    1024 x 1024 stream, M_S = 16 and M = 128 on one ring, 132 cycles (a bank of
+    8 Poisson cycles replayed) so the long window wraps.  At cycles 15, 127
+    and 131: short-window I/Q bit-exact and the plain amplitude within 2 ulp on
+    64 sampled pixels against the oracle's windows; the served image and gate
+    bit-exact against the entry points called one by one on the full image."""
+    need_gpu()
+    H = W = 1024
+    M, Ms, n, nb = 128, 16, 132, 8
+    check_at = {15, 127, 131}
+    rng = np.random.default_rng(1511033905)
+    bank = poisson_cycles(rng, nb, H, W)
+    srv = qld.Server(1 << 36, out_slots=16)
+    sid, ok = srv.open(H, W, M, M_short=Ms, bits=12, mode=qld.MODE_LEARNED)
+    assert ok
+    dn = qld.Denoiser(H, W, 1)
+    dn.set_params(Lr.he_init(5))
+    srv.set_denoiser(sid, dn, float("inf"))
+    got = {}
+
+    def collect():
+        for r in srv.poll(256):
+            if r.cycle in check_at:
+                _, _, pIs, pQs = srv.result_iq(r)
+                got[r.cycle] = dict(served=view(r.amp, H, W, torch.float32),
+                                    plain=view(r.amp_plain, H, W, torch.float32),
+                                    Is=view(pIs, H, W, torch.int32), Qs=view(pQs, H, W, torch.int32),
+                                    gate=float(r.gate), learned=int(r.learned), warm=int(r.warm))
+
+    say("learned stream full size", H, W, M, Ms, n)
+    for c in range(n):
+        for j in range(4):
+            assert srv.submit(sid, bank[c % nb][j], 4 * c + j, time.monotonic_ns()) == qld.OK
+        if c % 4 == 3:
+            srv.drain()
+            collect()
+    srv.drain()
+    collect()
+    srv.close()
+    assert sorted(got) == sorted(check_at)
+    ys, xs = rng.integers(0, H, 64), rng.integers(0, W, 64)
+    series = [np.ascontiguousarray(bank[c % nb][:, ys, xs][:, None, :]) for c in range(n)]
+    longw = list(oracle.window_series(series, M))
+    shortw = list(oracle.window_series(series, Ms))
+    for c in sorted(check_at):
+        r = got[c]
+        assert np.array_equal(r["Is"][ys, xs], shortw[c][0][0]) and np.array_equal(r["Qs"][ys, xs], shortw[c][1][0]), c
+        assert amp_ulps(r["plain"][ys, xs], oracle.amplitude(longw[c][0][0], longw[c][1][0])).max() <= 2.0, c
+        sum_S = int(sum(bank[j % nb].astype(np.int64).sum() for j in range(c - Ms + 1, c + 1)))
+        y, g = reproduce(dn, r["Is"], r["Qs"], sum_S, Ms)
+        assert r["gate"] == g and r["learned"] == 1, c
+        assert np.array_equal(r["served"], y), c
+        assert r["warm"] == (1 if c + 1 >= M else 0), c
+    dn.close()
+
+
 def test_learned_stream_gate_fallback_reset_and_plain_neighbour():
     need_gpu()
     H, W, M, Ms, n = 32, 48, 6, 2, 16
