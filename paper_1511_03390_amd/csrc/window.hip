@@ -26,6 +26,24 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// One 16-byte group of a frame unpacked into VPX samples.
+template <int ELEM, int VPX>
+__device__ __forceinline__ void unpack_frame(const u32x4 &q, int32_t (&v)[VPX]) {
+    const uint32_t w[4] = {q[0], q[1], q[2], q[3]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if constexpr (ELEM == 2) {
+            v[2 * k] = (int32_t)(w[k] & 0xffffu);
+            v[2 * k + 1] = (int32_t)(w[k] >> 16);
+        } else {
+            v[4 * k] = (int32_t)(w[k] & 0xffu);
+            v[4 * k + 1] = (int32_t)((w[k] >> 8) & 0xffu);
+            v[4 * k + 2] = (int32_t)((w[k] >> 16) & 0xffu);
+            v[4 * k + 3] = (int32_t)(w[k] >> 24);
+        }
+    }
+}
+
 template <int ELEM, int VPX, bool VEC>
 __device__ __forceinline__ void load_frame(const uint8_t *p, bool full, int nvalid, int32_t (&v)[VPX]) {
     if constexpr (VEC) {
@@ -209,21 +227,38 @@ __global__ __launch_bounds__(kBlock) void window_batch_kernel(WinBatch bt) {
         const uint8_t *f = J.stage + (int64_t)((J.stage0 + ci) % J.n_stage) * J.slot_b + y * J.rp_b +
                            (int64_t)x0 * ELEM;
         int32_t s0[VPX], s1[VPX], s2[VPX], s3[VPX];
-        load_frame<ELEM, VPX, VEC>(f, full, nvalid, s0);
-        load_frame<ELEM, VPX, VEC>(f + J.fs_b, full, nvalid, s1);
-        load_frame<ELEM, VPX, VEC>(f + 2 * J.fs_b, full, nvalid, s2);
-        load_frame<ELEM, VPX, VEC>(f + 3 * J.fs_b, full, nvalid, s3);
+        const int64_t slot = c % J.M;
+        RT *rs = ring + (slot * npx_p + sidx) * 2;
+        const bool old = c >= J.M;
+        int32_t oi[VPX], oq[VPX];
+        if (VEC && full) {
+            // Whole lane: the four frames' loads and the oldest ring entry are
+            // issued together, then unpacked (a branch between the loads had
+            // made each wait for the one before).
+            u32x4 q[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                q[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(f + i * J.fs_b));
+            if (old) ring_load<RT, VPX>(rs, oi, oq);
+            __builtin_amdgcn_sched_barrier(0);
+            unpack_frame<ELEM, VPX>(q[0], s0);
+            unpack_frame<ELEM, VPX>(q[1], s1);
+            unpack_frame<ELEM, VPX>(q[2], s2);
+            unpack_frame<ELEM, VPX>(q[3], s3);
+        } else {
+            load_frame<ELEM, VPX, false>(f, full, nvalid, s0);
+            load_frame<ELEM, VPX, false>(f + J.fs_b, full, nvalid, s1);
+            load_frame<ELEM, VPX, false>(f + 2 * J.fs_b, full, nvalid, s2);
+            load_frame<ELEM, VPX, false>(f + 3 * J.fs_b, full, nvalid, s3);
+            if (old) ring_load<RT, VPX>(rs, oi, oq);
+        }
         int32_t di[VPX], dq[VPX];
 #pragma unroll
         for (int k = 0; k < VPX; ++k) {
             di[k] = s0[k] - s2[k];
             dq[k] = s1[k] - s3[k];
         }
-        const int64_t slot = c % J.M;
-        RT *rs = ring + (slot * npx_p + sidx) * 2;
-        if (c >= J.M) {
-            int32_t oi[VPX], oq[VPX];
-            ring_load<RT, VPX>(rs, oi, oq);
+        if (old) {
 #pragma unroll
             for (int k = 0; k < VPX; ++k) {
                 I[k] -= oi[k];
