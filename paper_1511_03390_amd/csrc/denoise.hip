@@ -158,27 +158,54 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const __bf16 *__restrict
         }
     }
     const int y = y0 + wave;
-    if (y >= H) return;
+    if constexpr (MODE == 2) {
+        if (y >= H) return;
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int px = x0 + 16 * g + 4 * kb + i;
-            if (px >= W) continue;
-            if constexpr (MODE == 2) {
-                if (m == 0) static_cast<float *>(out)[(img + y) * W + px] = acc[g][0][i] + bias[0];
-            } else {
+            for (int i = 0; i < 4; ++i) {
+                const int px = x0 + 16 * g + 4 * kb + i;
+                if (px < W && m == 0) static_cast<float *>(out)[(img + y) * W + px] = acc[g][0][i] + bias[0];
+            }
+    } else {
+        // The wave's 64 pixels x 32 channels go out through LDS (the input
+        // tile is no longer read): each lane writes its bf16 results (MODE 0:
+        // bias and ReLU applied first), then moves four 16-byte chunks, so the
+        // global stores (and MODE 1's ReLU-mask loads) are 1 KiB contiguous
+        // per instruction.  Rounding before masking equals masking first (the
+        // mask is 0 or 1).  Rows of 40 channels keep the writes conflict-free.
+        constexpr int kORow = 40;
+        __bf16(*ot)[kORow] = reinterpret_cast<__bf16(*)[kORow]>(&tile[0][0][0]) + wave * 64;
+        static_assert(4 * 64 * kORow * sizeof(__bf16) <= sizeof(tile), "output staging fits in the tile");
+        __syncthreads();                                  // every wave is done reading the input tile
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) {
                     const int co = 16 * cb + m;
-                    const int64_t idx = ((img + y) * W + px) * 32 + co;
                     float v = acc[g][cb][i];
                     if (MODE == 0) v = fmaxf(v + bias[co], 0.0f);
-                    else v = (float)act[idx] > 0.0f ? v : 0.0f;
-                    static_cast<__bf16 *>(out)[idx] = (__bf16)v;
+                    ot[16 * g + 4 * kb + i][co] = (__bf16)v;
                 }
+        __syncthreads();
+        if (y >= H) return;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int j = lane + 64 * jj, pl = j >> 2, cg = j & 3;
+            const int px = x0 + pl;
+            if (px >= W) continue;
+            const int64_t idx = ((img + y) * W + px) * 32 + cg * 8;
+            bf16x8 v = *reinterpret_cast<const bf16x8 *>(&ot[pl][cg * 8]);
+            if constexpr (MODE == 1) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(act + idx);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (float)a[e] > 0.0f ? v[e] : (__bf16)0.0f;
             }
+            *reinterpret_cast<bf16x8 *>(static_cast<__bf16 *>(out) + idx) = v;
         }
+    }
 }
 
 // 2 -> 32 input layer: the 18 (tap, channel) products form one K = 32 MFMA.
