@@ -238,17 +238,29 @@ __global__ __launch_bounds__(256) void conv1_kernel(const __bf16 *__restrict__ x
         acc[g][0] = mfma16(a, w0, f32x4{0.f, 0.f, 0.f, 0.f});
         acc[g][1] = mfma16(a, w1, f32x4{0.f, 0.f, 0.f, 0.f});
     }
+    // Out through a per-wave LDS tile (64 pixels x 32 channels, rows of 40):
+    // 16-byte global stores, 1 KiB contiguous per instruction.  Only this
+    // wave reads what it wrote, so a wave-level scheduling barrier suffices.
+    __shared__ __align__(16) __bf16 ot_all[4][64][40];
+    __bf16(*ot)[40] = ot_all[threadIdx.x >> 6];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int px = xs + 16 * g + 4 * kb + i;
-                if (px >= W) continue;
                 const int co = 16 * cb + m;
-                out[((img + y) * W + px) * 32 + co] = (__bf16)fmaxf(acc[g][cb][i] + bias[co], 0.0f);
+                ot[16 * g + 4 * kb + i][co] = (__bf16)fmaxf(acc[g][cb][i] + bias[co], 0.0f);
             }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        const int j = lane + 64 * jj, pl = j >> 2, cg = j & 3;
+        const int px = xs + pl;
+        if (px >= W) continue;
+        *reinterpret_cast<bf16x8 *>(out + ((img + y) * W + px) * 32 + cg * 8) =
+            *reinterpret_cast<const bf16x8 *>(&ot[pl][cg * 8]);
+    }
 }
 
 // dy = 2 (y - t) / N; per-block partial sums of (y - t)^2.
