@@ -289,25 +289,30 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *__restrict__ y, 
 __global__ __launch_bounds__(256) void out_back_kernel(const float *__restrict__ dy, const __bf16 *__restrict__ w4,
                                                        const __bf16 *__restrict__ a3, __bf16 *__restrict__ dz, int B,
                                                        int H, int W) {
+    // Four lanes per pixel, 8 channels each: a wave's loads of a3 and stores
+    // of dz are 1 KiB contiguous per instruction.
     const int64_t n = (int64_t)B * H * W;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = gt >> 2;
+    const int cg = (int)(gt & 3);
     if (p >= n) return;
     const int x = (int)(p % W), y = (int)((p / W) % H);
     const int64_t b = p / ((int64_t)H * W);
-    float acc[32];
+    float acc[8];
 #pragma unroll
-    for (int c = 0; c < 32; ++c) acc[c] = 0.f;
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
     for (int t = 0; t < 9; ++t) {
         const int iy = y - tap_dy(t), ix = x - tap_dx(t);
         if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
         const float g = dy[(b * H + iy) * W + ix];
 #pragma unroll
-        for (int c = 0; c < 32; ++c) acc[c] = fmaf(g, (float)w4[t * 32 + c], acc[c]);
+        for (int c = 0; c < 8; ++c) acc[c] = fmaf(g, (float)w4[t * 32 + cg * 8 + c], acc[c]);
     }
-    const __bf16 *ap = a3 + p * 32;
-    __bf16 *dp = dz + p * 32;
+    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a3 + p * 32 + cg * 8);
+    bf16x8 o;
 #pragma unroll
-    for (int c = 0; c < 32; ++c) dp[c] = (__bf16)((float)ap[c] > 0.f ? acc[c] : 0.f);
+    for (int c = 0; c < 8; ++c) o[c] = (__bf16)((float)av[c] > 0.f ? acc[c] : 0.f);
+    *reinterpret_cast<bf16x8 *>(dz + p * 32 + cg * 8) = o;
 }
 
 // 32x32 weight gradient on the matrix cores: D[tap][ci][co] = sum_px a[px + tap][ci] dz[px][co]
@@ -955,8 +960,8 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, d->lpart, kLossBlocks, npx, d->loss);
     // Output layer: dW4, db4, and dz3 = bf16(d a3 * (a3 > 0)).
     QLD_TRY(dw_out(d, B, s));
-    hipLaunchKernelGGL(out_back_kernel, dim3((unsigned)ceil_div(npx, 256)), dim3(256), 0, s, d->dy, d->w4, d->a3,
-                       d->dzA, B, H, W);
+    hipLaunchKernelGGL(out_back_kernel, dim3((unsigned)ceil_div(4 * npx, 256)), dim3(256), 0, s, d->dy, d->w4,
+                       d->a3, d->dzA, B, H, W);
     const int g = conv_grid(B, H, W);
     // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
     QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));   // and b3
