@@ -60,6 +60,7 @@ struct AccumArgs {
     int32_t x_begin;       // first column this kernel covers
     int32_t ncols;         // columns it covers (vector kernel: whole lanes only)
     int32_t n_tiles;       // work-group tiles over its lanes
+    int32_t n_units;       // (tile, split) work units, tiles rounded up to a multiple of kXcds
     int32_t wave_base;     // first stats-partial row of this kernel
     uint32_t top;          // 2^bits - 1
     int32_t *I;
@@ -460,9 +461,8 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
     }
 }
 
-__device__ __forceinline__ void tile_and_split(const AccumArgs &a, int &tile, int &split) {
-    // Work-group id -> (pixel tile, frame chunk), chunks of a tile on one XCD.
-    const int b = blockIdx.x;
+__device__ __forceinline__ void tile_and_split(const AccumArgs &a, int b, int &tile, int &split) {
+    // Work unit -> (pixel tile, frame chunk), chunks of a tile on one XCD.
     const int xcd = b % kXcds;
     const int q = b / kXcds;
     split = q % a.n_split;
@@ -472,17 +472,21 @@ __device__ __forceinline__ void tile_and_split(const AccumArgs &a, int &tile, in
 template <int ELEM, bool STATS, bool PACKED>
 __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
     clear_stats_once(a);
-    int tile, split;
-    tile_and_split(a, tile, split);
-    if (tile >= a.n_tiles) return;
     const int64_t n_vec = (int64_t)(a.ncols / (16 / ELEM)) * a.H;
     uint32_t *lds = nullptr;
     if constexpr (STATS) {
         __shared__ uint32_t stats_lds[kWavesPerBlock * kStatsSlots * kStatsRow];
         lds = stats_lds;
     }
-    if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split, lds);
-    else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, lds);
+    // Persistent grid (a multiple of kXcds work-groups): work-group b takes
+    // units b, b + gridDim.x, ..., all on its own XCD.
+    for (int u = blockIdx.x; u < a.n_units; u += gridDim.x) {
+        int tile, split;
+        tile_and_split(a, u, tile, split);
+        if (tile >= a.n_tiles) continue;
+        if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split, lds);
+        else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, lds);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -492,7 +496,7 @@ template <int ELEM, bool STATS>
 __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
     clear_stats_once(a);
     int tile, split;
-    tile_and_split(a, tile, split);
+    tile_and_split(a, blockIdx.x, tile, split);
     if (tile >= a.n_tiles) return;
     const int64_t n_px = (int64_t)a.ncols * a.H;
     const int64_t g = (int64_t)tile * kBlock + threadIdx.x;
@@ -628,19 +632,28 @@ hipError_t launch_scalar(const AccumArgs &a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Frame-axis split: only until the grid holds QLD_ACCUM_BLOCKS_PER_CU
-// work-groups per CU, with at least 16 cycles per work-group.  Measured on
-// MI355X with 2 MiB frames: one pass over the frames at 1-2 work-groups per CU
-// streams fastest (the whole grid sweeps the stack as one front).
+// Grid and frame-axis split of the vector kernel.  The grid is persistent:
+// at most QLD_ACCUM_BLOCKS_PER_CU work-groups per CU, looping over (tile,
+// split) units.  Measured on MI355X: one pass over the frames at 1-2
+// work-groups per CU streams fastest (the whole grid sweeps the stack as one
+// front); at 2160 x 2160 x 800 without statistics (2279 tiles, up to 8 groups
+// per CU resident when each tile had its own group) the cap gains 3%.  With
+// fewer tiles than work-groups a frame split fills the grid (at least 16
+// cycles per unit).  Splitting larger images to even out the rounds (2279
+// tiles on 512 groups: 5 rounds, the last 45% full; 9 half rounds split in
+// two) measured no faster: the partials' reduction costs what the tail did.
 #ifndef QLD_ACCUM_BLOCKS_PER_CU
 #define QLD_ACCUM_BLOCKS_PER_CU 2
 #endif
+int64_t accum_grid_cap() {
+    return std::max<int64_t>(kXcds, ((int64_t)QLD_ACCUM_BLOCKS_PER_CU * device_cu_count()) / kXcds * kXcds);
+}
+
 int32_t choose_split(int64_t n_tiles, int32_t n_frames) {
-    const int64_t want_blocks = (int64_t)QLD_ACCUM_BLOCKS_PER_CU * device_cu_count();
-    int64_t ns = 1;
-    if (n_tiles < want_blocks) ns = ceil_div(want_blocks, n_tiles);
-    ns = std::max<int64_t>(1, std::min<int64_t>(ns, (n_frames / 4) / 16));
-    return (int32_t)ns;
+    const int64_t G = accum_grid_cap();
+    const int64_t smax = std::max<int64_t>(1, (n_frames / 4) / 16);
+    if (n_tiles >= G) return 1;
+    return (int32_t)std::min<int64_t>(ceil_div(G, n_tiles), smax);
 }
 
 }  // namespace
@@ -745,12 +758,14 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     }
     // 16-bit partial sums hold at least two cycles for data of up to 14 bits.
     const bool packed = eb == 1 || top <= 16383;
-    const int64_t gv = ceil_div(vt, kXcds) * kXcds * av.n_split;
+    const int64_t uv = ceil_div(vt, kXcds) * kXcds * av.n_split;
     const int64_t gs = ceil_div(st, kXcds) * kXcds * as.n_split;
-    if (gv > 0x7fffffff || gs > 0x7fffffff) {
+    if (uv > 0x7fffffff || gs > 0x7fffffff) {
         set_error("grid too large");
         return QLD_E_SHAPE;
     }
+    av.n_units = (int32_t)uv;
+    const int64_t gv = std::min<int64_t>(uv, accum_grid_cap());
 
     hipEvent_t ev0, ev1;
     take_kernel_timer(&ev0, &ev1);

@@ -117,7 +117,16 @@ def test_full_range_16bit_and_overflow_edge():
 
 
 @pytest.mark.parametrize("T,H,W,bits,phase0", [(64, 17, 40, 12, 1), (4096, 16, 16, 12, 0), (9, 5, 1003, 16, 3),
-                                               (1024, 64, 64, 12, 2)])
+                                               (1024, 64, 64, 12, 2),
+                                               # more pixel tiles than work-groups: 550 tiles, unsplit,
+                                               # two rounds of the persistent grid
+                                               (64, 1100, 1024, 12, 3),
+                                               # 520 tiles plus a 4-column scalar tail, ragged
+                                               # last cycle
+                                               (130, 520, 2052, 12, 1),
+                                               # 300 tiles split in two: 608 units on 512
+                                               # work-groups (some take two units)
+                                               (256, 300, 2048, 12, 2)])
 def test_lockin_image_overwrites_and_matches_accumulate(T, H, W, bits, phase0):
     """qld_lockin_image (one pass: I/Q, amplitude and statistics overwritten)
     on garbage-filled outputs equals clearing them, qld_accumulate and
