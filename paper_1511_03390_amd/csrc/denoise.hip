@@ -347,27 +347,46 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
     for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
     const bf16x8 zero = zero8();
-    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+    // A segment's global loads: dz of pixel x0 + (t & 63), channels 8 (t >> 6)
+    // .. +8; a of rows y-1, y, y+1, pixels x0-1 .. x0+64 (3 x 4 x 66 16-byte
+    // items, item t + 256 i for lane t).  The next segment's are issued before
+    // the current one's matrix products, so they are in flight meanwhile.
+    constexpr int kAItems = 3 * 4 * 66;
+    bf16x8 vd, va[4];
+    auto fetch = [&](int64_t sg) {
         const int x0 = (int)(sg % segs_x) * kSegPx;
         const int64_t row = sg / segs_x;            // b * H + y
         const int y = (int)(row % H);
-        __syncthreads();                            // the previous segment's readers are done
-        {   // dz: pixel x0 + (t & 63), channels 8 (t >> 6) .. +8
-            const int px = t & 63, cg = t >> 6, x = x0 + px;
-            const bf16x8 v = x < W ? *reinterpret_cast<const bf16x8 *>(dz + (row * W + x) * 32 + cg * 8) : zero;
+        const int x = x0 + (t & 63);
+        vd = x < W ? *reinterpret_cast<const bf16x8 *>(dz + (row * W + x) * 32 + (t >> 6) * 8) : zero;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = v[i];
-        }
-        // a: rows y-1, y, y+1; pixels x0-1 .. x0+64 at aT columns 7 .. 72.
-        for (int item = t; item < 3 * 4 * 66; item += 256) {
+        for (int i = 0; i < 4; ++i) {
+            const int item = t + 256 * i;
             const int px = item % 66, q = item / 66, cg = q & 3, r = q >> 2;
-            const int x = x0 - 1 + px, iy = y + r - 1;
-            const bool ok = x >= 0 && x < W && iy >= 0 && iy < H;
-            const bf16x8 v = ok ? *reinterpret_cast<const bf16x8 *>(a + ((row - y + iy) * W + x) * 32 + cg * 8) : zero;
+            const int xa = x0 - 1 + px, iy = y + r - 1;
+            const bool ok = item < kAItems && xa >= 0 && xa < W && iy >= 0 && iy < H;
+            va[i] = ok ? *reinterpret_cast<const bf16x8 *>(a + ((row - y + iy) * W + xa) * 32 + cg * 8) : zero;
+        }
+    };
+    if ((int64_t)blockIdx.x < n_seg) fetch(blockIdx.x);
+    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+        __syncthreads();                            // the previous segment's readers are done
+        {
+            const int px = t & 63, cg = t >> 6;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) aT[r][cg * 8 + i][px + 7] = v[i];
+            for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = vd[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int item = t + 256 * i;
+            if (item < kAItems) {
+                const int px = item % 66, q = item / 66, cg = q & 3, r = q >> 2;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) aT[r][cg * 8 + e][px + 7] = va[i][e];
+            }
         }
         __syncthreads();
+        if (sg + gridDim.x < n_seg) fetch(sg + gridDim.x);
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             const int pxb = kk * 32 + kb * 8;       // this lane's 8 pixels: x0 + pxb .. +8
@@ -435,30 +454,37 @@ __global__ __launch_bounds__(256) void dw1_kernel(const __bf16 *__restrict__ x, 
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
     const bf16x8 zero = zero8();
-    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+    // A segment's global loads (its dz1 chunk; lanes t < 198: the two input
+    // channels of pixel x0 - 1 + t % 66 in row y - 1 + t / 66), the next
+    // segment's issued before the current one's matrix products.
+    bf16x8 vd;
+    uint32_t vx = 0;                                 // bf16 pair (channel 0 low)
+    auto fetch = [&](int64_t sg) {
         const int x0 = (int)(sg % segs_x) * kSegPx;
         const int64_t row = sg / segs_x;
         const int y = (int)(row % H);
+        const int xx = x0 + (t & 63);
+        vd = xx < W ? *reinterpret_cast<const bf16x8 *>(dz + (row * W + xx) * 32 + (t >> 6) * 8) : zero;
+        const int px = t % 66, rr = t / 66;
+        const int xi = x0 - 1 + px, iy = y + rr - 1;
+        const bool ok = t < 3 * 66 && xi >= 0 && xi < W && iy >= 0 && iy < H;
+        vx = ok ? *reinterpret_cast<const uint32_t *>(x + ((row - y + iy) * W + xi) * 2) : 0u;
+    };
+    if ((int64_t)blockIdx.x < n_seg) fetch(blockIdx.x);
+    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
         __syncthreads();
         {
-            const int px = t & 63, cg = t >> 6, xx = x0 + px;
-            const bf16x8 v = xx < W ? *reinterpret_cast<const bf16x8 *>(dz + (row * W + xx) * 32 + cg * 8) : zero;
+            const int px = t & 63, cg = t >> 6;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = v[i];
+            for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = vd[i];
         }
         if (t < 3 * 66) {
             const int px = t % 66, rr = t / 66;
-            const int xx = x0 - 1 + px, iy = y + rr - 1;
-            __bf16 v0 = (__bf16)0.0f, v1 = (__bf16)0.0f;
-            if (xx >= 0 && xx < W && iy >= 0 && iy < H) {
-                const __bf16 *q = x + ((row - y + iy) * W + xx) * 2;
-                v0 = q[0];
-                v1 = q[1];
-            }
-            xT[rr][0][px + 7] = v0;
-            xT[rr][1][px + 7] = v1;
+            xT[rr][0][px + 7] = __builtin_bit_cast(__bf16, (uint16_t)(vx & 0xffffu));
+            xT[rr][1][px + 7] = __builtin_bit_cast(__bf16, (uint16_t)(vx >> 16));
         }
         __syncthreads();
+        if (sg + gridDim.x < n_seg) fetch(sg + gridDim.x);
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             const int pxb = kk * 32 + kb * 8;
@@ -511,21 +537,40 @@ __global__ __launch_bounds__(256) void dw_out_kernel(const __bf16 *__restrict__ 
     const int64_t n_seg = (int64_t)B * H * segs_x;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, bacc = 0.f;
     const bf16x8 zero = zero8();
-    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+    // A segment's global loads (dy of its 64 pixels, the a3 items of
+    // dw32_kernel), the next segment's issued before the current one's sums.
+    constexpr int kAItems = 3 * 4 * 66;
+    float vdy = 0.f;
+    bf16x8 va[4];
+    auto fetch = [&](int64_t sg) {
         const int x0 = (int)(sg % segs_x) * kSegPx;
         const int64_t row = sg / segs_x;
         const int y = (int)(row % H);
-        __syncthreads();
-        if (t < kSegPx) dyS[t] = x0 + t < W ? dy[row * W + x0 + t] : 0.f;
-        for (int item = t; item < 3 * 4 * 66; item += 256) {
+        vdy = t < kSegPx && x0 + t < W ? dy[row * W + x0 + t] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int item = t + 256 * i;
             const int px = item % 66, qq = item / 66, cg = qq & 3, rr = qq >> 2;
             const int x = x0 - 1 + px, iy = y + rr - 1;
-            const bool ok = x >= 0 && x < W && iy >= 0 && iy < H;
-            const bf16x8 v = ok ? *reinterpret_cast<const bf16x8 *>(a + ((row - y + iy) * W + x) * 32 + cg * 8) : zero;
+            const bool ok = item < kAItems && x >= 0 && x < W && iy >= 0 && iy < H;
+            va[i] = ok ? *reinterpret_cast<const bf16x8 *>(a + ((row - y + iy) * W + x) * 32 + cg * 8) : zero;
+        }
+    };
+    if ((int64_t)blockIdx.x < n_seg) fetch(blockIdx.x);
+    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+        __syncthreads();
+        if (t < kSegPx) dyS[t] = vdy;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) aT[rr][cg * 8 + i][px + 7] = v[i];
+        for (int i = 0; i < 4; ++i) {
+            const int item = t + 256 * i;
+            if (item < kAItems) {
+                const int px = item % 66, qq = item / 66, cg = qq & 3, rr = qq >> 2;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) aT[rr][cg * 8 + e][px + 7] = va[i][e];
+            }
         }
         __syncthreads();
+        if (sg + gridDim.x < n_seg) fetch(sg + gridDim.x);
         if (t < 192) {
             const __bf16 *rp = &aT[r][ci][0];
             const int p0 = half * 32;
