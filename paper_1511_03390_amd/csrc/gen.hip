@@ -46,10 +46,13 @@ struct Table {
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                               uint32_t k1, uint32_t out[4]) {
     constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u, kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+    // Each round's two 32 x 32 -> 64-bit products are taken whole (one
+    // v_mad_u64_u32 each instead of separate low and high multiplies).
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = kM0 * c0, hi0 = __umulhi(kM0, c0);
-        const uint32_t lo1 = kM1 * c2, hi1 = __umulhi(kM1, c2);
+        const uint64_t p0 = (uint64_t)kM0 * c0, p1 = (uint64_t)kM1 * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
