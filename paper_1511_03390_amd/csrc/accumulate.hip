@@ -27,9 +27,9 @@
 //     kernel's bandwidth at 256x256 and 512x512;
 //   * per-frame statistics: each lane's sum of its samples (v_dot2_u32_u16 /
 //     v_sad_u8) goes to LDS, one row per frame; every 64 frames lane j adds up
-//     row j, which transposes the cross-lane reduction into plain adds, and
-//     stores the per-wave partial; a small kernel folds the partials into
-//     frame_sum.  Clipped samples are rare: a packed max per frame detects
+//     row j, which transposes the cross-lane reduction into plain adds, the
+//     four waves' sums are added in LDS and the work-group partial stored; a
+//     small kernel folds the partials into frame_sum.  Clipped samples are rare: a packed max per frame detects
 //     whether any sample reaches 2^bits - 1 and only then are they counted
 //     with ballots.  (The scalar kernel reduces with DPP row shifts instead.)
 #include "qld_internal.hpp"
@@ -61,7 +61,7 @@ struct AccumArgs {
     int32_t ncols;         // columns it covers (vector kernel: whole lanes only)
     int32_t n_tiles;       // work-group tiles over its lanes
     int32_t n_units;       // (tile, split) work units, tiles rounded up to a multiple of kXcds
-    int32_t wave_base;     // first stats-partial row of this kernel
+    int32_t row_base;      // first stats-partial row of this kernel (vector: one per tile, scalar: per wave)
     uint32_t top;          // 2^bits - 1
     int32_t *I;
     int32_t *Q;
@@ -139,11 +139,14 @@ struct Stats {
     uint32_t *part_sum, *part_sat;
 };
 
-// Per-wave, per-frame statistics of the vector kernel, transposed through LDS:
-// each lane writes its lane sum of frame slot j into row j of a
+// Per-frame statistics of the vector kernel, transposed through LDS: each
+// lane writes its lane sum of frame slot j into row j of its wave's
 // [kStatsSlots][65]-word buffer (one store per frame, consecutive banks); at a
 // flush lane j adds up row j (the padding column puts the lanes' reads in
-// different banks) and stores that frame's wave partial.  Slots follow the
+// different banks), the four waves' sums meet in LDS after a work-group
+// barrier (every wave of a group flushes at the same frame counts), and wave 0
+// stores the work-group partial of each frame: a quarter of the partials, and
+// of the reduction's reads, of one row per wave.  Slots follow the
 // wave's frames in order (cycle k0 + j/4, phase j%4), so a slot's frame index
 // is computed at the flush instead of being carried.  The saturation count is
 // wave-uniform; it is written into lane j's register only for frames that have
@@ -158,6 +161,8 @@ struct StatsLds {
     int64_t split = 0, S = 1;            // frame of (cycle k, phase j) = 4 (split + k S) + j
     int64_t row;
     uint32_t *lds;                       // this wave's [kStatsSlots][kStatsRow] words
+    uint32_t *comb;                      // the work-group's [2][kWavesPerBlock][2][64] words
+    int parity = 0;                      // comb half of this flush (the halves alternate)
     uint32_t *part_sum, *part_sat;
 
     __device__ __forceinline__ void put(uint32_t lane_sum) {
@@ -169,8 +174,9 @@ struct StatsLds {
     }
 
     __device__ __forceinline__ void flush() {
-        const int lane = (int)(threadIdx.x & 63);
+        const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
         __builtin_amdgcn_wave_barrier();
+        uint32_t sum = 0;
         if (lane < slot) {
             const uint32_t *r = lds + lane * kStatsRow;
             uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -181,11 +187,26 @@ struct StatsLds {
                 s2 += r[i + 2];
                 s3 += r[i + 3];
             }
-            const int64_t t = 4 * (split + (k0 + lane / 4) * S) + lane % 4;
-            part_sum[row + t] = (s0 + s1) + (s2 + s3);
-            part_sat[row + t] = buf_sat;
+            sum = (s0 + s1) + (s2 + s3);
         }
-        __builtin_amdgcn_wave_barrier();
+        uint32_t *c = comb + parity * (kWavesPerBlock * 2 * 64);
+        c[(wave * 2 + 0) * 64 + lane] = sum;
+        c[(wave * 2 + 1) * 64 + lane] = buf_sat;
+        // A half is rewritten two flushes later, after the next flush's
+        // barrier, which wave 0 reaches only once it has read this one.
+        __syncthreads();
+        if (wave == 0 && lane < slot) {
+            uint32_t gs = 0, gc = 0;
+#pragma unroll
+            for (int w = 0; w < kWavesPerBlock; ++w) {
+                gs += c[(w * 2 + 0) * 64 + lane];
+                gc += c[(w * 2 + 1) * 64 + lane];
+            }
+            const int64_t t = 4 * (split + (k0 + lane / 4) * S) + lane % 4;
+            part_sum[row + t] = gs;
+            part_sat[row + t] = gc;
+        }
+        parity ^= 1;
         k0 += slot / 4;
         slot = 0;
         buf_sat = 0;
@@ -361,7 +382,8 @@ __device__ __forceinline__ u32x4 ld16(const uint8_t *p) {
 // MASKED: some lanes of this work-group are past the last vector; they read
 // a valid address and zero what they read.
 template <int ELEM, bool STATS, bool PACKED, bool MASKED>
-__device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split, uint32_t *stats_lds) {
+__device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split, uint32_t *stats_lds,
+                                         uint32_t *stats_comb) {
     constexpr int kPx = 16 / ELEM;
     const int nvx = a.ncols / kPx;
     const int64_t n_vec = (int64_t)nvx * a.H;
@@ -387,8 +409,9 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
     if constexpr (STATS) {
         st.part_sum = a.part_sum;
         st.part_sat = a.part_sat;
-        st.row = ((int64_t)a.wave_base + (int64_t)tile * kWavesPerBlock + (threadIdx.x >> 6)) * a.n_frames;
+        st.row = ((int64_t)a.row_base + tile) * a.n_frames;
         st.lds = stats_lds + (threadIdx.x >> 6) * kStatsSlots * kStatsRow;
+        st.comb = stats_comb;
         st.split = split;
         st.S = a.n_split;
     }
@@ -473,10 +496,12 @@ template <int ELEM, bool STATS, bool PACKED>
 __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
     clear_stats_once(a);
     const int64_t n_vec = (int64_t)(a.ncols / (16 / ELEM)) * a.H;
-    uint32_t *lds = nullptr;
+    uint32_t *lds = nullptr, *comb = nullptr;
     if constexpr (STATS) {
         __shared__ uint32_t stats_lds[kWavesPerBlock * kStatsSlots * kStatsRow];
+        __shared__ uint32_t stats_comb[2 * kWavesPerBlock * 2 * 64];
         lds = stats_lds;
+        comb = stats_comb;
     }
     // Persistent grid (a multiple of kXcds work-groups): work-group b takes
     // units b, b + gridDim.x, ..., all on its own XCD.
@@ -484,8 +509,8 @@ __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
         int tile, split;
         tile_and_split(a, u, tile, split);
         if (tile >= a.n_tiles) continue;
-        if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split, lds);
-        else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, lds);
+        if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split, lds, comb);
+        else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, lds, comb);
     }
 }
 
@@ -518,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
     if constexpr (STATS) {
         st.part_sum = a.part_sum;
         st.part_sat = a.part_sat;
-        st.row = ((int64_t)a.wave_base + (int64_t)tile * kWavesPerBlock + (threadIdx.x >> 6)) * a.n_frames;
+        st.row = ((int64_t)a.row_base + (int64_t)tile * kWavesPerBlock + (threadIdx.x >> 6)) * a.n_frames;
     }
     int32_t I = 0, Q = 0;
     // Cycles split, split + S, ... (all work-groups sweep the stack together).
@@ -565,19 +590,19 @@ __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
 }
 
 // frame_sum[t] += sum over waves of part_sum[w][t] (and the same for counts).
-// Grid: (ceil(T/256), ceil(n_waves/kRowsPerBlock)), 256 lanes per work-group.
+// Grid: (ceil(T/256), ceil(n_rows/kRowsPerBlock)), 256 lanes per work-group.
 constexpr int kRowsPerBlock = 16;
 
-// Folds the per-wave partials: work-group (frames 256 bx .. +256, waves
+// Folds the partial rows: work-group (frames 256 bx .. +256, rows
 // kRowsPerBlock by .. +kRowsPerBlock); the rows are read with many loads in
 // flight per lane, and the integer sums combined with order-free atomics.
 __global__ __launch_bounds__(256) void qld_stats_reduce_kernel(const uint32_t *ps, const uint32_t *pc,
-                                                               int64_t n_waves, int32_t T,
+                                                               int64_t n_rows, int32_t T,
                                                                uint64_t *frame_sum, uint32_t *frame_sat) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= T) return;
     const int64_t w0 = (int64_t)blockIdx.y * kRowsPerBlock;
-    const int64_t w1 = min(n_waves, w0 + kRowsPerBlock);
+    const int64_t w1 = min(n_rows, w0 + kRowsPerBlock);
     uint64_t s = 0;
     uint32_t c = 0;
 #pragma unroll 16
@@ -724,11 +749,11 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     av.x_begin = 0;
     av.ncols = vcols;
     av.n_tiles = (int32_t)vt;
-    av.wave_base = 0;
+    av.row_base = 0;
     as.x_begin = vcols;
     as.ncols = scols;
     as.n_tiles = (int32_t)st;
-    as.wave_base = (int32_t)(vt * kWavesPerBlock);
+    as.row_base = (int32_t)vt;
     av.n_split = choose_split(vt + st, n_frames);
     as.n_split = av.n_split;
     // With a frame split the splits store I/Q partials and
@@ -743,8 +768,9 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     }
 
     const bool stats = frame_sum || frame_sat;
-    const int64_t n_waves = (vt + st) * kWavesPerBlock;
-    const size_t stats_b = stats ? ((sizeof(uint32_t) * 2 * (size_t)n_waves * (size_t)n_frames + 255) / 256) * 256 : 0;
+    // Statistics partial rows: one per vector tile, one per scalar-kernel wave.
+    const int64_t n_rows = vt + st * kWavesPerBlock;
+    const size_t stats_b = stats ? ((sizeof(uint32_t) * 2 * (size_t)n_rows * (size_t)n_frames + 255) / 256) * 256 : 0;
     const size_t iq_b = split ? sizeof(int32_t) * 2 * (size_t)av.n_split * (size_t)npx : 0;
     if (stats_b + iq_b > 0) {
         char *ws = static_cast<char *>(stream_workspace(s, stats_b + iq_b));
@@ -752,7 +778,7 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
         if (stats) {
             uint32_t *ps = reinterpret_cast<uint32_t *>(ws);
             av.part_sum = as.part_sum = ps;
-            av.part_sat = as.part_sat = ps + (size_t)n_waves * n_frames;
+            av.part_sat = as.part_sat = ps + (size_t)n_rows * n_frames;
         }
         if (split) av.part_iq = as.part_iq = reinterpret_cast<int32_t *>(ws + stats_b);
     }
@@ -783,8 +809,8 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
         QLD_TRY(check_hip(e, "qld_accum_scalar_kernel launch"));
     }
     if (stats) {
-        dim3 g2((unsigned)ceil_div(n_frames, 256), (unsigned)ceil_div(n_waves, kRowsPerBlock));
-        hipLaunchKernelGGL(qld_stats_reduce_kernel, g2, dim3(256), 0, s, av.part_sum, av.part_sat, n_waves,
+        dim3 g2((unsigned)ceil_div(n_frames, 256), (unsigned)ceil_div(n_rows, kRowsPerBlock));
+        hipLaunchKernelGGL(qld_stats_reduce_kernel, g2, dim3(256), 0, s, av.part_sum, av.part_sat, n_rows,
                            n_frames, frame_sum, frame_sat);
         QLD_TRY(check_hip(hipGetLastError(), "qld_stats_reduce_kernel launch"));
     }
