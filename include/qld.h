@@ -24,7 +24,7 @@
  *     Frame t is sampled at lock-in phase (phase0 + t) mod 4.
  *   - The caller owns every buffer it passes; libqld owns the handles it
  *     creates (qld_window, qld_server) and the device memory behind them.
- *   - Batch calls that need scratch memory (per-wave frame statistics, the
+ *   - Batch calls that need scratch memory (frame statistics partials, the
  *     I/Q partials of a frame-split grid, twiddle and reference tables) take
  *     it from a device workspace that libqld keeps per (device, stream) and
  *     grows on demand (hipMalloc; a grow first synchronises that stream).
