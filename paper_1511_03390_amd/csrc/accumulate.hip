@@ -55,7 +55,8 @@ struct AccumArgs {
     int64_t fs_b;          // frame stride, bytes
     int32_t H, W;
     int32_t n_frames;
-    int32_t n_split;       // work-groups per pixel tile; split s takes cycles s, s+n_split, ...
+    int32_t n_split;       // work-groups per split tile; split s takes cycles s, s+n_split, ...
+    int32_t n_full;        // vector kernel: tiles 0 .. n_full-1 are not split (a multiple of kXcds)
     int32_t rot;           // phase of frame 0, mod 4
     int32_t x_begin;       // first column this kernel covers
     int32_t ncols;         // columns it covers (vector kernel: whole lanes only)
@@ -65,7 +66,7 @@ struct AccumArgs {
     uint32_t top;          // 2^bits - 1
     int32_t *I;
     int32_t *Q;
-    int32_t *part_iq;      // n_split > 1: [n_split][2][H*W] I/Q partials, indexed like I/Q
+    int32_t *part_iq;      // n_split > 1: [n_split][2][H*W] I/Q partials of the split tiles, indexed like I/Q
     uint32_t *part_sum;    // [waves][n_frames]
     uint32_t *part_sat;
     // One-shot image (qld_lockin_image): I/Q written, not added (single pass
@@ -382,7 +383,7 @@ __device__ __forceinline__ u32x4 ld16(const uint8_t *p) {
 // MASKED: some lanes of this work-group are past the last vector; they read
 // a valid address and zero what they read.
 template <int ELEM, bool STATS, bool PACKED, bool MASKED>
-__device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split, uint32_t *stats_lds,
+__device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split, int S, uint32_t *stats_lds,
                                          uint32_t *stats_comb) {
     constexpr int kPx = 16 / ELEM;
     const int nvx = a.ncols / kPx;
@@ -394,9 +395,8 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
     const int x0 = a.x_begin + (int)(gc % nvx) * kPx;
     const uint32_t vmask = valid ? 0xffffffffu : 0u;
 
-    // This work-group owns cycles split, split + S, split + 2S, ... (S = n_split),
-    // so all work-groups sweep the stack together.
-    const int64_t S = a.n_split;
+    // This work-group owns cycles split, split + S, split + 2S, ... of its
+    // tile, so all work-groups sweep the stack together.
     const int64_t n_cyc_all = a.n_frames >> 2;
     const int64_t my = split < n_cyc_all ? (n_cyc_all - split + S - 1) / S : 0;
     const int64_t fs = a.fs_b;
@@ -413,7 +413,7 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
         st.lds = stats_lds + (threadIdx.x >> 6) * kStatsSlots * kStatsRow;
         st.comb = stats_comb;
         st.split = split;
-        st.S = a.n_split;
+        st.S = S;
     }
     auto load = [&](const uint8_t *q) {
         u32x4 d = ld16(q);
@@ -466,13 +466,13 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
 
     if (!valid) return;
     const int64_t npx = (int64_t)a.H * a.W;
-    int32_t *Ip = a.n_split > 1 ? a.part_iq + 2 * npx * split + y * a.W + x0 : a.I + y * a.W + x0;
-    int32_t *Qp = a.n_split > 1 ? Ip + npx : a.Q + y * a.W + x0;
+    int32_t *Ip = S > 1 ? a.part_iq + 2 * npx * split + y * a.W + x0 : a.I + y * a.W + x0;
+    int32_t *Qp = S > 1 ? Ip + npx : a.Q + y * a.W + x0;
 #pragma unroll
     for (int k = 0; k < kPx; ++k) {
         int32_t oi, oq;
         rotate_iq(a.rot, acc.I[k], acc.Q[k], oi, oq);
-        if (a.n_split > 1) {
+        if (S > 1) {
             Ip[k] = oi;
             Qp[k] = oq;
         } else {
@@ -484,12 +484,21 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
     }
 }
 
-__device__ __forceinline__ void tile_and_split(const AccumArgs &a, int b, int &tile, int &split) {
-    // Work unit -> (pixel tile, frame chunk), chunks of a tile on one XCD.
-    const int xcd = b % kXcds;
-    const int q = b / kXcds;
-    split = q % a.n_split;
-    tile = (q / a.n_split) * kXcds + xcd;
+__device__ __forceinline__ void tile_and_split(const AccumArgs &a, int b, int &tile, int &split, int &S) {
+    // Work unit -> (pixel tile, frame chunk), chunks of a tile on one XCD:
+    // units below n_full are whole tiles; after them each tile is split S ways.
+    if (b < a.n_full) {
+        tile = b;
+        split = 0;
+        S = 1;
+        return;
+    }
+    const int r = b - a.n_full;
+    const int xcd = r % kXcds;
+    const int q = r / kXcds;
+    S = a.n_split;
+    split = q % S;
+    tile = a.n_full + (q / S) * kXcds + xcd;
 }
 
 template <int ELEM, bool STATS, bool PACKED>
@@ -506,11 +515,11 @@ __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
     // Persistent grid (a multiple of kXcds work-groups): work-group b takes
     // units b, b + gridDim.x, ..., all on its own XCD.
     for (int u = blockIdx.x; u < a.n_units; u += gridDim.x) {
-        int tile, split;
-        tile_and_split(a, u, tile, split);
+        int tile, split, S;
+        tile_and_split(a, u, tile, split, S);
         if (tile >= a.n_tiles) continue;
-        if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split, lds, comb);
-        else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, lds, comb);
+        if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split, S, lds, comb);
+        else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, S, lds, comb);
     }
 }
 
@@ -520,8 +529,8 @@ __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
 template <int ELEM, bool STATS>
 __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
     clear_stats_once(a);
-    int tile, split;
-    tile_and_split(a, blockIdx.x, tile, split);
+    int tile, split, S_unit;
+    tile_and_split(a, blockIdx.x, tile, split, S_unit);   // n_full = 0 here: S_unit = n_split
     if (tile >= a.n_tiles) return;
     const int64_t n_px = (int64_t)a.ncols * a.H;
     const int64_t g = (int64_t)tile * kBlock + threadIdx.x;
@@ -616,12 +625,13 @@ __global__ __launch_bounds__(256) void qld_stats_reduce_kernel(const uint32_t *p
 
 // Frame-split images: per pixel, the S split partials added in split order,
 // then I/Q replaced (overwrite) or added to, and the amplitude written when
-// amp is non-NULL.  part: [S][2][npx].
-__global__ __launch_bounds__(256) void qld_iq_reduce_kernel(const int32_t *__restrict__ part, int32_t S, int64_t npx,
-                                                            int32_t overwrite, int32_t *__restrict__ I,
+// amp is non-NULL, for pixels p0 .. npx-1 (those of the split tiles).
+// part: [S][2][npx].
+__global__ __launch_bounds__(256) void qld_iq_reduce_kernel(const int32_t *__restrict__ part, int32_t S, int64_t p0,
+                                                            int64_t npx, int32_t overwrite, int32_t *__restrict__ I,
                                                             int32_t *__restrict__ Q, float *__restrict__ amp) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
+    for (int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
         int32_t si = 0, sq = 0;
         for (int32_t k = 0; k < S; ++k) {
             si += part[2 * npx * k + p];
@@ -664,9 +674,11 @@ hipError_t launch_scalar(const AccumArgs &a, int grid, hipStream_t s) {
 // front); at 2160 x 2160 x 800 without statistics (2279 tiles, up to 8 groups
 // per CU resident when each tile had its own group) the cap gains 3%.  With
 // fewer tiles than work-groups a frame split fills the grid (at least 16
-// cycles per unit).  Splitting larger images to even out the rounds (2279
-// tiles on 512 groups: 5 rounds, the last 45% full; 9 half rounds split in
-// two) measured no faster: the partials' reduction costs what the tail did.
+// cycles per unit).  Splitting every tile of a larger image to even out the
+// rounds (2279 tiles on 512 groups: 5 rounds, the last 45% full; 9 half
+// rounds split in two) measured no faster, the partials' reduction costing
+// what the tail did; splitting only the tiles of the last round (see
+// accumulate_impl) gains 2-4% at 2160 x 2160 x 800.
 #ifndef QLD_ACCUM_BLOCKS_PER_CU
 #define QLD_ACCUM_BLOCKS_PER_CU 2
 #endif
@@ -756,11 +768,29 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     as.row_base = (int32_t)vt;
     av.n_split = choose_split(vt + st, n_frames);
     as.n_split = av.n_split;
+    // Tail of the persistent grid: with more tiles than work-groups and no
+    // scalar columns (the vector lanes then cover the pixels in flat order),
+    // the tiles past the last whole round are split over the frames so that
+    // round ends sooner; only their pixels take the partials' reduction.
+    // 2160 x 2160: 2279 tiles on 512 work-groups = 4 rounds + 231 tiles split
+    // 2 ways (4.5 rounds instead of 5).
+    int64_t p_split = 0;                    // first pixel of the split tiles
+    if (st == 0 && av.n_split == 1) {
+        const int64_t G = accum_grid_cap();
+        const int64_t full = (vt / G) * G, rest = vt - full;
+        const int64_t s2 = rest > 0 ? std::min<int64_t>(G / rest, std::max<int64_t>(1, (n_frames / 4) / 16)) : 1;
+        if (full > 0 && s2 >= 2) {
+            av.n_full = (int32_t)full;
+            av.n_split = (int32_t)s2;
+            p_split = full * kBlock * lw;
+        }
+    }
     // With a frame split the splits store I/Q partials and
     // qld_iq_reduce_kernel adds them (and writes amp); without one the
-    // accumulation kernel's epilogue does both.
+    // accumulation kernel's epilogue does both (for the whole tiles of a
+    // split tail too).
     const bool split = av.n_split > 1;
-    if (!split) av.amp = as.amp = amp;
+    av.amp = as.amp = amp;
     // Only the first kernel launched clears the statistics.
     if (overwrite && (frame_sum || frame_sat)) {
         if (vt > 0) av.clear_n = n_frames;
@@ -784,7 +814,7 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     }
     // 16-bit partial sums hold at least two cycles for data of up to 14 bits.
     const bool packed = eb == 1 || top <= 16383;
-    const int64_t uv = ceil_div(vt, kXcds) * kXcds * av.n_split;
+    const int64_t uv = av.n_full + ceil_div(vt - av.n_full, kXcds) * kXcds * av.n_split;
     const int64_t gs = ceil_div(st, kXcds) * kXcds * as.n_split;
     if (uv > 0x7fffffff || gs > 0x7fffffff) {
         set_error("grid too large");
@@ -815,9 +845,9 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
         QLD_TRY(check_hip(hipGetLastError(), "qld_stats_reduce_kernel launch"));
     }
     if (split) {
-        const int64_t blocks = std::min<int64_t>(ceil_div(npx, 256), 16ll * device_cu_count());
-        hipLaunchKernelGGL(qld_iq_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, av.part_iq, av.n_split, npx,
-                           overwrite ? 1 : 0, I, Q, overwrite ? amp : nullptr);
+        const int64_t blocks = std::min<int64_t>(ceil_div(npx - p_split, 256), 16ll * device_cu_count());
+        hipLaunchKernelGGL(qld_iq_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, av.part_iq, av.n_split,
+                           p_split, npx, overwrite ? 1 : 0, I, Q, overwrite ? amp : nullptr);
         QLD_TRY(check_hip(hipGetLastError(), "qld_iq_reduce_kernel launch"));
     }
     return QLD_OK;

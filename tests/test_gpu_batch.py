@@ -126,7 +126,10 @@ def test_full_range_16bit_and_overflow_edge():
                                                (130, 520, 2052, 12, 1),
                                                # 300 tiles split in two: 608 units on 512
                                                # work-groups (some take two units)
-                                               (256, 300, 2048, 12, 2)])
+                                               (256, 300, 2048, 12, 2),
+                                               # 600 tiles: one whole round of 512, the other 88
+                                               # split 4 ways (partials from row 512 on)
+                                               (262, 600, 2048, 12, 1)])
 def test_lockin_image_overwrites_and_matches_accumulate(T, H, W, bits, phase0):
     """qld_lockin_image (one pass: I/Q, amplitude and statistics overwritten)
     on garbage-filled outputs equals clearing them, qld_accumulate and
