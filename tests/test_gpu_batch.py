@@ -63,6 +63,10 @@ CASES = [
     (np.uint8, 33, 7, 31, 1, 1, 8, 0),
     (np.uint8, 2000, 8, 48, 16, 2, 8, 0),
     (np.uint8, 9, 13, 17, 0, 0, 8, 3),
+    # More tiles than work-groups with a frame-split tail: u8 (16 pixels per
+    # lane, 550 tiles), and u16 with padded rows (600 tiles).
+    (np.uint8, 130, 1100, 2048, 0, 1, 8, 0),
+    (np.uint16, 134, 600, 2048, 8, 3, 12, 0),
 ]
 
 
