@@ -23,6 +23,10 @@
 // thresholds; a binary search inside the bracket finishes it.  Brackets hold
 // at most a few thresholds except in the outermost sub-buckets (probability
 // 2^-16 each), so the lanes of a wave rarely wait on a long search.
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+
 #include "qld_internal.hpp"
 
 namespace qld {
@@ -32,7 +36,7 @@ constexpr int kTableMax = 2048;     // thresholds per rate (lambda up to ~6900)
 constexpr int kGuide = 1024;
 constexpr int kSub = 256;           // sub-guide entries over [0, 2^24) and [2^32 - 2^24, 2^32)
 constexpr uint32_t kHighStart = 0xFF000000u;
-constexpr int kBlock = 1024;     // one work-group per CU (the eight tables take 86 KB of LDS)
+constexpr int kBlock = 1024;     // 16 waves; two work-groups per CU where the tables fit twice in LDS
 constexpr double kRateMax = 6000.0;  // tables of at most kTableMax thresholds
 
 struct Table {
@@ -42,6 +46,18 @@ struct Table {
     uint16_t hguide[kSub];          // #{thr <= 2^32 - 2^24 + i 2^16}
     uint32_t thr[kTableMax];
 };
+// The part of a table before its thresholds; in LDS the eight headers come
+// first, then the eight threshold arrays at a stride of the launch's largest n.
+constexpr int kHeadBytes = (int)offsetof(Table, thr);
+static_assert(kHeadBytes % 4 == 0, "header copied in words");
+
+// Thresholds of a rate's table: the table size of build_tables_kernel.
+int32_t table_size(double lam) {
+    const int32_t m = (int32_t)std::floor(lam);
+    const int32_t w = (int32_t)std::ceil(12.0 * std::sqrt(lam)) + 10;
+    const int32_t lo = m - w < 0 ? 0 : m - w;
+    return m + w - lo;
+}
 
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                               uint32_t k1, uint32_t out[4]) {
@@ -127,6 +143,7 @@ struct GenArgs {
     const Table *tables;      // [n][8]: (mask state, phase)
     int32_t n_tiles, H, W, M_S, M_L;
     int32_t blocks_per_tile;
+    int32_t thr_stride;       // LDS words per threshold array (>= every table's n)
     uint32_t tile0, key0, key1;
     uint32_t top;
     int32_t *I_S, *Q_S, *I_L, *Q_L;
@@ -136,7 +153,7 @@ struct GenArgs {
 // X(u) = lo + #{k : thr[k] <= u}.  The count lies between the guide entries of
 // u's bucket and of the next bucket (thresholds are non-decreasing); a binary
 // search between them finishes it.
-__device__ __forceinline__ int32_t invert(const Table *__restrict__ T, uint32_t u) {
+__device__ __forceinline__ int32_t invert(const Table *__restrict__ T, const uint32_t *__restrict__ thr, uint32_t u) {
     int32_t a, b;
     if (u < (1u << 24)) {
         const uint32_t i = u >> 16;
@@ -153,7 +170,7 @@ __device__ __forceinline__ int32_t invert(const Table *__restrict__ T, uint32_t 
     }
     while (a < b) {
         const int32_t mid = (a + b) >> 1;
-        if (T->thr[mid] <= u) a = mid + 1;
+        if (thr[mid] <= u) a = mid + 1;
         else b = mid;
     }
     return T->lo + a;
@@ -169,17 +186,24 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // copied to LDS first.
 __global__ __launch_bounds__(kBlock) void gen_pairs_kernel(GenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    Table *lt = reinterpret_cast<Table *>(smem);
     const int tile = blockIdx.x / a.blocks_per_tile;
     const int part = blockIdx.x % a.blocks_per_tile;
     if (tile >= a.n_tiles) return;
+    // LDS: eight table headers (lo, n, guides), then eight threshold arrays.
+    uint32_t *lthr = reinterpret_cast<uint32_t *>(smem + 8 * kHeadBytes);
     {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.tables + (int64_t)tile * 8);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(lt);
-        const int nw = (int)(8 * sizeof(Table) / 4);
-        for (int i = threadIdx.x; i < nw; i += kBlock) dst[i] = src[i];
+        const Table *src = a.tables + (int64_t)tile * 8;
+        constexpr int hw = kHeadBytes / 4;
+        for (int i = threadIdx.x; i < 8 * hw; i += kBlock)
+            reinterpret_cast<uint32_t *>(smem)[i] = reinterpret_cast<const uint32_t *>(src + i / hw)[i % hw];
+        for (int i = threadIdx.x; i < 8 * a.thr_stride; i += kBlock) {
+            const int j = i / a.thr_stride, k = i % a.thr_stride;
+            lthr[i] = k < src[j].n ? src[j].thr[k] : 0xFFFFFFFFu;
+        }
     }
     __syncthreads();
+    // Table j's header (only lo, n and the guides are read through it).
+    auto head = [&](int j) { return reinterpret_cast<const Table *>(smem + j * kHeadBytes); };
     const int64_t npx = (int64_t)a.H * a.W;
     const int64_t per = ceil_div(npx, a.blocks_per_tile);
     const int64_t p0 = (int64_t)part * per, p1 = min(npx, p0 + per);
@@ -188,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void gen_pairs_kernel(GenArgs a) {
         const int64_t p = pb + threadIdx.x;
         const bool valid = p < p1;
         const int mk = valid ? (a.mask[(int64_t)tile * npx + p] ? 1 : 0) : 0;
-        const Table *T0 = lt + mk * 4;
+        const int j0 = mk * 4;
         int32_t I = 0, Q = 0, Is = 0, Qs = 0;
         uint32_t s32 = 0;
         if (valid) {
@@ -197,7 +221,8 @@ __global__ __launch_bounds__(kBlock) void gen_pairs_kernel(GenArgs a) {
                 philox4x32_10((uint32_t)p, (uint32_t)c, a.tile0 + (uint32_t)tile, 0u, a.key0, a.key1, r);
                 int32_t x[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) x[j] = min(invert(T0 + j, r[j]), (int32_t)a.top);
+                for (int j = 0; j < 4; ++j)
+                    x[j] = min(invert(head(j0 + j), lthr + (j0 + j) * a.thr_stride, r[j]), (int32_t)a.top);
                 I += x[0] - x[2];
                 Q += x[1] - x[3];
                 s32 += (uint32_t)(x[0] + x[1] + x[2] + x[3]);
@@ -297,7 +322,11 @@ extern "C" qld_status qld_gen_pairs(const uint8_t *mask, const double *rates_hos
     a.Q_L = Q_L;
     a.sum_S = reinterpret_cast<unsigned long long *>(sum_S);
     a.sum_L = reinterpret_cast<unsigned long long *>(sum_L);
+    int32_t max_n = 1;
+    for (int64_t i = 0; i < (int64_t)n_tiles * 8; ++i) max_n = std::max(max_n, table_size(rates_host[i]));
+    a.thr_stride = std::min(kTableMax, max_n + 4);   // + 4: margin over the host's recomputation of n
+    const size_t lds = (size_t)8 * kHeadBytes + (size_t)8 * a.thr_stride * 4;
     const int64_t grid = (int64_t)n_tiles * a.blocks_per_tile;
-    hipLaunchKernelGGL(gen_pairs_kernel, dim3((unsigned)grid), dim3(kBlock), 8 * sizeof(Table), s, a);
+    hipLaunchKernelGGL(gen_pairs_kernel, dim3((unsigned)grid), dim3(kBlock), lds, s, a);
     return check_hip(hipGetLastError(), "gen_pairs_kernel launch");
 }
