@@ -117,10 +117,26 @@ __global__ __launch_bounds__(256) void nrmse_part_kernel(const float *__restrict
 __global__ void nrmse_final_kernel(const double *__restrict__ part, int chunks, int B, float *__restrict__ out) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
+    // Chunks in order; loads issued 16 chunks at a time.
+    const double *pb = part + (int64_t)b * chunks * 2;
     double e = 0.0, r = 0.0;
-    for (int c = 0; c < chunks; ++c) {
-        e += part[((int64_t)b * chunks + c) * 2];
-        r += part[((int64_t)b * chunks + c) * 2 + 1];
+    int c = 0;
+    for (; c + 16 <= chunks; c += 16) {
+        double ve[16], vr[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            ve[i] = pb[(int64_t)(c + i) * 2];
+            vr[i] = pb[(int64_t)(c + i) * 2 + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            e += ve[i];
+            r += vr[i];
+        }
+    }
+    for (; c < chunks; ++c) {
+        e += pb[(int64_t)c * 2];
+        r += pb[(int64_t)c * 2 + 1];
     }
     out[b] = r > 0.0 ? (float)sqrt(e / r) : 0.0f;
 }
