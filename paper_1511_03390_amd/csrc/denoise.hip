@@ -610,9 +610,19 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float *__restric
     const int c = blockIdx.x * 64 + (threadIdx.x & 63);
     const int g = threadIdx.x >> 6;
     const int r0 = blockIdx.y * 64, r1 = min(R, r0 + 64);
+    // Rows r0 + g, r0 + g + 4, ... in order; their loads issued together.
     float s = 0.f;
-    if (c < n)
-        for (int r = r0 + g; r < r1; r += 4) s += in[(int64_t)r * n + c];
+    if (c < n) {
+        int r = r0 + g;
+        for (; r + 4 * 15 < r1; r += 4 * 16) {
+            float v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = in[(int64_t)(r + 4 * i) * n + c];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) s += v[i];
+        }
+        for (; r < r1; r += 4) s += in[(int64_t)r * n + c];
+    }
     red[g][threadIdx.x & 63] = s;
     __syncthreads();
     if (g == 0 && c < n) out[(int64_t)blockIdx.y * n + c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
