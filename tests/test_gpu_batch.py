@@ -88,6 +88,33 @@ def test_random_shapes(dt, T, H, W, pextra, phase0, bits, mis):
                          fsat.cpu().numpy(), phase0, bits)
 
 
+def test_accumulate_onto_running_sums_with_split_tail():
+    # 600 tiles: the first 512 add into I/Q in the kernel, the split tail in
+    # the partials' reduction; accumulating a stack onto running sums (two
+    # chunks with the phase carried over, on top of garbage-free but non-zero
+    # I/Q) equals the oracle's sums plus the starting values.
+    need_gpu()
+    rng = np.random.default_rng(29)
+    T, H, W = 258, 600, 2048
+    f = rng.integers(0, 4096, size=(T, H, W)).astype(np.uint16)
+    dev = to_dev(f)
+    I0 = rng.integers(-10 ** 6, 10 ** 6, size=(H, W)).astype(np.int32)
+    Q0 = rng.integers(-10 ** 6, 10 ** 6, size=(H, W)).astype(np.int32)
+    I = torch.from_numpy(I0).cuda()
+    Q = torch.from_numpy(Q0).cuda()
+    fsum = torch.zeros(T, dtype=torch.int64, device="cuda")
+    fsat = torch.zeros(T, dtype=torch.int32, device="cuda")
+    qld.accumulate(dev[:130], I, Q, 2, 12, fsum[:130], fsat[:130])
+    qld.accumulate(dev[130:], I, Q, 2 + 130, 12, fsum[130:], fsat[130:])
+    torch.cuda.synchronize()
+    oI, oQ = oracle.qld(f, 2)
+    assert np.array_equal(I.cpu().numpy().astype(np.int64), oI + I0), "I differs"
+    assert np.array_equal(Q.cpu().numpy().astype(np.int64), oQ + Q0), "Q differs"
+    s, n = oracle.frame_stats(f, 12)
+    assert np.array_equal(fsum.cpu().numpy().astype(np.uint64), s)
+    assert np.array_equal(fsat.cpu().numpy().astype(np.uint32), n)
+
+
 def test_chunked_accumulation_equals_whole():
     need_gpu()
     rng = np.random.default_rng(3)
