@@ -107,6 +107,61 @@ def test_target_bias_reduction_closed_form():
     assert t.mean() < 0.45 * plain.mean()
 
 
+def test_normalise_hand_built():
+    # Reading L17: x = (I, Q) / (sigma sqrt(M_S)), sigma^2 = 2 b, b = the mean
+    # sample level over the window's H * W * 4 * M_S samples; scale = sigma / sqrt(M_S).
+    # H = W = 2, M_S = 4: 64 samples summing to 512 give b = 8, sigma = 4, so the
+    # divisor is 4 * 2 = 8 and the scale 4 / 2 = 2.
+    I = np.array([[[8, -16], [24, 0]]])
+    Q = np.array([[[0, 4], [-8, 40]]])
+    x, scale = L.normalise(I, Q, np.array([512]), 4, 2, 2)
+    assert x.shape == (1, 2, 2, 2)
+    assert np.array_equal(x[0, :, :, 0], [[1.0, -2.0], [3.0, 0.0]])
+    assert np.array_equal(x[0, :, :, 1], [[0.0, 0.5], [-1.0, 5.0]])
+    assert np.array_equal(scale, [2.0])
+
+
+def test_normalise_unit_variance_on_signal_free_poisson():
+    # Unmodulated Poisson light of rate lam: each cycle adds S0 - S2 of variance
+    # 2 lam to I (and S1 - S3 to Q), so Var(I) = 2 M lam while the window's mean
+    # level estimates lam: x has unit variance per channel, zero mean, and the
+    # scale equals the standard deviation of I / M.
+    rng = np.random.default_rng(11)
+    lam, M, H, W = 300.0, 16, 128, 128
+    fr = rng.poisson(lam, size=(4 * M, H, W)).astype(np.uint16)
+    I, Q = oracle.qld(fr)
+    x, scale = L.normalise(I[None], Q[None], np.array([int(fr.astype(np.int64).sum())]), M, H, W)
+    for ch in range(2):
+        assert abs(x[0, :, :, ch].var() - 1.0) < 0.03, ch
+        assert abs(x[0, :, :, ch].mean()) < 0.02, ch
+    assert abs((I / M).std() / scale[0] - 1.0) < 0.03
+
+
+def test_target_hand_built():
+    # t = sqrt(max(I^2 + Q^2 - 4 M_L b, 0)) / M_L / scale, b the mean level.
+    # H = 1, W = 2, M_L = 5: 40 samples summing to 4000 give b = 100, so the
+    # noise power is 4 * 5 * 100 = 2000.  (30, 40): sqrt(2500 - 2000) / 5 / 0.5
+    # = sqrt(80); (10, 0): 100 < 2000, clipped to 0.
+    t = L.target(np.array([[[30, 10]]]), np.array([[[40, 0]]]), np.array([4000]), 5, 1, 2, np.array([0.5]))
+    assert t.shape == (1, 1, 2)
+    assert abs(t[0, 0, 0] - math.sqrt(80.0)) < 1e-12 and t[0, 0, 1] == 0.0
+
+
+def test_target_signal_free_closed_form():
+    # Without signal, I and Q are (to a very good approximation) independent
+    # Gaussians of variance 2 M lam, so r^2 = I^2 + Q^2 is 4 M lam times a unit
+    # exponential E, and M^2 t^2 = 4 M lam max(E - 1, 0) with E[max(E - 1, 0)]
+    # = 1/e: mean(t^2) = (4 lam / M) / e.  (Removing 2 M b instead would give
+    # e^-1/2, i.e. 65% more; 8 M b, e^-2.)
+    rng = np.random.default_rng(12)
+    lam, M, H, W = 300.0, 32, 256, 256
+    fr = rng.poisson(lam, size=(4 * M, H, W)).astype(np.uint16)
+    I, Q = oracle.qld(fr)
+    t = L.target(I[None], Q[None], np.array([int(fr.astype(np.int64).sum())]), M, H, W, np.array([1.0]))
+    ratio = float((t ** 2).mean()) / (4 * lam / M / math.e)
+    assert abs(ratio - 1.0) < 0.03, ratio
+
+
 def test_bf16_rounding():
     v = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -7, -2.5, 3.0e38 * 0 + 65504.0])
     r = L.bf16(v)
