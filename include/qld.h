@@ -112,6 +112,11 @@ int64_t qld_frame_stride_hint(int32_t H, int32_t W, int64_t row_pitch, qld_dtype
  *   frame_sat  device uint32 [n_frames] or NULL: frame_sat[t] += number of
  *              samples equal to 2^bits - 1 (clipped pixels break the exact
  *              cancellation of the unmodulated light)
+ * Precondition: every sample is <= 2^bits - 1 (d->bits states the range of
+ * the data, not only of the dtype).  The overflow check below and the 16-bit
+ * partial sums of the fast path rely on it; a larger sample gives undefined
+ * I/Q (and is not counted in frame_sat).  Data of unknown range must be
+ * described with bits = 8 (U8) or 16 (U16).
  * Errors: QLD_E_OVERFLOW if ceil(n_frames/4) * (2^bits - 1) >= 2^31 (the
  * caller must split longer stacks into separate accumulators).  Inputs need
  * no particular alignment; 16-byte aligned base and pitches take the fast
@@ -157,7 +162,8 @@ qld_status dft_bin_baseline(const void *frames, const qld_frame_desc *d, int32_t
 
 /*
  * dft_bin_baseline_f64 -- the same single-bin DFT in double precision, the
- * precision the paper computes in (Methods, computations in double): twiddles
+ * precision the paper computes in (Supplementary Information, "Details of
+ * apparatus": every computation in double precision): twiddles
  * from the exact integer angle rounded to double, multiply-adds in double.
  *   re, im     device double [H][W] (dense, overwritten)
  * Error <= (N + 2) * 2^-53 * sum_n |S_n| per component.  The sample read is
@@ -284,6 +290,16 @@ qld_status qld_fwindow_destroy(qld_fwindow *w);
 /* ------------------------------------------------------------------------ */
 /* Serving: many camera streams, one GPU, continuous batching               */
 /* ------------------------------------------------------------------------ */
+/*
+ * The paper's real-time loop (Supplementary Information, "Timing sequence for
+ * hybrid parallelisation", which also displays a sliding sequence at the
+ * camera rate) hands every camera frame on as it arrives: one thread
+ * takes it from the camera, another copies it to the GPU, a kernel adds it to
+ * the lock-in sums, and the image is refreshed from a sliding window.  The
+ * server below does the same for many cameras at once: submits copy frames to
+ * the device as they arrive, and a scheduler applies every complete cycle of
+ * every stream that is ready in one batched launch.
+ */
 
 typedef struct qld_server qld_server;
 
@@ -320,6 +336,9 @@ typedef struct {
     float gate;                /* LEARNED: the gate's predicted excess NRMSE, NaN
                                   while the short window is not yet full; PLAIN: 0 */
     int32_t learned;           /* 1 if amp is the denoiser's output */
+    int64_t seq;               /* the stream's cycle count when this cycle was
+                                  taken (0, 1, 2, ... over the stream's life);
+                                  see qld_stream_result_valid */
 } qld_result;
 
 /*
@@ -330,6 +349,11 @@ typedef struct {
  *   flags             QLD_SERVER_KEEP_IQ to also keep per-cycle I/Q
  * Starts a scheduler thread (batches every ready cycle of every stream into
  * one launch) and a completion thread (stamps t_done_ns, publishes results).
+ * At most one launch round is on the device at a time (see
+ * qld_server_set_max_inflight): cycles that complete while it runs are
+ * gathered into the next round, so a launch carries the ready cycles of all
+ * streams.  (Supplementary Information, "Timing sequence for hybrid
+ * parallelisation": frames are processed as they arrive.)
  */
 qld_status qld_server_create(size_t hbm_budget_bytes, int32_t out_slots, int32_t flags,
                              qld_server **out);
@@ -341,6 +365,9 @@ size_t qld_server_stream_bytes(const qld_server *s, const qld_frame_desc *d, int
                                int32_t M_short, int32_t mode);
 
 /* Open a stream of dense host frames (d->row_pitch/frame_stride are ignored)
+ * (Supplementary Information, "Timing sequence for hybrid parallelisation":
+ * one camera's frames handed to the GPU; admission by HBM budget is this
+ * library's own)
  * with a window of M_cycles cycles and optionally a short window of M_short
  * (0 = none) cycles sharing the same ring.  mode: QLD_MODE_PLAIN, or
  * QLD_MODE_LEARNED (needs 1 <= M_short <= M_cycles, and a denoiser set with
@@ -372,7 +399,11 @@ typedef struct qld_denoiser qld_denoiser;
 qld_status qld_stream_set_denoiser(qld_server *s, int32_t stream_id, qld_denoiser *dn, float gate_threshold);
 
 /*
- * Submit one frame (host pointer, dense [H][W] of the stream's dtype).  Frame
+ * Submit one frame (host pointer, dense [H][W] of the stream's dtype)
+ * (Supplementary Information, "Timing sequence for hybrid parallelisation":
+ * each camera frame is copied to the GPU as it arrives; here the hand-over
+ * returns a status and no ticket -- the cycle's image is identified by its
+ * stream and camera cycle in qld_stream_poll).  Frame
  * index f has lock-in phase f mod 4; a cycle is the four frames 4m..4m+3.
  * The frame is copied into pinned staging before the call returns, so the
  * caller may reuse its buffer at once.  frame_index must be the previous
@@ -380,14 +411,58 @@ qld_status qld_stream_set_denoiser(qld_server *s, int32_t stream_id, qld_denoise
  * frames are skipped until the next index that is a multiple of 4) and the
  * call returns QLD_E_GAP; a smaller one is rejected (QLD_E_INVAL).  A pending
  * stream returns QLD_E_AGAIN.  Blocks while all staging slots of the stream
- * are in flight (back-pressure).  Thread-safe: one submitting thread per stream.
+ * are in flight (back-pressure); while the server is held (qld_server_hold)
+ * it returns QLD_E_AGAIN instead, having taken nothing (submit the same frame
+ * again later).  Thread-safe: one submitting thread per stream.
  */
 qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const void *host_frame,
                              int64_t frame_index, uint64_t t_arrival_ns);
 
+/*
+ * Submit a whole cycle: the four frames first_frame_index .. +3 (host,
+ * dense [4][H][W]), first_frame_index a multiple of 4 (else QLD_E_INVAL).
+ * The same as four qld_stream_submit calls, with one copy into pinned
+ * staging and one host-to-device copy instead of four.  A first_frame_index
+ * beyond the next expected frame resets the window (a partial cycle from
+ * single-frame submits is dropped) and returns QLD_E_GAP, the cycle itself
+ * being taken as the first of the new window.  Back-pressure, hold and
+ * threading as qld_stream_submit.  (Same passage as qld_stream_submit.)
+ */
+qld_status qld_stream_submit_cycle(qld_server *s, int32_t stream_id, const void *host_frames,
+                                   int64_t first_frame_index, uint64_t t_arrival_ns);
+
+/*
+ * Hold (on != 0) or release (on = 0) the scheduler.  While held nothing is
+ * launched; submits still copy frames into free staging slots.  Releasing
+ * launches every staged cycle of every stream together (one launch per
+ * sample format).  qld_server_drain, qld_stream_close and qld_server_destroy
+ * release a hold.  For callers that gather a known set of cycles into one
+ * launch (and for tests of batching).
+ */
+qld_status qld_server_hold(qld_server *s, int32_t on);
+
+/*
+ * Launch rounds the scheduler may have on the device at once, 1..64
+ * (default 1).  With 1 every cycle that lands while a round runs waits for
+ * the next round, which then carries them all; larger values launch sooner
+ * and batch less.  QLD_E_INVAL outside the range.
+ */
+qld_status qld_server_set_max_inflight(qld_server *s, int32_t n);
+
 /* Completed images, oldest first, at most max; *n_out set.  Non-blocking.
- * Returns QLD_E_DEVICE if a launch has failed. */
+ * Returns QLD_E_DEVICE if a launch has failed.  (Supplementary Information,
+ * "Timing sequence for hybrid parallelisation": the processed image is handed
+ * on for display as soon as it is formed.) */
 qld_status qld_stream_poll(qld_server *s, qld_result *out, int32_t max, int32_t *n_out);
+
+/*
+ * *valid = 1 while the output slot of a polled result still holds that
+ * cycle's image (and I/Q), 0 once a later cycle of the stream has been
+ * launched into the slot or the stream has closed.  A result's slot is
+ * reused out_slots cycles later, so a slow reader can find a newer image
+ * there: copy the image, then call this; 1 means the copy is this cycle's.
+ */
+qld_status qld_stream_result_valid(qld_server *s, const qld_result *res, int32_t *valid);
 
 /* Device I/Q and short-window I/Q of a polled result, each NULL when not
  * kept: the long window's with QLD_SERVER_KEEP_IQ, the short window's with

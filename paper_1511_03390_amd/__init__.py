@@ -38,8 +38,9 @@ EXPORTS = (
     "qld_fwindow_bytes", "qld_fwindow_create", "qld_fwindow_update", "qld_fwindow_reset", "qld_fwindow_info",
     "qld_fwindow_destroy",
     "qld_server_create", "qld_server_stream_bytes", "qld_stream_open", "qld_stream_state",
-    "qld_stream_set_denoiser", "qld_stream_submit", "qld_stream_poll", "qld_stream_result_iq", "qld_server_drain",
-    "qld_stream_close", "qld_server_destroy", "qld_server_stats",
+    "qld_stream_set_denoiser", "qld_stream_submit", "qld_stream_submit_cycle", "qld_server_hold",
+    "qld_server_set_max_inflight", "qld_stream_poll", "qld_stream_result_valid", "qld_stream_result_iq",
+    "qld_server_drain", "qld_stream_close", "qld_server_destroy", "qld_server_stats",
     "qld_status_str", "qld_last_error", "qld_version", "qld_time_next_kernel", "qld_frame_stride_hint", "qld_read_probe",
     "qld_gen_pairs", "qld_denoise_prepare", "qld_denoise_target", "qld_clean_amplitude",
     "qld_judge_nrmse", "qld_judge_cnr", "qld_denoiser_param_count", "qld_denoiser_create",
@@ -64,7 +65,8 @@ class Result(ctypes.Structure):
     _fields_ = [("stream_id", ctypes.c_int32), ("warm", ctypes.c_int32), ("cycle", ctypes.c_int64),
                 ("t_arrival_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
                 ("amp", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
-                ("amp_plain", ctypes.c_void_p), ("gate", ctypes.c_float), ("learned", ctypes.c_int32)]
+                ("amp_plain", ctypes.c_void_p), ("gate", ctypes.c_float), ("learned", ctypes.c_int32),
+                ("seq", ctypes.c_int64)]
 
 
 _vp, _i32, _i64, _u64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
@@ -106,6 +108,10 @@ _sig("qld_denoiser_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTE
 _sig("qld_stream_open", ctypes.c_int, _vp, _dp, _i32, _i32, _i32, ctypes.POINTER(_i32))
 _sig("qld_stream_state", ctypes.c_int, _vp, _i32, ctypes.POINTER(_i32))
 _sig("qld_stream_submit", ctypes.c_int, _vp, _i32, _vp, _i64, _u64)
+_sig("qld_stream_submit_cycle", ctypes.c_int, _vp, _i32, _vp, _i64, _u64)
+_sig("qld_server_hold", ctypes.c_int, _vp, _i32)
+_sig("qld_server_set_max_inflight", ctypes.c_int, _vp, _i32)
+_sig("qld_stream_result_valid", ctypes.c_int, _vp, ctypes.POINTER(Result), ctypes.POINTER(_i32))
 _sig("qld_stream_poll", ctypes.c_int, _vp, ctypes.POINTER(Result), _i32, ctypes.POINTER(_i32))
 _sig("qld_stream_result_iq", ctypes.c_int, _vp, ctypes.POINTER(Result), ctypes.POINTER(_vp),
      ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp))
@@ -449,6 +455,26 @@ class Server:
             raise ValueError("frame must be C-contiguous")
         return _check(_lib.qld_stream_submit(self._h, int(sid), ctypes.c_void_p(frame.ctypes.data), int(index),
                                              int(t_arrival_ns)), "qld_stream_submit", ok=(OK, E_GAP, E_AGAIN))
+
+    def submit_cycle(self, sid, frames, first_index, t_arrival_ns):
+        """frames: host numpy array [4][H][W] (uint8 / uint16), C-contiguous, the
+        frames first_index .. first_index + 3 (first_index a multiple of 4)."""
+        if not frames.flags["C_CONTIGUOUS"]:
+            raise ValueError("frames must be C-contiguous")
+        return _check(_lib.qld_stream_submit_cycle(self._h, int(sid), ctypes.c_void_p(frames.ctypes.data),
+                                                   int(first_index), int(t_arrival_ns)),
+                      "qld_stream_submit_cycle", ok=(OK, E_GAP, E_AGAIN))
+
+    def hold(self, on=True):
+        _check(_lib.qld_server_hold(self._h, 1 if on else 0), "qld_server_hold")
+
+    def set_max_inflight(self, n):
+        _check(_lib.qld_server_set_max_inflight(self._h, int(n)), "qld_server_set_max_inflight")
+
+    def result_valid(self, res):
+        v = _i32()
+        _check(_lib.qld_stream_result_valid(self._h, ctypes.byref(res), ctypes.byref(v)), "qld_stream_result_valid")
+        return bool(v.value)
 
     def poll(self, max_results=256):
         buf = (Result * max_results)()

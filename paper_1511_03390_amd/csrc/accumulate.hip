@@ -66,7 +66,8 @@ struct AccumArgs {
     uint32_t top;          // 2^bits - 1
     int32_t *I;
     int32_t *Q;
-    int32_t *part_iq;      // n_split > 1: [n_split][2][H*W] I/Q partials of the split tiles, indexed like I/Q
+    int32_t *part_iq;      // n_split > 1: [n_split][2][part_n] I/Q partials of pixels part_p0 .. part_p0+part_n-1
+    int64_t part_p0, part_n;  //   (the pixels of the split tiles, in I/Q order)
     uint32_t *part_sum;    // [waves][n_frames]
     uint32_t *part_sat;
     // One-shot image (qld_lockin_image): I/Q written, not added (single pass
@@ -382,9 +383,14 @@ __device__ __forceinline__ u32x4 ld16(const uint8_t *p) {
 // (fold_every * (2^bits - 1) <= 32767); otherwise every cycle goes to int32.
 // MASKED: some lanes of this work-group are past the last vector; they read
 // a valid address and zero what they read.
+// stats_parity: the comb half of the work-group's next statistics flush.  It
+// is carried from one persistent-grid unit to the next (every wave of the
+// work-group flushes equally often, so it is uniform): a unit that ends on an
+// odd number of flushes must not start the next unit on the half whose read
+// by wave 0 only the next flush's barrier orders.
 template <int ELEM, bool STATS, bool PACKED, bool MASKED>
 __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split, int S, uint32_t *stats_lds,
-                                         uint32_t *stats_comb) {
+                                         uint32_t *stats_comb, int &stats_parity) {
     constexpr int kPx = 16 / ELEM;
     const int nvx = a.ncols / kPx;
     const int64_t n_vec = (int64_t)nvx * a.H;
@@ -412,6 +418,7 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
         st.row = ((int64_t)a.row_base + tile) * a.n_frames;
         st.lds = stats_lds + (threadIdx.x >> 6) * kStatsSlots * kStatsRow;
         st.comb = stats_comb;
+        st.parity = stats_parity;
         st.split = split;
         st.S = S;
     }
@@ -462,12 +469,12 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
     }
     if constexpr (STATS) {
         if (st.slot) st.flush();
+        stats_parity = st.parity;
     }
 
     if (!valid) return;
-    const int64_t npx = (int64_t)a.H * a.W;
-    int32_t *Ip = S > 1 ? a.part_iq + 2 * npx * split + y * a.W + x0 : a.I + y * a.W + x0;
-    int32_t *Qp = S > 1 ? Ip + npx : a.Q + y * a.W + x0;
+    int32_t *Ip = S > 1 ? a.part_iq + 2 * a.part_n * split + (y * a.W + x0 - a.part_p0) : a.I + y * a.W + x0;
+    int32_t *Qp = S > 1 ? Ip + a.part_n : a.Q + y * a.W + x0;
 #pragma unroll
     for (int k = 0; k < kPx; ++k) {
         int32_t oi, oq;
@@ -514,12 +521,14 @@ __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
     }
     // Persistent grid (a multiple of kXcds work-groups): work-group b takes
     // units b, b + gridDim.x, ..., all on its own XCD.
+    int parity = 0;
     for (int u = blockIdx.x; u < a.n_units; u += gridDim.x) {
         int tile, split, S;
         tile_and_split(a, u, tile, split, S);
         if (tile >= a.n_tiles) continue;
-        if ((int64_t)(tile + 1) * kBlock <= n_vec) vec_body<ELEM, STATS, PACKED, false>(a, tile, split, S, lds, comb);
-        else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, S, lds, comb);
+        if ((int64_t)(tile + 1) * kBlock <= n_vec)
+            vec_body<ELEM, STATS, PACKED, false>(a, tile, split, S, lds, comb, parity);
+        else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, S, lds, comb, parity);
     }
 }
 
@@ -585,10 +594,9 @@ __global__ __launch_bounds__(kBlock) void qld_accum_scalar_kernel(AccumArgs a) {
     int32_t oi, oq;
     rotate_iq(a.rot, I, Q, oi, oq);
     if (a.n_split > 1) {
-        const int64_t npx = (int64_t)a.H * a.W;
-        int32_t *Ip = a.part_iq + 2 * npx * split + y * a.W + x;
+        int32_t *Ip = a.part_iq + 2 * a.part_n * split + (y * a.W + x - a.part_p0);
         Ip[0] = oi;
-        Ip[npx] = oq;
+        Ip[a.part_n] = oq;
     } else {
         const int64_t o = y * a.W + x;
         const int32_t ni = a.overwrite ? oi : add_wrap(a.I[o], oi), nq = a.overwrite ? oq : add_wrap(a.Q[o], oq);
@@ -626,16 +634,17 @@ __global__ __launch_bounds__(256) void qld_stats_reduce_kernel(const uint32_t *p
 // Frame-split images: per pixel, the S split partials added in split order,
 // then I/Q replaced (overwrite) or added to, and the amplitude written when
 // amp is non-NULL, for pixels p0 .. npx-1 (those of the split tiles).
-// part: [S][2][npx].
+// part: [S][2][npx - p0].
 __global__ __launch_bounds__(256) void qld_iq_reduce_kernel(const int32_t *__restrict__ part, int32_t S, int64_t p0,
                                                             int64_t npx, int32_t overwrite, int32_t *__restrict__ I,
                                                             int32_t *__restrict__ Q, float *__restrict__ amp) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n = npx - p0;
     for (int64_t p = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
         int32_t si = 0, sq = 0;
         for (int32_t k = 0; k < S; ++k) {
-            si += part[2 * npx * k + p];
-            sq += part[2 * npx * k + npx + p];
+            si += part[2 * n * k + (p - p0)];
+            sq += part[2 * n * k + n + (p - p0)];
         }
         if (!overwrite) {
             si = add_wrap(si, I[p]);
@@ -801,7 +810,9 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     // Statistics partial rows: one per vector tile, one per scalar-kernel wave.
     const int64_t n_rows = vt + st * kWavesPerBlock;
     const size_t stats_b = stats ? ((sizeof(uint32_t) * 2 * (size_t)n_rows * (size_t)n_frames + 255) / 256) * 256 : 0;
-    const size_t iq_b = split ? sizeof(int32_t) * 2 * (size_t)av.n_split * (size_t)npx : 0;
+    av.part_p0 = as.part_p0 = p_split;
+    av.part_n = as.part_n = npx - p_split;
+    const size_t iq_b = split ? sizeof(int32_t) * 2 * (size_t)av.n_split * (size_t)(npx - p_split) : 0;
     if (stats_b + iq_b > 0) {
         char *ws = static_cast<char *>(stream_workspace(s, stats_b + iq_b));
         if (!ws) return QLD_E_NOMEM;

@@ -8,7 +8,11 @@
 //     pinned staging and enqueue its host-to-device copy on the copy stream;
 //   * a scheduler thread: takes every ready cycle of every admitted stream
 //     and applies them in ONE launch of the batched window kernel (streams of
-//     different sizes share the launch), after waiting on the copy events;
+//     different sizes share the launch), after waiting on the copy events.
+//     At most max_inflight launch rounds are on the device at once (one by
+//     default): cycles that land while a round runs are gathered into the
+//     next one, so under load a launch carries the cycles of several
+//     streams (continuous batching) instead of one launch per cycle;
 //   * a completion thread: waits for each launch's event, stamps the host
 //     time and publishes the images (qld_stream_poll).
 // A LEARNED stream (not in the paper) also runs its denoiser on the short
@@ -38,8 +42,10 @@ namespace qld {
 namespace {
 
 constexpr int kStageCycles = 4;      // staged cycles per stream on the device
-constexpr int kPinnedFrames = 8;     // pinned host frame buffers per stream
+constexpr int kPinnedCycles = 2;     // pinned host cycle buffers (4 frames each) per stream
+constexpr int kPinnedFrames = 4 * kPinnedCycles;
 constexpr int kMaxCyclesPerJob = 8;  // cycles of one stream applied per launch
+constexpr int kMaxInflight = 64;
 
 uint64_t now_ns() {
     timespec ts;
@@ -75,11 +81,10 @@ struct StreamRec {
     float *gate_dev = nullptr;      // [out_slots]
     float *gate_host = nullptr;     // pinned [out_slots]
     int ring = 0;
-    uint8_t *pin = nullptr;         // [kPinnedFrames][H][W]
+    uint8_t *pin = nullptr;         // [kPinnedCycles][4][H][W]: frame (k, phase) at k % kPinnedCycles
     size_t frame_bytes = 0;
-    hipEvent_t pin_ev[kPinnedFrames] = {};
+    hipEvent_t pin_ev[kPinnedFrames] = {};   // last copy out of each pinned frame
     bool pin_used[kPinnedFrames] = {};
-    int pin_next = 0;
     hipEvent_t slot_ev[kStageCycles] = {};
     uint64_t slot_tarr[kStageCycles] = {};
     int64_t slot_cam_cycle[kStageCycles] = {};
@@ -119,6 +124,7 @@ struct LearnedJob {
 struct Inflight {
     hipEvent_t ev;
     std::vector<CycleRef> cycles;
+    bool round_end;     // last launch of a scheduler round
 };
 
 }  // namespace
@@ -141,6 +147,9 @@ struct qld_server {
     std::deque<qld::Inflight> inflight;
     std::vector<hipEvent_t> free_events;
     bool stop = false;
+    bool hold = false;       // qld_server_hold: launch nothing while set
+    int max_inflight = 1;    // launch rounds on the device at once
+    int n_inflight = 0;
     std::thread sched, complete;
     int64_t batches = 0, cycles = 0;
     int32_t max_streams = 0;
@@ -320,12 +329,19 @@ void scheduler_loop(qld_server *srv) {
     std::unique_lock<std::mutex> lk(srv->mu);
     size_t rr = 0;  // round-robin start for fairness when a launch is full
     while (true) {
+        // Launch when something is ready, unless held or the device already
+        // has max_inflight rounds: what lands meanwhile joins the next round.
         srv->cv_sched.wait(lk, [&] {
             if (srv->stop) return true;
+            if (srv->hold || srv->n_inflight >= srv->max_inflight) return false;
             for (auto &kv : srv->streams)
                 if (!kv.second->ready.empty()) return true;
             return false;
         });
+        if (srv->hold || srv->n_inflight >= srv->max_inflight) {
+            if (srv->stop) break;
+            continue;
+        }
         std::vector<StreamRec *> order;
         for (auto &kv : srv->streams)
             if (!kv.second->ready.empty()) order.push_back(kv.second.get());
@@ -339,6 +355,7 @@ void scheduler_loop(qld_server *srv) {
         std::map<int, std::vector<StreamRec *>> groups;
         for (StreamRec *r : order) groups[r->eb * 2 + (r->d.bits > 15 ? 1 : 0)].push_back(r);
 
+        std::vector<Inflight> round;
         for (auto &g : groups) {
             WinBatch b{};
             std::vector<CycleRef> refs;
@@ -427,7 +444,12 @@ void scheduler_loop(qld_server *srv) {
             }
             srv->batches++;
             srv->max_streams = std::max<int32_t>(srv->max_streams, b.n_jobs);
-            srv->inflight.push_back(Inflight{ev, std::move(refs)});
+            round.push_back(Inflight{ev, std::move(refs), false});
+        }
+        if (!round.empty()) {
+            round.back().round_end = true;
+            for (Inflight &f : round) srv->inflight.push_back(std::move(f));
+            srv->n_inflight++;
             srv->cv_complete.notify_one();
         }
     }
@@ -470,9 +492,14 @@ void completion_loop(qld_server *srv) {
                 res.gate = r->gate_host[c.out_slot];
                 res.learned = (res.gate == res.gate && res.gate <= c.gate_thr) ? 1 : 0;
             }
+            res.seq = c.k;
             srv->results.push_back(res);
             r->done++;
             srv->cycles++;
+        }
+        if (f.round_end) {
+            srv->n_inflight--;
+            srv->cv_sched.notify_one();
         }
         srv->cv_done.notify_all();
     }
@@ -619,14 +646,11 @@ extern "C" qld_status qld_stream_set_denoiser(qld_server *s, int32_t stream_id, 
     return QLD_OK;
 }
 
-extern "C" qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const void *host_frame,
-                                        int64_t frame_index, uint64_t t_arrival_ns) {
-    clear_error();
-    if (!s || !host_frame) {
-        set_error("server and host_frame must be non-NULL");
-        return QLD_E_INVAL;
-    }
-    std::unique_lock<std::mutex> lk(s->mu);
+namespace qld {
+namespace {
+
+// The stream a submit goes to, if it may take frames now (mu held).
+qld_status open_for_submit(qld_server *s, int32_t stream_id, StreamRec **out) {
     if (s->async_error != QLD_OK) return s->async_error;
     StreamRec *r = find_stream(s, stream_id);
     if (!r || r->state == QLD_STREAM_CLOSED) {
@@ -641,66 +665,69 @@ extern "C" qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const 
         set_error("stream %d is LEARNED and has no denoiser", stream_id);
         return QLD_E_STATE;
     }
-    if (frame_index < r->next_frame) {
-        set_error("frame index %lld < expected %lld", (long long)frame_index, (long long)r->next_frame);
-        return QLD_E_INVAL;
+    *out = r;
+    return QLD_OK;
+}
+
+// Back-pressure before the first frame of the stream's next cycle: its
+// device staging slot must have been consumed (mu held; waits).  While the
+// server is held nothing is launched, so instead of waiting for ever this
+// returns QLD_E_AGAIN and the submit takes nothing.
+qld_status wait_slot(qld_server *s, StreamRec *r, std::unique_lock<std::mutex> &lk) {
+    const int64_t k = r->submitted;
+    auto slot_free = [&] { return r->done > k - kStageCycles; };
+    s->cv_done.wait(lk, [&] { return slot_free() || s->async_error != QLD_OK || s->hold; });
+    if (s->async_error != QLD_OK) return s->async_error;
+    if (!slot_free()) {
+        set_error("stream %d: every staging slot holds a cycle the held server has not launched", r->id);
+        return QLD_E_AGAIN;
     }
-    qld_status ret = QLD_OK;
-    if (frame_index > r->next_frame) {
-        // A gap loses the phase alignment: drop the partial cycle, restart the window.
-        r->cur = 0;
-        r->dropping = true;
-        r->reset_next = true;
-        ret = QLD_E_GAP;
-        set_error("frame index jumped from %lld to %lld: window reset", (long long)r->next_frame,
-                  (long long)frame_index);
-    }
-    r->next_frame = frame_index + 1;
-    const int phase = (int)(frame_index & 3);
-    if (r->dropping) {
-        if (phase != 0) return ret;   // wait for the first frame of a cycle
-        r->dropping = false;
-    }
-    if (phase != r->cur) {
-        // Stream started mid-cycle (first frame index not a multiple of 4).
-        r->cur = 0;
-        if (phase != 0) return ret;
-    }
+    return QLD_OK;
+}
+
+// Copies n frames (phases phase .. phase + n - 1 of the stream's next cycle)
+// from host memory into pinned staging and enqueues one host-to-device copy
+// of them on the copy stream; the cycle goes to the scheduler once its last
+// frame is in.  mu is held on entry and exit and released around the copies.
+qld_status stage_frames(qld_server *s, StreamRec *r, std::unique_lock<std::mutex> &lk, const void *host, int phase,
+                        int n, int64_t cam_cycle, uint64_t t_arrival_ns) {
     const int64_t k = r->submitted;
     const int slot = (int)(k % kStageCycles);
-    if (phase == 0) {
-        // Back-pressure: the staging slot must have been consumed.
-        s->cv_done.wait(lk, [&] { return r->done > k - kStageCycles || s->async_error != QLD_OK; });
-        if (s->async_error != QLD_OK) return s->async_error;
+    const int p0 = (int)(k % kPinnedCycles) * 4 + phase;
+    bool used[4];
+    hipEvent_t pev[4];
+    for (int i = 0; i < n; ++i) {
+        used[i] = r->pin_used[p0 + i];
+        r->pin_used[p0 + i] = true;
+        pev[i] = r->pin_ev[p0 + i];
     }
-    const int p = r->pin_next;
-    r->pin_next = (r->pin_next + 1) % kPinnedFrames;
-    const bool used = r->pin_used[p];
-    r->pin_used[p] = true;
-    hipEvent_t pev = r->pin_ev[p];
-    uint8_t *pin = r->pin + (size_t)p * r->frame_bytes;
+    uint8_t *pin = r->pin + (size_t)p0 * r->frame_bytes;
     uint8_t *dst = r->stage + (size_t)slot * r->slot_b + (size_t)phase * r->fs_b;
+    const size_t row = (size_t)r->d.W * r->eb;
     lk.unlock();
 
     hipError_t e = hipSuccess;
-    if (used) e = hipEventSynchronize(pev);   // the pinned buffer's previous copy is done
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        if (used[i]) e = hipEventSynchronize(pev[i]);   // the pinned frame's previous copy is done
     if (e == hipSuccess) {
-        memcpy(pin, host_frame, r->frame_bytes);
-        e = hipMemcpy2DAsync(dst, (size_t)r->rp_b, pin, (size_t)r->d.W * r->eb, (size_t)r->d.W * r->eb,
-                             (size_t)r->d.H, hipMemcpyHostToDevice, s->copy);
+        memcpy(pin, host, (size_t)n * r->frame_bytes);
+        // The staged frames of a cycle are consecutive [H][Wp] planes, so n
+        // frames are one copy of n * H rows.
+        e = hipMemcpy2DAsync(dst, (size_t)r->rp_b, pin, row, row, (size_t)n * r->d.H, hipMemcpyHostToDevice,
+                             s->copy);
     }
-    if (e == hipSuccess) e = hipEventRecord(pev, s->copy);
-    if (e == hipSuccess && phase == 3) e = hipEventRecord(r->slot_ev[slot], s->copy);
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipEventRecord(pev[i], s->copy);
+    if (e == hipSuccess && phase + n == 4) e = hipEventRecord(r->slot_ev[slot], s->copy);
 
     lk.lock();
     if (e != hipSuccess) {
         set_error("frame copy failed: %s", hipGetErrorString(e));
         return QLD_E_DEVICE;
     }
-    r->cur = phase + 1;
-    if (phase == 3) {
+    r->cur = phase + n;
+    if (r->cur == 4) {
         r->slot_tarr[slot] = t_arrival_ns;
-        r->slot_cam_cycle[slot] = frame_index >> 2;
+        r->slot_cam_cycle[slot] = cam_cycle;
         r->slot_reset[slot] = r->reset_next;
         r->reset_next = false;
         r->ready.push_back(k);
@@ -708,7 +735,132 @@ extern "C" qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const 
         r->cur = 0;
         s->cv_sched.notify_one();
     }
-    return ret;
+    return QLD_OK;
+}
+
+}  // namespace
+}  // namespace qld
+
+extern "C" qld_status qld_stream_submit(qld_server *s, int32_t stream_id, const void *host_frame,
+                                        int64_t frame_index, uint64_t t_arrival_ns) {
+    clear_error();
+    if (!s || !host_frame) {
+        set_error("server and host_frame must be non-NULL");
+        return QLD_E_INVAL;
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    StreamRec *r = nullptr;
+    QLD_TRY(open_for_submit(s, stream_id, &r));
+    if (frame_index < r->next_frame) {
+        set_error("frame index %lld < expected %lld", (long long)frame_index, (long long)r->next_frame);
+        return QLD_E_INVAL;
+    }
+    // What the frame does is decided before any state changes, so that a
+    // submit returning QLD_E_AGAIN has taken nothing and can be repeated.
+    // A gap loses the phase alignment: the partial cycle is dropped, frames
+    // are skipped until a cycle starts, and the window restarts.
+    const bool gap = frame_index > r->next_frame;
+    const int phase = (int)(frame_index & 3);
+    bool dropping = gap || r->dropping;
+    int cur = gap ? 0 : r->cur;
+    bool take = true;
+    if (dropping) {
+        if (phase != 0) take = false;   // wait for the first frame of a cycle
+        else dropping = false;
+    }
+    if (take && phase != cur) {
+        // Stream started mid-cycle (first frame index not a multiple of 4).
+        cur = 0;
+        if (phase != 0) take = false;
+    }
+    if (take && phase == 0) QLD_TRY(wait_slot(s, r, lk));
+    qld_status ret = QLD_OK;
+    if (gap) {
+        r->reset_next = true;
+        ret = QLD_E_GAP;
+        set_error("frame index jumped from %lld to %lld: window reset", (long long)r->next_frame,
+                  (long long)frame_index);
+    }
+    r->next_frame = frame_index + 1;
+    r->dropping = dropping;
+    r->cur = cur;
+    if (!take) return ret;
+    const qld_status st = stage_frames(s, r, lk, host_frame, phase, 1, frame_index >> 2, t_arrival_ns);
+    return st != QLD_OK ? st : ret;
+}
+
+extern "C" qld_status qld_stream_submit_cycle(qld_server *s, int32_t stream_id, const void *host_frames,
+                                              int64_t first_frame_index, uint64_t t_arrival_ns) {
+    clear_error();
+    if (!s || !host_frames) {
+        set_error("server and host_frames must be non-NULL");
+        return QLD_E_INVAL;
+    }
+    if (first_frame_index < 0 || first_frame_index % 4 != 0) {
+        set_error("first_frame_index %lld is not a multiple of 4", (long long)first_frame_index);
+        return QLD_E_INVAL;
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    StreamRec *r = nullptr;
+    QLD_TRY(open_for_submit(s, stream_id, &r));
+    if (first_frame_index < r->next_frame) {
+        set_error("frame index %lld < expected %lld", (long long)first_frame_index, (long long)r->next_frame);
+        return QLD_E_INVAL;
+    }
+    const bool gap = first_frame_index > r->next_frame;
+    QLD_TRY(wait_slot(s, r, lk));
+    qld_status ret = QLD_OK;
+    if (gap) {
+        r->reset_next = true;
+        ret = QLD_E_GAP;
+        set_error("frame index jumped from %lld to %lld: window reset", (long long)r->next_frame,
+                  (long long)first_frame_index);
+    }
+    r->next_frame = first_frame_index + 4;
+    r->dropping = false;
+    r->cur = 0;
+    const qld_status st = stage_frames(s, r, lk, host_frames, 0, 4, first_frame_index >> 2, t_arrival_ns);
+    return st != QLD_OK ? st : ret;
+}
+
+extern "C" qld_status qld_server_hold(qld_server *s, int32_t on) {
+    clear_error();
+    if (!s) return QLD_E_INVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->hold = on != 0;
+    }
+    s->cv_sched.notify_all();
+    s->cv_done.notify_all();   // a submit waiting for a staging slot re-checks
+    return QLD_OK;
+}
+
+extern "C" qld_status qld_server_set_max_inflight(qld_server *s, int32_t n) {
+    clear_error();
+    if (!s || n < 1 || n > kMaxInflight) {
+        set_error("max_inflight must be in 1..%d", kMaxInflight);
+        return QLD_E_INVAL;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->max_inflight = n;
+    }
+    s->cv_sched.notify_all();
+    return QLD_OK;
+}
+
+extern "C" qld_status qld_stream_result_valid(qld_server *s, const qld_result *res, int32_t *valid) {
+    clear_error();
+    if (!s || !res || !valid) return QLD_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    StreamRec *r = find_stream(s, res->stream_id);
+    // The result's output slot is rewritten by the stream's cycle
+    // seq + out_slots; cycles are launched in order.
+    *valid = (r && r->state != QLD_STREAM_CLOSED && res->seq >= 0 && res->seq < r->launched &&
+              r->launched <= res->seq + s->out_slots)
+                 ? 1
+                 : 0;
+    return QLD_OK;
 }
 
 extern "C" qld_status qld_stream_poll(qld_server *s, qld_result *out, int32_t max, int32_t *n_out) {
@@ -728,6 +880,8 @@ extern "C" qld_status qld_server_drain(qld_server *s) {
     clear_error();
     if (!s) return QLD_E_INVAL;
     std::unique_lock<std::mutex> lk(s->mu);
+    s->hold = false;
+    s->cv_sched.notify_all();
     s->cv_done.wait(lk, [&] {
         if (s->async_error != QLD_OK) return true;
         for (auto &kv : s->streams)
@@ -752,6 +906,8 @@ extern "C" qld_status qld_stream_close(qld_server *s, int32_t stream_id) {
         return QLD_OK;
     }
     r->state = QLD_STREAM_CLOSED;
+    s->hold = false;
+    s->cv_sched.notify_all();
     s->cv_done.wait(lk, [&] { return r->done >= r->submitted || s->async_error != QLD_OK; });
     // Results already published keep pointing at this stream's output slots:
     // drop them so nobody reads freed memory.
@@ -773,6 +929,8 @@ extern "C" qld_status qld_server_destroy(qld_server *s) {
     if (!s) return QLD_OK;
     {
         std::unique_lock<std::mutex> lk(s->mu);
+        s->hold = false;
+        s->cv_sched.notify_all();
         s->cv_done.wait(lk, [&] {
             if (s->async_error != QLD_OK) return true;
             for (auto &kv : s->streams)

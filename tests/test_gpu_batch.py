@@ -193,6 +193,25 @@ def test_lockin_image_overwrites_and_matches_accumulate(T, H, W, bits, phase0):
     assert e.value.status == qld.E_SHAPE
 
 
+def test_statistics_over_odd_flush_counts_and_grid_rounds():
+    """Per-frame statistics when each persistent-grid unit ends on an odd
+    number of statistics flushes (808 frames: 13 flushes of 64 frames per
+    unit) and work-groups take several units (520 tiles on 512 work-groups:
+    a whole round, then the 8-tile tail split over the frames): the sums
+    and counts stay exact across the units of a work-group."""
+    need_gpu()
+    rng = np.random.default_rng(808)
+    T, H, W, bits = 808, 1040, 1024, 12
+    f = rng.integers(0, 1 << bits, size=(T, H, W), dtype=np.uint16)
+    f[:, ::9, ::4] = (1 << bits) - 1
+    say("statistics case", T, H, W)
+    dev = to_dev(f)
+    I, Q, amp, fsum, fsat = qld.lockin(dev, phase0=1, bits=bits, stats=True)
+    torch.cuda.synchronize()
+    check_against_oracle(f, I.cpu().numpy(), Q.cpu().numpy(), amp.cpu().numpy(), fsum.cpu().numpy(),
+                         fsat.cpu().numpy(), 1, bits)
+
+
 def test_hinted_frame_stride_gives_the_same_image():
     # A stack laid out with qld_frame_stride_hint (gaps between frames) gives
     # the same I/Q, amplitude and statistics as the dense layout.

@@ -92,9 +92,14 @@ def test_window_sinusoid_closed_form():
 # Serving: alone vs in the mix, admission by budget, gaps.
 # ---------------------------------------------------------------------------
 
-def run_server(streams, n_cycles, M, budget=None, interleave=True, Ms=0):
+def run_server(streams, n_cycles, M, budget=None, interleave=True, Ms=0, held=False, whole_cycles=False):
     """Submit ``n_cycles`` cycles of each (H, W, seed) stream; return per-stream
-    {cycle: (I, Q, amp[, Is, Qs])} read back right after each poll."""
+    {cycle: (I, Q, amp[, Is, Qs])} read back right after each poll.
+    held: the scheduler is drained and held while each round of cycles (one
+    per stream) is submitted, and released after it, so each round is one
+    launch carrying every stream.
+    whole_cycles: cycles go in with qld_stream_submit_cycle instead of four
+    single-frame submits."""
     need = 0
     srv = qld.Server(budget or (1 << 34), out_slots=64, keep_iq=True)
     ids = []
@@ -122,9 +127,20 @@ def run_server(streams, n_cycles, M, budget=None, interleave=True, Ms=0):
     frames = [[cam.cycle(c) for c in range(n_cycles)] for cam in cams]
     order = [(c, j, s) for c in range(n_cycles) for j in range(4) for s in range(len(ids))] if interleave else \
         [(c, j, s) for s in range(len(ids)) for c in range(n_cycles) for j in range(4)]
+    if whole_cycles:
+        order = [o for o in order if o[1] == 0]
     for (c, j, s) in order:
-        srv.submit(ids[s], frames[s][c][j], 4 * c + j, time.monotonic_ns())
-        if j == 3 and c % 8 == 7:
+        if held and s == 0 and j == 0:
+            srv.drain()          # the previous round is done: its staging slots are free
+            srv.hold(True)
+        if whole_cycles:
+            st = srv.submit_cycle(ids[s], np.ascontiguousarray(frames[s][c]), 4 * c, time.monotonic_ns())
+        else:
+            st = srv.submit(ids[s], frames[s][c][j], 4 * c + j, time.monotonic_ns())
+        assert st == qld.OK, (c, j, s, st)
+        if held and s == len(ids) - 1 and (j == 3 or whole_cycles):
+            srv.hold(False)
+        if (j == 3 or whole_cycles) and c % 8 == 7:
             collect()
     srv.drain()
     collect()
@@ -134,14 +150,22 @@ def run_server(streams, n_cycles, M, budget=None, interleave=True, Ms=0):
 
 
 def test_server_alone_vs_mix_and_oracle():
+    """Three streams of different sizes, each cycle of the three staged while
+    the scheduler is held and launched together: every launch is a mix of all
+    three (the batched kernel's job lookup for jobs 1 and 2 runs).  Each
+    stream's I/Q/amplitude after every cycle equals the same stream run alone
+    (unheld, one launch per cycle) and the oracle's re-summing window."""
     need_gpu()
     shapes = [(48, 80, 11), (96, 64, 12), (40, 136, 13)]
     M, n = 6, 16
-    mixed, frames, st = run_server(shapes, n, M)
+    mixed, frames, st = run_server(shapes, n, M, held=True)
     say("server stats", st)
     assert st["cycles"] == 3 * n
+    assert st["max_streams_in_batch"] == 3
+    assert st["batches"] == n
     for k, shp in enumerate(shapes):
-        alone, _, _ = run_server([shp], n, M)
+        alone, _, sta = run_server([shp], n, M)
+        assert sta["max_streams_in_batch"] == 1
         for c in range(n):
             for a, b in zip(alone[0][c], mixed[k][c]):
                 assert np.array_equal(a, b), (shp, c)
@@ -204,6 +228,59 @@ def test_server_full_size_three_cameras_sampled():
             I, Q, amp = got[sid][c]
             assert np.array_equal(I, ref[c][0][0]) and np.array_equal(Q, ref[c][1][0]), (k, c)
             assert amp_ulps(amp, oracle.amplitude(ref[c][0][0], ref[c][1][0])).max() <= 2.0, (k, c)
+
+
+def test_server_whole_cycle_submit_and_result_validity():
+    """qld_stream_submit_cycle (one host copy and one transfer per cycle) gives
+    the same images as frame-by-frame submits; while held, a fifth staged
+    cycle is refused with QLD_E_AGAIN and taken after the release; a result
+    stays valid until its output slot is relaunched."""
+    need_gpu()
+    shapes = [(40, 72, 31), (17, 200, 32)]
+    M, n = 5, 12
+    by_cycle, frames, st = run_server(shapes, n, M, whole_cycles=True, held=True)
+    assert st["max_streams_in_batch"] == 2 and st["cycles"] == 2 * n and st["batches"] == n
+    by_frame, _, _ = run_server(shapes, n, M)
+    for k in range(len(shapes)):
+        ref = list(oracle.window_series(frames[k], M))
+        for c in range(n):
+            for a, b in zip(by_cycle[k][c], by_frame[k][c]):
+                assert np.array_equal(a, b), (k, c)
+            assert np.array_equal(by_cycle[k][c][0], ref[c][0]) and np.array_equal(by_cycle[k][c][1], ref[c][1])
+
+    H, W = 24, 40
+    srv = qld.Server(1 << 32, out_slots=2, keep_iq=True)
+    sid, ok = srv.open(H, W, 3, bits=16)
+    assert ok
+    cam = scenes.CameraStream(H, W, 33, bits=16, bank=8)
+    cyc = [np.ascontiguousarray(cam.cycle(c)) for c in range(8)]
+    srv.hold(True)
+    for c in range(4):
+        assert srv.submit_cycle(sid, cyc[c], 4 * c, 0) == qld.OK
+    assert srv.submit_cycle(sid, cyc[4], 16, 0) == qld.E_AGAIN       # staging full, nothing launched
+    assert srv.submit(sid, cyc[4][0], 16, 0) == qld.E_AGAIN
+    assert srv.poll() == []
+    srv.hold(False)
+    srv.drain()
+    first = srv.poll()
+    assert [r.cycle for r in first] == [0, 1, 2, 3] and [r.seq for r in first] == [0, 1, 2, 3]
+    # Two output slots: cycles 0 and 1 were overwritten by 2 and 3.
+    assert [srv.result_valid(r) for r in first] == [False, False, True, True]
+    assert srv.submit_cycle(sid, cyc[4], 16, 0) == qld.OK
+    assert srv.submit_cycle(sid, cyc[6], 24, 0) == qld.E_GAP           # cycle 5 missing: new window
+    with pytest.raises(qld.QldError):
+        srv.submit_cycle(sid, cyc[7], 26, 0)                           # not a cycle start
+    srv.drain()
+    rest = srv.poll()
+    assert [r.cycle for r in rest] == [4, 6]
+    assert not srv.result_valid(first[2]) and srv.result_valid(rest[1])
+    pI, pQ, _, _ = srv.result_iq(rest[1])
+    I = qld.device_view(pI, (H, W), torch.int32).cpu().numpy()
+    assert np.array_equal(I, oracle.qld(cyc[6])[0])
+    ref = list(oracle.window_series(cyc[:5], 3))
+    pI, pQ, _, _ = srv.result_iq(rest[0])
+    assert np.array_equal(qld.device_view(pI, (H, W), torch.int32).cpu().numpy(), ref[4][0])
+    srv.close()
 
 
 def test_server_short_window_shares_ring():
