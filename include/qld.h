@@ -149,6 +149,34 @@ qld_status qld_lockin_image(const void *frames, const qld_frame_desc *d, int32_t
                             qld_hip_stream stream);
 
 /*
+ * qld_lockin_image_noalloc -- qld_lockin_image for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * qld_lockin_image (the same kernels run), but the scratch the kernels need
+ * (per-work-group frame-statistics partials when frame_sum or frame_sat is
+ * given; per-split I/Q partials when a small image's frames are split over
+ * several work-groups) lives in a fixed device array of
+ * QLD_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends.  The call makes no hipMalloc/hipFree and no
+ * allocating library call.  The array's device address is looked up once
+ * per device, on the first call with that device current.
+ * Errors: as qld_lockin_image, plus QLD_E_NOMEM (nothing launched) when the
+ * call would need more scratch than the array holds: about
+ * 8 * n_frames * (H*W / 2048 for aligned 16-bit stacks, / 4096 for 8-bit,
+ * / 64 for unaligned ones) bytes with statistics, plus 8 bytes per pixel per
+ * frame split of images too small to fill the GPU.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (two host threads, or two streams whose work is not
+ * ordered) race on it and give undefined results.  Calls ordered on one
+ * stream are safe; the array keeps the last call's partials, and every call
+ * writes all of the scratch it reads, so nothing needs clearing.
+ */
+#define QLD_NOALLOC_SCRATCH_BYTES (32u << 20)
+qld_status qld_lockin_image_noalloc(const void *frames, const qld_frame_desc *d, int32_t n_frames,
+                                    int32_t phase0, int32_t *I, int32_t *Q, float *amp, uint64_t *frame_sum,
+                                    uint32_t *frame_sat, qld_hip_stream stream);
+
+/*
  * dft_bin_baseline -- the Fourier alternative at one frequency (Methods,
  * Fourier map |F(omega)|^2 of each pixel's series):
  *     X_k = sum_{n < N} S_n exp(-2 pi i ((k n) mod N) / N),   N = n_frames

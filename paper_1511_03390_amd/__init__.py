@@ -26,13 +26,14 @@ _lib = ctypes.CDLL(LIB_PATH)
 # Status codes (qld_status).
 OK, E_INVAL, E_DTYPE, E_SHAPE, E_ALIGN, E_OVERFLOW, E_NOMEM, E_BUDGET, E_AGAIN, E_STATE, E_GAP, E_DEVICE, E_IO = range(13)
 U8, U16 = 1, 2
+NOALLOC_SCRATCH_BYTES = 32 << 20      # QLD_NOALLOC_SCRATCH_BYTES
 STREAM_PENDING, STREAM_ACTIVE, STREAM_CLOSED = 1, 2, 3
 SERVER_KEEP_IQ = 1
 MODE_PLAIN, MODE_LEARNED = 0, 1
 
 # Every entry point the header declares (checked by the tests).
 EXPORTS = (
-    "qld_accumulate", "qld_lockin_image", "qld_amplitude", "dft_bin_baseline", "dft_bin_baseline_f64", "qld_lockin_ratio", "qld_lockin_bank",
+    "qld_accumulate", "qld_lockin_image", "qld_lockin_image_noalloc", "qld_amplitude", "dft_bin_baseline", "dft_bin_baseline_f64", "qld_lockin_ratio", "qld_lockin_bank",
     "qld_window_bytes", "qld_window_create", "qld_window_update", "qld_window_reset",
     "qld_window_destroy", "qld_window_info", "qld_window_save", "qld_window_load",
     "qld_fwindow_bytes", "qld_fwindow_create", "qld_fwindow_update", "qld_fwindow_reset", "qld_fwindow_info",
@@ -82,6 +83,7 @@ def _sig(name, res, *args):
 
 _sig("qld_accumulate", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp, _vp, _vp)
 _sig("qld_lockin_image", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("qld_lockin_image_noalloc", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("qld_amplitude", ctypes.c_int, _vp, _vp, _i64, _vp, _vp)
 _sig("dft_bin_baseline", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp)
 _sig("dft_bin_baseline_f64", ctypes.c_int, _vp, _dp, _i32, _i32, _vp, _vp, _vp)
@@ -253,6 +255,17 @@ def lockin_image(frames, I, Q, amp=None, phase0=0, bits=None, frame_sum=None, fr
     n = frames.shape[0] if frames.dim() == 3 else 1
     _check(_lib.qld_lockin_image(_ptr(frames), ctypes.byref(d), int(n), int(phase0), _ptr(I), _ptr(Q), _ptr(amp),
                                  _ptr(frame_sum), _ptr(frame_sat), _stream(stream)), "qld_lockin_image")
+
+
+def lockin_image_noalloc(frames, I, Q, amp=None, phase0=0, bits=None, frame_sum=None, frame_sat=None,
+                         stream=None):
+    """lockin_image through the entry point that allocates no device memory
+    (its scratch is the library's fixed per-device array)."""
+    d = frame_desc(frames, bits)
+    n = frames.shape[0] if frames.dim() == 3 else 1
+    _check(_lib.qld_lockin_image_noalloc(_ptr(frames), ctypes.byref(d), int(n), int(phase0), _ptr(I), _ptr(Q),
+                                         _ptr(amp), _ptr(frame_sum), _ptr(frame_sat), _stream(stream)),
+           "qld_lockin_image_noalloc")
 
 
 def amplitude(I, Q, amp, stream=None):

@@ -32,6 +32,8 @@
 //     small kernel folds the partials into frame_sum.  Clipped samples are rare: a packed max per frame detects
 //     whether any sample reaches 2^bits - 1 and only then are they counted
 //     with ballots.  (The scalar kernel reduces with DPP row shifts instead.)
+#include <mutex>
+
 #include "qld_internal.hpp"
 
 namespace qld {
@@ -707,16 +709,53 @@ int32_t choose_split(int64_t n_tiles, int32_t n_frames) {
 
 using namespace qld;
 
+// Scratch of qld_lockin_image_noalloc: a fixed array in device memory, one
+// copy per device (loaded with this file's code object).  Host code never
+// uses the array's name as an address: on the host it is only a stand-in for
+// the symbol, so the device address of each device's copy is looked up with
+// hipGetSymbolAddress (with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[QLD_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, or nullptr (error set).
+char *noalloc_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        set_error("qld_lockin_image_noalloc: no usable current device");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            set_error("qld_lockin_image_noalloc: hipGetSymbolAddress of the scratch array failed (%s)",
+                      hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
 
 // overwrite = false: (I, Q) += the stack's sums, frame statistics added.
 // overwrite = true: one image: I/Q and the statistics replaced, amp (may be
 // NULL) written.  Without a frame split all of it happens in the accumulation
 // kernel's epilogue; with one, qld_iq_reduce_kernel adds the splits' partials
 // into I/Q (or replaces them) and writes the amplitude.
+// noalloc: the scratch comes from the fixed device array (noalloc_scratch)
+// instead of the per-stream workspace, and a call that needs more than it
+// holds is refused before anything is launched.
 qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t n_frames, int32_t phase0,
                            int32_t *I, int32_t *Q, float *amp, uint64_t *frame_sum, uint32_t *frame_sat,
-                           bool overwrite, qld_hip_stream stream) {
+                           bool overwrite, bool noalloc, qld_hip_stream stream) {
     int eb = 0;
     QLD_TRY(check_desc(d, &eb));
     if (n_frames < 0) {
@@ -814,7 +853,17 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     av.part_n = as.part_n = npx - p_split;
     const size_t iq_b = split ? sizeof(int32_t) * 2 * (size_t)av.n_split * (size_t)(npx - p_split) : 0;
     if (stats_b + iq_b > 0) {
-        char *ws = static_cast<char *>(stream_workspace(s, stats_b + iq_b));
+        char *ws = nullptr;
+        if (noalloc) {
+            if (stats_b + iq_b > (size_t)QLD_NOALLOC_SCRATCH_BYTES) {
+                set_error("qld_lockin_image_noalloc: this call needs %zu bytes of scratch, the fixed array holds %zu",
+                          stats_b + iq_b, (size_t)QLD_NOALLOC_SCRATCH_BYTES);
+                return QLD_E_NOMEM;
+            }
+            ws = noalloc_scratch();
+        } else {
+            ws = static_cast<char *>(stream_workspace(s, stats_b + iq_b));
+        }
         if (!ws) return QLD_E_NOMEM;
         if (stats) {
             uint32_t *ps = reinterpret_cast<uint32_t *>(ws);
@@ -870,7 +919,7 @@ extern "C" qld_status qld_accumulate(const void *frames, const qld_frame_desc *d
                                      int32_t phase0, int32_t *I, int32_t *Q, uint64_t *frame_sum,
                                      uint32_t *frame_sat, qld_hip_stream stream) {
     clear_error();
-    return accumulate_impl(frames, d, n_frames, phase0, I, Q, nullptr, frame_sum, frame_sat, false, stream);
+    return accumulate_impl(frames, d, n_frames, phase0, I, Q, nullptr, frame_sum, frame_sat, false, false, stream);
 }
 
 extern "C" qld_status qld_lockin_image(const void *frames, const qld_frame_desc *d, int32_t n_frames,
@@ -881,7 +930,18 @@ extern "C" qld_status qld_lockin_image(const void *frames, const qld_frame_desc 
         set_error("qld_lockin_image needs n_frames >= 1 (got %d)", n_frames);
         return QLD_E_SHAPE;
     }
-    return accumulate_impl(frames, d, n_frames, phase0, I, Q, amp, frame_sum, frame_sat, true, stream);
+    return accumulate_impl(frames, d, n_frames, phase0, I, Q, amp, frame_sum, frame_sat, true, false, stream);
+}
+
+extern "C" qld_status qld_lockin_image_noalloc(const void *frames, const qld_frame_desc *d, int32_t n_frames,
+                                               int32_t phase0, int32_t *I, int32_t *Q, float *amp,
+                                               uint64_t *frame_sum, uint32_t *frame_sat, qld_hip_stream stream) {
+    clear_error();
+    if (n_frames < 1) {
+        set_error("qld_lockin_image_noalloc needs n_frames >= 1 (got %d)", n_frames);
+        return QLD_E_SHAPE;
+    }
+    return accumulate_impl(frames, d, n_frames, phase0, I, Q, amp, frame_sum, frame_sat, true, true, stream);
 }
 
 namespace {

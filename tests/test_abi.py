@@ -115,3 +115,20 @@ def test_server_argument_errors():
     assert q.lib.qld_server_create(1 << 20, 0, 0, ctypes.byref(ctypes.c_void_p())) == q.E_INVAL
     assert q.lib.qld_stream_submit(None, 1, None, 0, 0) == q.E_INVAL
     assert q.lib.qld_stream_poll(None, None, 0, None) == q.E_INVAL
+
+
+def test_noalloc_scratch_limit_is_checked_before_any_launch():
+    src = open(os.path.join(ROOT, "include", "qld.h")).read()
+    m = re.search(r"#define QLD_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == q.NOALLOC_SCRATCH_BYTES
+    # An unaligned 8-bit 1024 x 1024 x 257 stack with statistics needs
+    # 4096 * 4 * 257 * 8 bytes of partials: more than the array holds, refused
+    # synchronously (the pointers are never dereferenced).
+    d = desc(H=1024, W=1024, dt=q.U8, bits=8)
+    p = ctypes.c_void_p
+    st = q.lib.qld_lockin_image_noalloc(p(1 << 20 | 1), ctypes.byref(d), 257, 0, p(1 << 21), p(1 << 22), None,
+                                        p(1 << 23), p(1 << 24), None)
+    assert st == q.E_NOMEM
+    assert b"scratch" in q.lib.qld_last_error()
+    assert q.lib.qld_lockin_image_noalloc(p(1 << 20), ctypes.byref(d), 0, 0, p(1 << 21), p(1 << 22), None,
+                                          None, None, None) == q.E_SHAPE
