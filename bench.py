@@ -22,6 +22,7 @@ versus plain QLD at 8 and 512 cycles).
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import threading
@@ -257,40 +258,46 @@ def cpu_baseline(oracle, frames, target_s, qld_I, torch):
                                   "hardware": "Xeon 4-core 3.4 GHz (8 threads), FP64"}}
 
 
-def bench_streaming(qld, torch, seconds, fps, M=64):
-    """Three cameras at `fps` frames/s each, M-cycle windows, one server."""
-    import numpy as np
+def camera_banks(shapes, n_bank, config=3):
+    """n_bank pre-rendered cycles ([4][H][W] uint16) per camera, replayed in order."""
     import scenes
-    shapes = scenes.STREAM_SHAPES
-    srv = qld.Server(1 << 36, out_slots=16)
-    cams, ids, banks = [], [], []
+    banks = []
     for k, (h, w) in enumerate(shapes):
-        sid, ok = srv.open(h, w, M, bits=16)
-        assert ok
-        ids.append(sid)
-        cam = scenes.CameraStream(h, w, scenes.seed_for(3, k), bits=16, bank=8)
-        banks.append([cam.cycle(c) for c in range(8)])
-    n_frames = int(seconds * fps)
-    lat = {sid: [] for sid in ids}
+        cam = scenes.CameraStream(h, w, scenes.seed_for(config, k), bits=16, bank=8)
+        banks.append([cam.cycle(c) for c in range(n_bank)])
+    return banks
+
+
+def run_paced(srv, ids, banks, n_frames, fps, f0=0, lat=None):
+    """Each camera thread submits its frames f0 .. f0 + n_frames - 1 one at a
+    time, frame f due at t_start + f / fps; a poller collects the latency of
+    every image.  Returns ({sid: [ms]}, wall seconds)."""
+    import numpy as np  # noqa: F401
+    lat = {sid: [] for sid in ids} if lat is None else lat
     stop = threading.Event()
+    t_start = time.monotonic_ns() + 200_000_000
+    period = 1e9 / fps
 
     def camera(k):
-        sid = ids[k]
-        t_start = time.monotonic_ns() + 200_000_000
-        period = int(1e9 / fps)
+        sid, bank = ids[k], banks[k]
         for f in range(n_frames):
-            t_due = t_start + f * period
+            t_due = t_start + int(f * period)
             while True:
                 now = time.monotonic_ns()
                 if now >= t_due:
                     break
                 time.sleep(min(0.002, (t_due - now) / 1e9))
-            srv.submit(sid, banks[k][(f // 4) % 8][f % 4], f, time.monotonic_ns())
+            fi = (f0[k] if isinstance(f0, (list, tuple)) else f0) + f
+            srv.submit(sid, bank[(fi // 4) % len(bank)][fi % 4], fi, time.monotonic_ns())
+
+    def collect(rs):
+        for r in rs:
+            if r.stream_id in lat:
+                lat[r.stream_id].append((r.t_done_ns - r.t_arrival_ns) / 1e6)
 
     def poller():
         while not stop.is_set():
-            for r in srv.poll(1024):
-                lat[r.stream_id].append((r.t_done_ns - r.t_arrival_ns) / 1e6)
+            collect(srv.poll(1024))
             time.sleep(0.0005)
 
     pt = threading.Thread(target=poller)
@@ -304,31 +311,77 @@ def bench_streaming(qld, torch, seconds, fps, M=64):
     srv.drain()
     stop.set()
     pt.join()
-    for r in srv.poll(4096):
-        lat[r.stream_id].append((r.t_done_ns - r.t_arrival_ns) / 1e6)
-    wall = time.perf_counter() - t0
+    collect(srv.poll(4096))
+    return lat, time.perf_counter() - t0
+
+
+def latency_summary(v):
+    import numpy as np
+    v = np.asarray(v, dtype=np.float64)
+    if not v.size:
+        return {"images": 0}
+    return {"images": int(v.size), "p50_ms": round(float(np.percentile(v, 50)), 3),
+            "p99_ms": round(float(np.percentile(v, 99)), 3), "max_ms": round(float(v.max()), 3)}
+
+
+def host_copy_rates(torch, mib=256):
+    """Host memcpy into pinned memory and pinned host-to-device copy, GB/s
+    (the two copies every served frame takes)."""
+    import numpy as np
+    n = mib << 20
+    src = np.ones(n, dtype=np.uint8)
+    pin = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(n, dtype=torch.uint8, device="cuda")
+    pv = pin.numpy()
+    np.copyto(pv, src)
+    t0 = time.perf_counter()
+    for _ in range(4):
+        np.copyto(pv, src)
+    memcpy = 4 * n / (time.perf_counter() - t0) / 1e9
+    dst.copy_(pin, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(4):
+        dst.copy_(pin, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = 4 * n / (time.perf_counter() - t0) / 1e9
+    return {"memcpy_gbs": round(memcpy, 1), "h2d_gbs": round(h2d, 1), "mib": mib}
+
+
+def bench_streaming(qld, torch, seconds, fps, M=64, unpaced_cycles=256):
+    """Three cameras at `fps` frames/s each, M-cycle windows, one server:
+    paced latency, unpaced saturation through whole-cycle submits, and
+    admission under a budget that holds only two of the three cameras."""
+    import numpy as np
+    shapes = scenes_mod().STREAM_SHAPES
+    banks = camera_banks(shapes, 16)
+    px = sum(h * w for h, w in shapes)
+
+    # Paced: every camera at `fps`, one frame per submit (as a grabber hands them over).
+    srv = qld.Server(1 << 36, out_slots=16)
+    ids = []
+    for (h, w) in shapes:
+        sid, ok = srv.open(h, w, M, bits=16)
+        assert ok
+        ids.append(sid)
+    n_frames = int(seconds * fps)
+    lat, wall = run_paced(srv, ids, banks, n_frames, fps)
     st = srv.stats()
-    per = []
-    allv = []
-    for k, sid in enumerate(ids):
-        v = np.array(lat[sid])
-        allv.extend(lat[sid])
-        per.append({"shape": list(shapes[k]), "images": int(v.size),
-                    "p50_ms": round(float(np.percentile(v, 50)), 3) if v.size else None,
-                    "p99_ms": round(float(np.percentile(v, 99)), 3) if v.size else None})
-    allv = np.array(allv)
-    # Unpaced: each camera thread submits its cycles back to back (saturation
-    # throughput); cycles of different streams that are ready together share a launch.
-    n_cyc = 64
-    b0 = srv.stats()["batches"]
+    srv.close()
+    per = [dict(shape=list(shapes[k]), **latency_summary(lat[sid])) for k, sid in enumerate(ids)]
+    allv = np.concatenate([np.asarray(lat[sid]) for sid in ids])
+
+    # Unpaced: each camera thread submits whole cycles back to back (one host
+    # copy and one host-to-device copy per cycle); while a launch runs, the
+    # cycles that land are gathered into the next one.
+    srv = qld.Server(1 << 36, out_slots=16)
+    ids_u = [srv.open(h, w, M, bits=16)[0] for (h, w) in shapes]
 
     def flood(k):
-        sid = ids[k]
-        for c in range(n_cyc):
-            for j in range(4):
-                srv.submit(sid, banks[k][c % 8][j], n_frames + 4 * c + j, time.monotonic_ns())
+        for c in range(unpaced_cycles):
+            srv.submit_cycle(ids_u[k], banks[k][c % len(banks[k])], 4 * c, time.monotonic_ns())
 
-    fl = [threading.Thread(target=flood, args=(k,)) for k in range(len(ids))]
+    fl = [threading.Thread(target=flood, args=(k,)) for k in range(len(shapes))]
     t0 = time.perf_counter()
     for t in fl:
         t.start()
@@ -336,17 +389,64 @@ def bench_streaming(qld, torch, seconds, fps, M=64):
         t.join()
     srv.drain()
     dt = time.perf_counter() - t0
-    unpaced_batches = srv.stats()["batches"] - b0
+    su = srv.stats()
     while srv.poll(4096):
         pass
-    px = sum(h * w for h, w in shapes)
     srv.close()
+    rates = host_copy_rates(torch)
+    unpaced = px * 4 * unpaced_cycles / dt
+    copy_bound = rates["h2d_gbs"] * 1e9 / 2          # 2 bytes per pixel-frame cross PCIe
+    window_bytes_per_pxf = 9.0                       # 36 B per pixel per cycle in HBM
     return {"fps_per_stream": fps, "frames_per_stream": n_frames, "window_cycles": M,
             "p50_ms": round(float(np.percentile(allv, 50)), 3), "p99_ms": round(float(np.percentile(allv, 99)), 3),
             "latency": "host time from the submit of a cycle's last frame to the completion of its image",
-            "per_stream": per, "batches": st["batches"], "max_streams_in_batch": st["max_streams_in_batch"],
-            "unpaced_pxf_per_s": round(px * 4 * n_cyc / dt), "unpaced_cycles": n_cyc * len(ids),
-            "unpaced_launches": unpaced_batches, "wall_s": round(wall, 2)}
+            "per_stream": per, "batches": st["batches"], "cycles": st["cycles"],
+            "max_streams_in_batch": st["max_streams_in_batch"], "wall_s": round(wall, 2),
+            "scene": "config-1 background and disks plus a disk moving 1 px/cycle; 16 pre-rendered cycles "
+                     "per camera replayed in order",
+            "unpaced": {"pxf_per_s": round(unpaced), "cycles": unpaced_cycles * len(shapes),
+                        "launches": su["batches"], "max_streams_in_batch": su["max_streams_in_batch"],
+                        "submit": "qld_stream_submit_cycle (4 frames per call)",
+                        "host_copies": rates,
+                        "h2d_bound_pxf_per_s": round(copy_bound),
+                        "frac_of_h2d_bound": round(unpaced / copy_bound, 3),
+                        "window_kernel_hbm_bound_pxf_per_s": round(HBM_PEAK_GBS * 1e9 / window_bytes_per_pxf),
+                        "frac_of_window_hbm_bound": round(unpaced * window_bytes_per_pxf / (HBM_PEAK_GBS * 1e9), 4)},
+            "admission": bench_admission(qld, banks, shapes, fps, M)}
+
+
+def bench_admission(qld, banks, shapes, fps, M, seconds=4.0):
+    """Budget for the 2048x2048 and 640x512 cameras only: the 1280x1024 camera
+    is refused (QLD_E_AGAIN, pending) at open and admitted when the 2048x2048
+    stream closes; latency of each phase."""
+    probe = qld.Server(1 << 40, out_slots=16)
+    need = [probe.stream_bytes(h, w, M, bits=16) for (h, w) in shapes]
+    probe.close()
+    budget = need[2] + need[0] + (1 << 20)
+    srv = qld.Server(budget, out_slots=16)
+    small, ok_s = srv.open(*shapes[0], M, bits=16)
+    big, ok_b = srv.open(*shapes[2], M, bits=16)
+    mid, ok_m = srv.open(*shapes[1], M, bits=16)
+    pending_at_open = srv.state(mid) == qld.STREAM_PENDING
+    n = int(seconds * fps)
+    lat1, _ = run_paced(srv, [small, big], [banks[0], banks[2]], n, fps)
+    srv.close_stream(big)
+    admitted_after_close = srv.state(mid) == qld.STREAM_ACTIVE
+    lat2, _ = run_paced(srv, [small, mid], [banks[0], banks[1]], n, fps, f0=[n, 0])
+    st = srv.stats()
+    srv.close()
+    return {"budget_bytes": budget, "stream_bytes": {"%dx%d" % (w, h): b for (h, w), b in zip(shapes, need)},
+            "admitted_at_open": {"640x512": ok_s, "2048x2048": ok_b, "1280x1024": ok_m},
+            "1280x1024_pending_at_open": pending_at_open,
+            "1280x1024_admitted_after_2048x2048_closed": admitted_after_close,
+            "phase1": {"640x512": latency_summary(lat1[small]), "2048x2048": latency_summary(lat1[big])},
+            "phase2": {"640x512": latency_summary(lat2[small]), "1280x1024": latency_summary(lat2[mid])},
+            "frames_per_phase": n, "max_streams_in_batch": st["max_streams_in_batch"]}
+
+
+def scenes_mod():
+    import scenes
+    return scenes
 
 
 def bench_bank(qld, torch, frames, dft_ms, F=32, reps=5):
@@ -534,6 +634,7 @@ def copy_calibration(torch, gib=1):
 def bench_learned(qld, torch, steps, eval_batches):
     """Learned short-window path at its tile size: 512 x 512 tiles, M_S = 8
     cycles in, bias-reduced M_L = 512-cycle amplitude out (64x fewer frames)."""
+    import numpy as np
     from paper_1511_03390_amd import learned as Lr
     H = W = 512
     B, M_S, M_L = 8, 8, 512
@@ -571,11 +672,27 @@ def bench_learned(qld, torch, steps, eval_batches):
     d.close()
     flop_step = Lr.flops_per_pixel_step() * B * H * W
     flop_fwd = 2 * (18 * 32 + 2 * 288 * 32 + 288) * B * H * W
-    # Training run and held-out evaluation.
+    # Training run and held-out evaluation (held-out tiles: scene seeds of
+    # batches 10^6.., disjoint from the training batches 0..steps-1).
     d, hist, train_s = Lr.train(steps=steps, batch=B, H=H, W=W, M_S=M_S, M_L=M_L, lr=2e-3)
+    t_ev = time.perf_counter()
     ev = Lr.evaluate(d, n_batches=eval_batches, batch=B, H=H, W=W, M_S=M_S, M_L=M_L)
+    ev_s = time.perf_counter() - t_ev
     d.close()
-    return {"workload": "512x512 tiles (Poisson 2000, ballistic 5e-4, 1-5 rectangles), M_S=8 in, "
+    pt = ev.pop("per_tile")
+
+    def spread(v):
+        return {"mean": round(float(np.mean(v)), 4), "std": round(float(np.std(v)), 4),
+                "p10": round(float(np.percentile(v, 10)), 4), "p50": round(float(np.percentile(v, 50)), 4),
+                "p90": round(float(np.percentile(v, 90)), 4)}
+
+    ratio = pt["learned"] / pt["plain_L"]
+    # Plain QLD's error against the noise-free amplitude falls as M^-k; k from
+    # the two windows measured, and the plain window whose error equals the
+    # learned one's.
+    k_exp = math.log(ev["plain_S"] / ev["plain_L"]) / math.log(M_L / M_S)
+    m_eq = M_L * (ev["plain_L"] / ev["learned"]) ** (1.0 / k_exp)
+    return {"workload": "512x512 tiles (Poisson 2000, ballistic 5e-4, 1-5 rectangles of sides 16-256), M_S=8 in, "
                         "bias-reduced M_L=512 amplitude target (64x fewer frames)",
             "pairs_trained": steps * B, "train_s": round(train_s, 2),
             "train_px_per_s": round(steps * B * H * W / train_s),
@@ -584,9 +701,25 @@ def bench_learned(qld, torch, steps, eval_batches):
             "forward_ms": round(fwd_ms, 3), "forward_tflops": round(flop_fwd / (fwd_ms * 1e-3) / 1e12, 1),
             "inference_ms_per_tile": round(fwd_ms / B, 4),
             "mfma_peak_tflops": 2500.0,
-            "nrmse_vs_noise_free": {k: round(v, 4) for k, v in ev.items() if k not in ("tiles", "gate", "fallback_rate")},
-            "gate_fallback_rate": ev["fallback_rate"], "eval_tiles": ev["tiles"],
-            "equal_snr_pass": bool(ev["learned"] <= ev["plain_L"] + 0.05),
+            "eval_tiles": ev["tiles"], "eval_s": round(ev_s, 2),
+            "held_out": "scene seeds of batches 10^6 .. 10^6 + %d, disjoint from training" % (eval_batches - 1),
+            "nrmse_vs_noise_free": {k: spread(pt[k]) for k in ("learned", "plain_S", "plain_L",
+                                                                 "plain_L_bias_reduced", "served",
+                                                                 "learned_vs_noisy_L")},
+            "gate_fallback_rate": ev["fallback_rate"],
+            "equal_snr": {
+                "criterion": "per tile NRMSE(learned @ M_S=8) <= NRMSE(plain @ M_L=512), both against the "
+                             "noise-free per-cycle amplitude (64x fewer frames)",
+                "tiles_passing": round(float(np.mean(ratio <= 1.0)), 4),
+                "ratio_learned_to_plain_L": spread(ratio),
+                "pass": bool(np.mean(ratio <= 1.0) >= 0.95),
+                "plain_error_exponent": round(k_exp, 3),
+                "plain_cycles_matching_learned": round(m_eq),
+                "frames_saved_factor": round(m_eq / M_S, 1)},
+            "literal_target": {
+                "criterion": "NRMSE(learned @ M_S, against plain QLD @ M_L per cycle) <= 0.05",
+                "value": round(ev["learned_vs_noisy_L"], 4), "pass": bool(ev["learned_vs_noisy_L"] <= 0.05),
+                "note": "unreachable at this SNR: the M_L=512 plain image itself has amplitude SNR ~0.7"},
             "gain_vs_plain_same_frames": round(ev["plain_S"] / ev["learned"], 2),
             "loss_first_last": [round(hist[0][1], 5), round(hist[-1][1], 5)]}
 
@@ -697,10 +830,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--stream-seconds", type=float, default=10.0)
+    ap.add_argument("--stream-seconds", type=float, default=100.0,
+                    help="paced streaming length (100 s = 10k frames per camera at 100 fps)")
     ap.add_argument("--stream-fps", type=float, default=100.0)
     ap.add_argument("--no-streaming", action="store_true")
-    ap.add_argument("--learned-steps", type=int, default=150)
+    ap.add_argument("--learned-steps", type=int, default=2500,
+                    help="training steps of 8 tiles (2500 = 20k pairs)")
+    ap.add_argument("--eval-tiles", type=int, default=1000, help="held-out tiles (a multiple of 8)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-learned-serving", action="store_true")
     ap.add_argument("--serving-train-steps", type=int, default=300)
@@ -742,6 +878,19 @@ def main():
             "kernel_ms_min": round(min(kern_ms), 4),
             "algorithmic_bytes_per_launch": kern_bytes,
             "step_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1)}
+
+    # The same step on the dense layout a frame grabber writes (frame stride H*W).
+    other = H * W if not args.dense else qld.frame_stride_hint(H, W)
+    log("batch QLD on the %s layout (frame stride %d)" % ("dense" if not args.dense else "hinted", other))
+    st2 = scenes.diffuse_scene_u16(device="cuda", frame_stride=other)
+    torch.cuda.synchronize()
+    el2, km2, _ = bench_batch(qld, torch, st2.frames, args.steps, args.warmup)
+    del st2
+    torch.cuda.empty_cache()
+    k2 = sum(km2) / len(km2)
+    layout2 = {"frame_stride": other, "ms_per_step": round(el2 / args.steps * 1e3, 4),
+               "pxf_per_s": round(pxf * args.steps / el2), "kernel_ms_avg": round(k2, 4),
+               "frac": round(kern_bytes / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     log("read probe")
     read_peak = bench_read_peak(qld, torch, frames)
@@ -798,7 +947,7 @@ def main():
     learned = None
     if not args.no_learned:
         log("learned path: %d training steps of 8 tiles" % args.learned_steps)
-        learned = bench_learned(qld, torch, args.learned_steps, 2)
+        learned = bench_learned(qld, torch, args.learned_steps, max(1, args.eval_tiles // 8))
 
     log("per-frame window")
     frame_window = bench_frame_window(qld, torch)
@@ -829,6 +978,7 @@ def main():
                    "H": H, "W": W, "frames": T, "bits": 12, "stats": True, "frame_stride": fstride,
                    "parallelism": "single GPU"},
         "roofline": roof,
+        ("dense_layout" if not args.dense else "hinted_layout"): layout2,
         "cpu_baseline": cpu,
         "dft_baseline": dft,
         "streaming": streaming,

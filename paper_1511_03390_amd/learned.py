@@ -113,9 +113,11 @@ def evaluate(d, n_batches=2, batch=8, H=512, W=512, M_S=8, M_L=512, seed=1511033
         g = gate.cpu().numpy()
         acc["gate"].append(g)
         acc["served"].append(np.where(g > gate_threshold, acc["plain_L"][-1], acc["learned"][-1]))
-    out = {k: float(np.mean(np.concatenate(v))) for k, v in acc.items()}
-    out["fallback_rate"] = float(np.mean(np.concatenate(acc["gate"]) > gate_threshold))
+    per_tile = {k: np.concatenate(v) for k, v in acc.items()}
+    out = {k: float(np.mean(v)) for k, v in per_tile.items()}
+    out["fallback_rate"] = float(np.mean(per_tile["gate"] > gate_threshold))
     out["tiles"] = n_batches * batch
+    out["per_tile"] = per_tile
     return out
 
 
