@@ -631,21 +631,17 @@ def copy_calibration(torch, gib=1):
     return {"kernel": "torch neg, int32", "launches": 3, "bytes_read": 4 * n, "bytes_written": 4 * n}
 
 
-def bench_learned(qld, torch, steps, eval_batches):
-    """Learned short-window path at its tile size: 512 x 512 tiles, M_S = 8
-    cycles in, bias-reduced M_L = 512-cycle amplitude out (64x fewer frames)."""
-    import numpy as np
+def bench_learned_step(qld, torch, reps=20, H=512, W=512, B=8, M_S=8, M_L=512):
+    """The learned path's kernels at one shape: pair generation (4 batches),
+    then the denoiser's training step (forward, backward, Adam) and forward
+    alone, each `reps` times back to back, timed by events."""
     from paper_1511_03390_amd import learned as Lr
-    H = W = 512
-    B, M_S, M_L = 8, 8, 512
-    # Pair generation alone.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(4):
         Lr.tile_batch(10 ** 7 + k, B, H, W, M_S, M_L, 1)
     torch.cuda.synchronize()
     gen_s = (time.perf_counter() - t0) / 4
-    # Denoiser step alone (forward, backward, Adam) on one batch, timed by events.
     b = Lr.tile_batch(10 ** 7, B, H, W, M_S, M_L, 1)
     d = qld.Denoiser(H, W, B)
     d.set_params(Lr.he_init(7))
@@ -654,7 +650,6 @@ def bench_learned(qld, torch, steps, eval_batches):
         d.backward(b.t)
         d.adam(1e-4)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
     e0.record()
     for _ in range(reps):
         d.forward(b.x)
@@ -672,6 +667,21 @@ def bench_learned(qld, torch, steps, eval_batches):
     d.close()
     flop_step = Lr.flops_per_pixel_step() * B * H * W
     flop_fwd = 2 * (18 * 32 + 2 * 288 * 32 + 288) * B * H * W
+    return {"shape": [B, H, W], "gen_s": gen_s, "gen_pairs_per_s": round(B / gen_s, 1),
+            "gen_samples_per_s": round(B * H * W * 4 * M_L / gen_s),
+            "step_ms": round(step_ms, 3), "step_tflops": round(flop_step / (step_ms * 1e-3) / 1e12, 1),
+            "forward_ms": round(fwd_ms, 3), "forward_tflops": round(flop_fwd / (fwd_ms * 1e-3) / 1e12, 1),
+            "inference_ms_per_tile": round(fwd_ms / B, 4), "mfma_peak_tflops": 2500.0}
+
+
+def bench_learned(qld, torch, steps, eval_batches):
+    """Learned short-window path at its tile size: 512 x 512 tiles, M_S = 8
+    cycles in, bias-reduced M_L = 512-cycle amplitude out (64x fewer frames)."""
+    import numpy as np
+    from paper_1511_03390_amd import learned as Lr
+    H = W = 512
+    B, M_S, M_L = 8, 8, 512
+    ls = bench_learned_step(qld, torch, 20, H, W, B, M_S, M_L)
     # Training run and held-out evaluation (held-out tiles: scene seeds of
     # batches 10^6.., disjoint from the training batches 0..steps-1).
     d, hist, train_s = Lr.train(steps=steps, batch=B, H=H, W=W, M_S=M_S, M_L=M_L, lr=2e-3)
@@ -696,11 +706,7 @@ def bench_learned(qld, torch, steps, eval_batches):
                         "bias-reduced M_L=512 amplitude target (64x fewer frames)",
             "pairs_trained": steps * B, "train_s": round(train_s, 2),
             "train_px_per_s": round(steps * B * H * W / train_s),
-            "gen_pairs_per_s": round(B / gen_s, 1), "gen_samples_per_s": round(B * H * W * 4 * M_L / gen_s),
-            "step_ms": round(step_ms, 3), "step_tflops": round(flop_step / (step_ms * 1e-3) / 1e12, 1),
-            "forward_ms": round(fwd_ms, 3), "forward_tflops": round(flop_fwd / (fwd_ms * 1e-3) / 1e12, 1),
-            "inference_ms_per_tile": round(fwd_ms / B, 4),
-            "mfma_peak_tflops": 2500.0,
+            **{k: v for k, v in ls.items() if k not in ("shape", "gen_s")},
             "eval_tiles": ev["tiles"], "eval_s": round(ev_s, 2),
             "held_out": "scene seeds of batches 10^6 .. 10^6 + %d, disjoint from training" % (eval_batches - 1),
             "nrmse_vs_noise_free": {k: spread(pt[k]) for k in ("learned", "plain_S", "plain_L",
@@ -845,6 +851,8 @@ def main():
                     help="lay the stack out with frame stride H*W instead of qld_frame_stride_hint")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprofv3 byte counters)")
+    ap.add_argument("--leg", choices=("all", "learned_step"), default="all",
+                    help="learned_step: only the learned path's kernels at 8 x 512^2 (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; "
@@ -856,6 +864,13 @@ def main():
     import scenes
 
     torch.cuda.set_device(0)
+    if args.leg == "learned_step":
+        log("learned path kernels at 8 x 512 x 512")
+        out = {"leg": "learned_step", "learned_step": bench_learned_step(qld, torch)}
+        if args.copy_calibration:
+            out["copy_calibration"] = copy_calibration(torch)
+        print(json.dumps(out), flush=True)
+        return
     fstride = H * W if args.dense else qld.frame_stride_hint(H, W)
     log("generating the 1024x1024x1024 uint16 stack on the GPU (frame stride %d elements)" % fstride)
     st = scenes.diffuse_scene_u16(device="cuda", frame_stride=fstride)
