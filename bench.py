@@ -636,6 +636,7 @@ def bench_learned_step(qld, torch, reps=20, H=512, W=512, B=8, M_S=8, M_L=512):
     then the denoiser's training step (forward, backward, Adam) and forward
     alone, each `reps` times back to back, timed by events."""
     from paper_1511_03390_amd import learned as Lr
+    Lr.tile_batch(10 ** 7 + 4, B, H, W, M_S, M_L, 1)      # first call: module load, allocations
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(4):

@@ -101,109 +101,150 @@ __device__ __forceinline__ bool tile_of(int H, int W, int &b, int &y, int &x0) {
 
 // ---------------------------------------------------------------------------
 // 3x3 convolutions with 32 input channels on the matrix cores (implicit GEMM).
-// A work-group computes 4 output rows x 64 pixels: it stages its input tile
-// (rows y0-1 .. y0+4, pixels x0-1 .. x0+64, 32 channels, zero outside the
-// image; 25 KB) in LDS once, each lane keeps its B-operand fragments of all 9
-// taps in registers, and wave w computes output row y0 + w: per tap and group
-// of 16 pixels one 16-byte LDS read (a lane's 8 input channels of one pixel;
-// the 64 lanes read 1 KiB contiguous) and one MFMA per 16 output channels.
+// A tile is 4 output rows x 64 pixels: its input (rows y0-1 .. y0+4, pixels
+// x0-1 .. x0+64, 32 channels, zero outside the image; 25 KB) is staged in LDS
+// once, each lane keeps its B-operand fragments of all 9 taps in registers,
+// and wave w computes output row y0 + w: per tap and group of 16 pixels one
+// 16-byte LDS read (a lane's 8 input channels of one pixel; the 64 lanes read
+// 1 KiB contiguous) and one MFMA per 16 output channels.
+// The grid is persistent: a work-group loads its weights once and walks tiles
+// blockIdx.x, + gridDim.x, ...; the next tile's input (7 16-byte loads per
+// lane, all issued before any is waited for) is in flight while the current
+// tile's products run, so the HBM latency is covered by the loop itself
+// rather than by other resident work-groups.
 // MODE 0 (forward):        out = bf16(relu(sum_tap in[p + tap] W[tap] + bias))
 // MODE 1 (input gradient): out = bf16((sum_tap in[p - tap] W^T[tap]) * (act[p] > 0))
 // MODE 2 (output layer):   y   = sum_tap in[p + tap] . w4[tap] + b4 (fp32; the
 //                          weights form one 16-column block with column 0 used)
 // ---------------------------------------------------------------------------
+constexpr int kTileItems = (kRows + 2) * (kCols + 2) * 4;   // 16-byte items of an input tile
+constexpr int kTilePer = (kTileItems + 255) / 256;          // per lane
+
 template <int MODE>
-__global__ __launch_bounds__(256) void conv_tile_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
+__global__ __launch_bounds__(256, 2) void conv_tile_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
                                                         const float *__restrict__ bias, const __bf16 *__restrict__ act,
-                                                        void *__restrict__ out, int H, int W) {
+                                                        void *__restrict__ out, int H, int W, int n_tiles) {
     constexpr int NCB = MODE == 2 ? 1 : 2;          // 16-channel output blocks
     __shared__ __align__(16) __bf16 tile[kRows + 2][kCols + 2][32];
     const int tx = (W + kCols - 1) / kCols, ty = (H + kRows - 1) / kRows;
-    int id = blockIdx.x;
-    const int x0 = (id % tx) * kCols;
-    id /= tx;
-    const int y0 = (id % ty) * kRows;
-    const int b = id / ty;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
-    const int64_t img = (int64_t)b * H;
     bf16x8 w[9][NCB];
 #pragma unroll
     for (int k = 0; k < 9; ++k)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
             w[k][cb] = *reinterpret_cast<const bf16x8 *>(wt + ((k * 16 * NCB + cb * 16 + m) * 32 + kb * 8));
-    for (int item = t; item < (kRows + 2) * (kCols + 2) * 4; item += 256) {
-        const int cg = item & 3, q = item >> 2, px = q % (kCols + 2), r = q / (kCols + 2);
-        const int iy = y0 - 1 + r, ix = x0 - 1 + px;
-        bf16x8 v = zero8();
-        if (iy >= 0 && iy < H && ix >= 0 && ix < W)
-            v = *reinterpret_cast<const bf16x8 *>(in + ((img + iy) * W + ix) * 32 + cg * 8);
-        *reinterpret_cast<bf16x8 *>(&tile[r][px][cg * 8]) = v;
-    }
-    __syncthreads();
-    f32x4 acc[4][NCB];
+    float bco[NCB];
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+    for (int cb = 0; cb < NCB; ++cb) bco[cb] = MODE == 1 ? 0.f : bias[MODE == 2 ? 0 : 16 * cb + m];
+
+    bf16x8 v[kTilePer];
+    auto fetch = [&](int tl) {
+        const int x0 = (tl % tx) * kCols, y0 = ((tl / tx) % ty) * kRows;
+        const int64_t img = (int64_t)(tl / (tx * ty)) * H;
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[g][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int sy = MODE == 1 ? -tap_dy(k) : tap_dy(k);
-        const int sx = MODE == 1 ? -tap_dx(k) : tap_dx(k);
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&tile[wave + 1 + sy][16 * g + m + 1 + sx][kb * 8]);
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) acc[g][cb] = mfma16(a, w[k][cb], acc[g][cb]);
+        for (int j = 0; j < kTilePer; ++j) {
+            const int item = t + 256 * j;
+            const int cg = item & 3, q = item >> 2, px = q % (kCols + 2), r = q / (kCols + 2);
+            const int iy = y0 - 1 + r, ix = x0 - 1 + px;
+            const bool ok = item < kTileItems && iy >= 0 && iy < H && ix >= 0 && ix < W;
+            v[j] = ok ? *reinterpret_cast<const bf16x8 *>(in + ((img + iy) * W + ix) * 32 + cg * 8) : zero8();
         }
-    }
-    const int y = y0 + wave;
-    if constexpr (MODE == 2) {
-        if (y >= H) return;
+    };
+    if (blockIdx.x < (unsigned)n_tiles) fetch(blockIdx.x);
+    for (int tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
+        const int x0 = (tl % tx) * kCols, y0 = ((tl / tx) % ty) * kRows;
+        const int64_t img = (int64_t)(tl / (tx * ty)) * H;
+        const int y = y0 + wave;
+        __syncthreads();                              // the previous tile's LDS readers are done
+        // Item i is the 16 bytes at offset 16 i of the tile (row, pixel, channel group).
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int px = x0 + 16 * g + 4 * kb + i;
-                if (px < W && m == 0) static_cast<float *>(out)[(img + y) * W + px] = acc[g][0][i] + bias[0];
-            }
-    } else {
-        // The wave's 64 pixels x 32 channels go out through LDS (the input
-        // tile is no longer read): each lane writes its bf16 results (MODE 0:
-        // bias and ReLU applied first), then moves four 16-byte chunks, so the
-        // global stores (and MODE 1's ReLU-mask loads) are 1 KiB contiguous
-        // per instruction.  Rounding before masking equals masking first (the
-        // mask is 0 or 1).  Rows of 40 channels keep the writes conflict-free.
-        constexpr int kORow = 40;
-        __bf16(*ot)[kORow] = reinterpret_cast<__bf16(*)[kORow]>(&tile[0][0][0]) + wave * 64;
-        static_assert(4 * 64 * kORow * sizeof(__bf16) <= sizeof(tile), "output staging fits in the tile");
-        __syncthreads();                                  // every wave is done reading the input tile
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) {
-                    const int co = 16 * cb + m;
-                    float v = acc[g][cb][i];
-                    if (MODE == 0) v = fmaxf(v + bias[co], 0.0f);
-                    ot[16 * g + 4 * kb + i][co] = (__bf16)v;
-                }
+        for (int j = 0; j < kTilePer; ++j) {
+            const int item = t + 256 * j;
+            if (item < kTileItems) reinterpret_cast<bf16x8 *>(&tile[0][0][0])[item] = v[j];
+        }
         __syncthreads();
-        if (y >= H) return;
+        if (tl + (int)gridDim.x < n_tiles) fetch(tl + gridDim.x);
+        // MODE 1: the ReLU mask of this wave's outputs, loaded ahead of the products.
+        bf16x8 am[4];
+        if constexpr (MODE == 1) {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int j = lane + 64 * jj, pl = j >> 2, cg = j & 3;
-            const int px = x0 + pl;
-            if (px >= W) continue;
-            const int64_t idx = ((img + y) * W + px) * 32 + cg * 8;
-            bf16x8 v = *reinterpret_cast<const bf16x8 *>(&ot[pl][cg * 8]);
-            if constexpr (MODE == 1) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(act + idx);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = (float)a[e] > 0.0f ? v[e] : (__bf16)0.0f;
+            for (int jj = 0; jj < 4; ++jj) {
+                const int j = lane + 64 * jj, pl = j >> 2, cg = j & 3;
+                const int px = x0 + pl;
+                am[jj] = y < H && px < W ? *reinterpret_cast<const bf16x8 *>(act + ((img + y) * W + px) * 32 + cg * 8)
+                                         : zero8();
             }
-            *reinterpret_cast<bf16x8 *>(static_cast<__bf16 *>(out) + idx) = v;
+        }
+        f32x4 acc[4][NCB];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[g][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int sy = MODE == 1 ? -tap_dy(k) : tap_dy(k);
+            const int sx = MODE == 1 ? -tap_dx(k) : tap_dx(k);
+            bf16x8 a[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                a[g] = *reinterpret_cast<const bf16x8 *>(&tile[wave + 1 + sy][16 * g + m + 1 + sx][kb * 8]);
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[g][cb] = mfma16(a[g], w[k][cb], acc[g][cb]);
+        }
+        if constexpr (MODE == 2) {
+            if (y < H && m == 0) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int px = x0 + 16 * g + 4 * kb + i;
+                        if (px < W) static_cast<float *>(out)[(img + y) * W + px] = acc[g][0][i] + bco[0];
+                    }
+            }
+        } else {
+            // The wave's 64 pixels x 32 channels go out through LDS (the input
+            // tile is no longer read): each lane writes its bf16 results (MODE 0:
+            // bias and ReLU applied first), then moves four 16-byte chunks, so the
+            // global stores are 1 KiB contiguous per instruction.  Rounding before
+            // masking equals masking first (the mask is 0 or 1).  Rows of 40
+            // channels keep the writes conflict-free.
+            constexpr int kORow = 40;
+            __bf16(*ot)[kORow] = reinterpret_cast<__bf16(*)[kORow]>(&tile[0][0][0]) + wave * 64;
+            static_assert(4 * 64 * kORow * sizeof(__bf16) <= sizeof(tile), "output staging fits in the tile");
+            __syncthreads();                              // every wave is done reading the input tile
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        const int co = 16 * cb + m;
+                        float vv = acc[g][cb][i];
+                        if (MODE == 0) vv = fmaxf(vv + bco[cb], 0.0f);
+                        ot[16 * g + 4 * kb + i][co] = (__bf16)vv;
+                    }
+            // Only this wave reads back what it wrote.
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (y < H) {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int j = lane + 64 * jj, pl = j >> 2, cg = j & 3;
+                    const int px = x0 + pl;
+                    if (px >= W) continue;
+                    const int64_t idx = ((img + y) * W + px) * 32 + cg * 8;
+                    bf16x8 o = *reinterpret_cast<const bf16x8 *>(&ot[pl][cg * 8]);
+                    if constexpr (MODE == 1) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) o[e] = (float)am[jj][e] > 0.0f ? o[e] : (__bf16)0.0f;
+                    }
+                    *reinterpret_cast<bf16x8 *>(static_cast<__bf16 *>(out) + idx) = o;
+                }
+            }
         }
     }
 }
@@ -298,17 +339,28 @@ __global__ __launch_bounds__(256) void out_back_kernel(const float *__restrict__
     if (p >= n) return;
     const int x = (int)(p % W), y = (int)((p / W) % H);
     const int64_t b = p / ((int64_t)H * W);
+    // Every load is issued before the arithmetic: this lane's activation, its
+    // 8 channels' weights of the nine taps (16-byte loads) and the nine
+    // neighbours' dy (an out-of-image tap reads the pixel itself and is
+    // skipped below, as if absent).
+    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a3 + p * 32 + cg * 8);
+    bf16x8 wv[9];
+    float g[9];
+    bool ok[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int iy = y - tap_dy(t), ix = x - tap_dx(t);
+        ok[t] = iy >= 0 && iy < H && ix >= 0 && ix < W;
+        wv[t] = *reinterpret_cast<const bf16x8 *>(w4 + t * 32 + cg * 8);
+        g[t] = dy[ok[t] ? (b * H + iy) * W + ix : p];
+    }
     float acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
-    for (int t = 0; t < 9; ++t) {
-        const int iy = y - tap_dy(t), ix = x - tap_dx(t);
-        if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
-        const float g = dy[(b * H + iy) * W + ix];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = fmaf(g, (float)w4[t * 32 + cg * 8 + c], acc[c]);
-    }
-    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a3 + p * 32 + cg * 8);
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = ok[t] ? fmaf(g[t], (float)wv[t][c], acc[c]) : acc[c];
     bf16x8 o;
 #pragma unroll
     for (int c = 0; c < 8; ++c) o[c] = (__bf16)((float)av[c] > 0.f ? acc[c] : 0.f);
@@ -318,100 +370,124 @@ __global__ __launch_bounds__(256) void out_back_kernel(const float *__restrict__
 // 32x32 weight gradient on the matrix cores: D[tap][ci][co] = sum_px a[px + tap][ci] dz[px][co]
 // (v_mfma_f32_16x16x32_bf16: M = co, N = ci, K = 32 pixels).  An MFMA operand
 // lane holds 8 consecutive pixels of one channel, so a work-group stages each
-// 64-pixel row segment transposed in LDS: dT[co][px] from dz, and aT[r][ci][px]
-// from the three input rows around it (pixels x0-1 .. x0+64, zero outside the
+// 64-pixel row segment transposed in LDS: dT[co][px] from dz, and aT[slot][ci][px]
+// from the input rows around it (pixels x0-1 .. x0+64, zero outside the
 // image).  A lane then reads its 8 pixels with one 16-byte LDS read; the taps
 // at dx = -1 / +1 combine two aligned reads with a 16-bit funnel shift.  Wave w
 // owns the 16x16 block (co block w & 1, ci block w >> 1) for all 9 taps; waves
-// 0 and 1 also sum their dz operands for the bias gradient.  Segments are
-// dealt round-robin to work-groups; each writes one row of partial sums
-// part[block][tap][ci][co] followed by the 32 bias sums (the canonical order
-// of W and b), summed later in a fixed order.
+// 0 and 1 also sum their dz operands for the bias gradient.
+// Work units are vertical runs of `rows` rows of one 64-pixel strip, walked
+// top to bottom: the input rows y-1, y, y+1 sit in a three-slot ring (row r
+// in slot (r + 3) % 3), so each row of `a` is loaded and transposed once per
+// unit instead of three times, and row y+2 of `a` and row y+1 of dz are in
+// flight while row y's products run.  Units are dealt round-robin to
+// work-groups; each writes one row of partial sums part[block][tap][ci][co]
+// followed by the 32 bias sums (the canonical order of W and b), summed later
+// in a fixed order.
 constexpr int kSegPx = 64;
 constexpr int kAStride = 88;   // bf16 per aT row: pixels x0-8 .. x0+71 (+8 pad); 176 B, 16-B multiple
 constexpr int kDStride = 72;   // bf16 per dT row: 64 pixels (+8 pad); 144 B
 constexpr int kW32Row = 9 * 1024 + 32;   // partial row: weights then bias
+constexpr int kARowItems = 4 * 66;       // 16-byte items of one row of `a` (4 channel groups x 66 pixels)
 
 typedef uint32_t u32x4w __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ int ring_slot(int r) { return (r + 3) % 3; }
+
 __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a, const __bf16 *__restrict__ dz, int B,
-                                                   int H, int W, float *__restrict__ part) {
+                                                   int H, int W, int rows, float *__restrict__ part) {
     __shared__ __align__(16) __bf16 aT[3][32][kAStride];
     __shared__ __align__(16) __bf16 dT[32][kDStride];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
     const int cb = wave & 1, cib = wave >> 1;
-    const int segs_x = (W + kSegPx - 1) / kSegPx;
-    const int64_t n_seg = (int64_t)B * H * segs_x;
+    const int segs_x = (W + kSegPx - 1) / kSegPx, runs_y = (H + rows - 1) / rows;
+    const int64_t n_units = (int64_t)B * segs_x * runs_y;
     f32x4 acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
     const bf16x8 zero = zero8();
-    // A segment's global loads: dz of pixel x0 + (t & 63), channels 8 (t >> 6)
-    // .. +8; a of rows y-1, y, y+1, pixels x0-1 .. x0+64 (3 x 4 x 66 16-byte
-    // items, item t + 256 i for lane t).  The next segment's are issued before
-    // the current one's matrix products, so they are in flight meanwhile.
-    constexpr int kAItems = 3 * 4 * 66;
-    bf16x8 vd, va[4];
-    auto fetch = [&](int64_t sg) {
-        const int x0 = (int)(sg % segs_x) * kSegPx;
-        const int64_t row = sg / segs_x;            // b * H + y
-        const int y = (int)(row % H);
-        const int x = x0 + (t & 63);
-        vd = x < W ? *reinterpret_cast<const bf16x8 *>(dz + (row * W + x) * 32 + (t >> 6) * 8) : zero;
+    // Row iy of `a` (item t + 256 i: pixel x0 - 1 + item % 66, channels
+    // 8 (item / 66) .. +8), and row y of dz (pixel x0 + (t & 63), channels
+    // 8 (t >> 6) .. +8); rows outside the image read as zero.
+    bf16x8 va[2], vd;
+    auto fetch_a = [&](int64_t img, int x0, int iy) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 2; ++i) {
             const int item = t + 256 * i;
-            const int px = item % 66, q = item / 66, cg = q & 3, r = q >> 2;
-            const int xa = x0 - 1 + px, iy = y + r - 1;
-            const bool ok = item < kAItems && xa >= 0 && xa < W && iy >= 0 && iy < H;
-            va[i] = ok ? *reinterpret_cast<const bf16x8 *>(a + ((row - y + iy) * W + xa) * 32 + cg * 8) : zero;
+            const int px = item % 66, cg = item / 66;
+            const int xa = x0 - 1 + px;
+            const bool ok = item < kARowItems && xa >= 0 && xa < W && iy >= 0 && iy < H;
+            va[i] = ok ? *reinterpret_cast<const bf16x8 *>(a + ((img + iy) * W + xa) * 32 + cg * 8) : zero;
         }
     };
-    if ((int64_t)blockIdx.x < n_seg) fetch(blockIdx.x);
-    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
-        __syncthreads();                            // the previous segment's readers are done
-        {
-            const int px = t & 63, cg = t >> 6;
+    auto store_a = [&](int slot) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = vd[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 2; ++i) {
             const int item = t + 256 * i;
-            if (item < kAItems) {
-                const int px = item % 66, q = item / 66, cg = q & 3, r = q >> 2;
+            if (item < kARowItems) {
+                const int px = item % 66, cg = item / 66;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) aT[r][cg * 8 + e][px + 7] = va[i][e];
+                for (int e = 0; e < 8; ++e) aT[slot][cg * 8 + e][px + 7] = va[i][e];
             }
         }
-        __syncthreads();
-        if (sg + gridDim.x < n_seg) fetch(sg + gridDim.x);
+    };
+    auto fetch_d = [&](int64_t img, int x0, int y) {
+        const int x = x0 + (t & 63);
+        vd = x < W ? *reinterpret_cast<const bf16x8 *>(dz + ((img + y) * W + x) * 32 + (t >> 6) * 8) : zero;
+    };
+    auto store_d = [&]() {
+        const int px = t & 63, cg = t >> 6;
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-            const int pxb = kk * 32 + kb * 8;       // this lane's 8 pixels: x0 + pxb .. +8
-            const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&dT[cb * 16 + m][pxb]);
-            if (cib == 0) {
-                float sb = 0.f;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) sb += (float)A[e];
-                bacc += sb;
+        for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = vd[i];
+    };
+    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const int x0 = (int)(u % segs_x) * kSegPx;
+        const int64_t q = u / segs_x;
+        const int y_begin = (int)(q % runs_y) * rows, y_end = min(H, y_begin + rows);
+        const int64_t img = (q / runs_y) * H;
+        __syncthreads();                            // the previous unit's readers are done
+        fetch_a(img, x0, y_begin - 1);
+        store_a(ring_slot(y_begin - 1));
+        fetch_a(img, x0, y_begin);
+        store_a(ring_slot(y_begin));
+        fetch_a(img, x0, y_begin + 1);
+        fetch_d(img, x0, y_begin);
+        for (int y = y_begin; y < y_end; ++y) {
+            __syncthreads();                        // readers of row y-2's slot and of dT are done
+            store_a(ring_slot(y + 1));
+            store_d();
+            __syncthreads();
+            if (y + 1 < y_end) {
+                fetch_a(img, x0, y + 2);
+                fetch_d(img, x0, y + 1);
             }
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const __bf16 *rp = &aT[r][cib * 16 + m][0];
-                const u32x4w pv = *reinterpret_cast<const u32x4w *>(rp + pxb);        // pixels pxb-8 ..
-                const u32x4w c = *reinterpret_cast<const u32x4w *>(rp + pxb + 8);     // pixels pxb ..
-                const u32x4w nx = *reinterpret_cast<const u32x4w *>(rp + pxb + 16);   // pixels pxb+8 ..
-                u32x4w lft, rgt;                                                      // shifted by -1 / +1
+            for (int kk = 0; kk < 2; ++kk) {
+                const int pxb = kk * 32 + kb * 8;       // this lane's 8 pixels: x0 + pxb .. +8
+                const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&dT[cb * 16 + m][pxb]);
+                if (cib == 0) {
+                    float sb = 0.f;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    lft[k] = __builtin_amdgcn_alignbit(c[k], k ? c[k - 1] : pv[3], 16);
-                    rgt[k] = __builtin_amdgcn_alignbit(k < 3 ? c[k + 1] : nx[0], c[k], 16);
+                    for (int e = 0; e < 8; ++e) sb += (float)A[e];
+                    bacc += sb;
                 }
-                acc[3 * r + 0] = mfma16(A, __builtin_bit_cast(bf16x8, lft), acc[3 * r + 0]);
-                acc[3 * r + 1] = mfma16(A, __builtin_bit_cast(bf16x8, c), acc[3 * r + 1]);
-                acc[3 * r + 2] = mfma16(A, __builtin_bit_cast(bf16x8, rgt), acc[3 * r + 2]);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const __bf16 *rp = &aT[ring_slot(y - 1 + r)][cib * 16 + m][0];
+                    const u32x4w pv = *reinterpret_cast<const u32x4w *>(rp + pxb);        // pixels pxb-8 ..
+                    const u32x4w c = *reinterpret_cast<const u32x4w *>(rp + pxb + 8);     // pixels pxb ..
+                    const u32x4w nx = *reinterpret_cast<const u32x4w *>(rp + pxb + 16);   // pixels pxb+8 ..
+                    u32x4w lft, rgt;                                                      // shifted by -1 / +1
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        lft[k] = __builtin_amdgcn_alignbit(c[k], k ? c[k - 1] : pv[3], 16);
+                        rgt[k] = __builtin_amdgcn_alignbit(k < 3 ? c[k + 1] : nx[0], c[k], 16);
+                    }
+                    acc[3 * r + 0] = mfma16(A, __builtin_bit_cast(bf16x8, lft), acc[3 * r + 0]);
+                    acc[3 * r + 1] = mfma16(A, __builtin_bit_cast(bf16x8, c), acc[3 * r + 1]);
+                    acc[3 * r + 2] = mfma16(A, __builtin_bit_cast(bf16x8, rgt), acc[3 * r + 2]);
+                }
             }
         }
     }
@@ -774,7 +850,16 @@ struct qld_denoiser {
 namespace qld {
 namespace {
 
-constexpr int kGradBlocks = 512;     // work-groups of the MFMA weight-gradient reduction
+constexpr int kGradBlocks = 512;     // work-groups of the MFMA weight-gradient reductions (dw1)
+constexpr int kW32Blocks = 1024;     // work-groups of dw32_kernel
+
+// Rows per work unit of dw32_kernel: enough units for every work-group, at
+// least 4 rows (each unit loads two halo rows of `a` beyond its own).
+int dw32_rows(int B, int H, int W) {
+    const int64_t strips = (int64_t)B * ceil_div(W, kSegPx);
+    const int64_t want = ceil_div(strips * H, kW32Blocks);
+    return (int)std::min<int64_t>(H, std::max<int64_t>(4, want));
+}
 constexpr int kSmallBlocks = 1024;   // work-groups of the output-layer gradient
 constexpr int kLossBlocks = 256;
 
@@ -793,6 +878,14 @@ qld_status dalloc(qld_denoiser *d, T **p, size_t count) {
 
 int conv_grid(int B, int H, int W) {
     return (int)((int64_t)B * ceil_div(H, kRows) * ceil_div(W, kCols));
+}
+
+// Persistent grid of conv_tile_kernel: at most kConvGroupsPerCU work-groups
+// per CU (a multiple of 8), looping over the tiles.
+constexpr int kConvGroupsPerCU = 2;
+int conv_persistent_grid(int n_tiles) {
+    const int64_t cap = std::max<int64_t>(8, (int64_t)kConvGroupsPerCU * device_cu_count() / 8 * 8);
+    return (int)std::min<int64_t>(n_tiles, cap);
 }
 
 qld_status pack(qld_denoiser *d, hipStream_t s) {
@@ -821,9 +914,10 @@ qld_status reduce_rows(qld_denoiser *d, const float *part, int R, int n, float *
 
 // Weights and bias of a 32 -> 32 layer (the bias follows the weights in the canonical order).
 qld_status dw32(qld_denoiser *d, const __bf16 *a, const __bf16 *dz, int B, int64_t off, hipStream_t s) {
-    hipLaunchKernelGGL(dw32_kernel, dim3(kGradBlocks), dim3(256), 0, s, a, dz, B, d->H, d->W, d->part);
+    hipLaunchKernelGGL(dw32_kernel, dim3(kW32Blocks), dim3(256), 0, s, a, dz, B, d->H, d->W, dw32_rows(B, d->H, d->W),
+                       d->part);
     QLD_TRY(check_hip(hipGetLastError(), "dw32 launch"));
-    return reduce_rows(d, d->part, kGradBlocks, kW32Row, d->grads + off, s);
+    return reduce_rows(d, d->part, kW32Blocks, kW32Row, d->grads + off, s);
 }
 
 // Weights and bias of the input layer.
@@ -859,7 +953,7 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     d->W = W;
     d->max_batch = max_batch;
     const size_t npx = (size_t)max_batch * H * W;
-    d->part_floats = std::max<int64_t>((int64_t)kGradBlocks * kW32Row,
+    d->part_floats = std::max<int64_t>((int64_t)kW32Blocks * kW32Row,
                                        ((int64_t)max_batch * 64 + 4096 + max_batch) * 32);   // >= B * pool_chunks(B) * 32
     qld_status st = QLD_OK;
     if (st == QLD_OK) st = dalloc(d, &d->params, N_ALL);
@@ -1002,12 +1096,13 @@ extern "C" qld_status qld_denoiser_forward(qld_denoiser *d, const float *x, int3
     take_kernel_timer(&ev0, &ev1);
     if (ev0) QLD_TRY(check_hip(hipEventRecord(ev0, s), "timer start"));
     hipLaunchKernelGGL(conv1_kernel, dim3(g), dim3(256), 0, s, d->x0, d->w1f, d->params + OFF_B1, d->a1, H, W);
-    hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(g), dim3(256), 0, s, d->a1, d->w2f, d->params + OFF_B2, nullptr, d->a2,
-                       H, W);
-    hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(g), dim3(256), 0, s, d->a2, d->w3f, d->params + OFF_B3, nullptr, d->a3,
-                       H, W);
-    hipLaunchKernelGGL((conv_tile_kernel<2>), dim3(g), dim3(256), 0, s, d->a3, d->w4f, d->params + OFF_B4, nullptr,
-                       d->y, H, W);
+    const int gp = conv_persistent_grid(g);
+    hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(gp), dim3(256), 0, s, d->a1, d->w2f, d->params + OFF_B2, nullptr,
+                       d->a2, H, W, g);
+    hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(gp), dim3(256), 0, s, d->a2, d->w3f, d->params + OFF_B3, nullptr,
+                       d->a3, H, W, g);
+    hipLaunchKernelGGL((conv_tile_kernel<2>), dim3(gp), dim3(256), 0, s, d->a3, d->w4f, d->params + OFF_B4, nullptr,
+                       d->y, H, W, g);
     if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
     const int chunks = pool_chunks(B);
     hipLaunchKernelGGL(pool_kernel, dim3(chunks, B), dim3(256), 0, s, d->a3, (int64_t)H * W, chunks, d->part);
@@ -1037,13 +1132,15 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     QLD_TRY(dw_out(d, B, s));
     hipLaunchKernelGGL(out_back_kernel, dim3((unsigned)ceil_div(4 * npx, 256)), dim3(256), 0, s, d->dy, d->w4,
                        d->a3, d->dzA, B, H, W);
-    const int g = conv_grid(B, H, W);
+    const int g = conv_grid(B, H, W), gp = conv_persistent_grid(g);
     // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
     QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));   // and b3
-    hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(g), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W);
+    hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(gp), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W,
+                       g);
     // Layer 2: dW2 from (a1, dz2); dz1 = bf16(conv^T(dz2, W2) * (a1 > 0)).
     QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));   // and b2
-    hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(g), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W);
+    hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(gp), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W,
+                       g);
     // Layer 1: dW1 from (x0, dz1).
     QLD_TRY(dw1(d, B, s));   // and b1
     // Gate (its own loss; its gradient reaches only Wg, bg).
