@@ -325,48 +325,6 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *__restrict__ y, 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Gradient of the output layer with respect to a3, masked by ReLU, in bf16:
-// dz3[q][c] = bf16((sum_tap dy[q - tap] w4[tap][c]) * (a3[q][c] > 0)).
-__global__ __launch_bounds__(256) void out_back_kernel(const float *__restrict__ dy, const __bf16 *__restrict__ w4,
-                                                       const __bf16 *__restrict__ a3, __bf16 *__restrict__ dz, int B,
-                                                       int H, int W) {
-    // Four lanes per pixel, 8 channels each: a wave's loads of a3 and stores
-    // of dz are 1 KiB contiguous per instruction.
-    const int64_t n = (int64_t)B * H * W;
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = gt >> 2;
-    const int cg = (int)(gt & 3);
-    if (p >= n) return;
-    const int x = (int)(p % W), y = (int)((p / W) % H);
-    const int64_t b = p / ((int64_t)H * W);
-    // Every load is issued before the arithmetic: this lane's activation, its
-    // 8 channels' weights of the nine taps (16-byte loads) and the nine
-    // neighbours' dy (an out-of-image tap reads the pixel itself and is
-    // skipped below, as if absent).
-    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a3 + p * 32 + cg * 8);
-    bf16x8 wv[9];
-    float g[9];
-    bool ok[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int iy = y - tap_dy(t), ix = x - tap_dx(t);
-        ok[t] = iy >= 0 && iy < H && ix >= 0 && ix < W;
-        wv[t] = *reinterpret_cast<const bf16x8 *>(w4 + t * 32 + cg * 8);
-        g[t] = dy[ok[t] ? (b * H + iy) * W + ix : p];
-    }
-    float acc[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
-#pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = ok[t] ? fmaf(g[t], (float)wv[t][c], acc[c]) : acc[c];
-    bf16x8 o;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) o[c] = (__bf16)((float)av[c] > 0.f ? acc[c] : 0.f);
-    *reinterpret_cast<bf16x8 *>(dz + p * 32 + cg * 8) = o;
-}
-
 // 32x32 weight gradient on the matrix cores: D[tap][ci][co] = sum_px a[px + tap][ci] dz[px][co]
 // (v_mfma_f32_16x16x32_bf16: M = co, N = ci, K = 32 pixels).  An MFMA operand
 // lane holds 8 consecutive pixels of one channel, so a work-group stages each
@@ -379,8 +337,8 @@ __global__ __launch_bounds__(256) void out_back_kernel(const float *__restrict__
 // Work units are vertical runs of `rows` rows of one 64-pixel strip, walked
 // top to bottom: the input rows y-1, y, y+1 sit in a three-slot ring (row r
 // in slot (r + 3) % 3), so each row of `a` is loaded and transposed once per
-// unit instead of three times, and row y+2 of `a` and row y+1 of dz are in
-// flight while row y's products run.  Units are dealt round-robin to
+// unit instead of three times, and rows y+2, y+3 of `a` and y+1, y+2 of dz
+// are in flight while row y's products run.  Units are dealt round-robin to
 // work-groups; each writes one row of partial sums part[block][tap][ci][co]
 // followed by the 32 bias sums (the canonical order of W and b), summed later
 // in a fixed order.
@@ -410,36 +368,85 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
     // Row iy of `a` (item t + 256 i: pixel x0 - 1 + item % 66, channels
     // 8 (item / 66) .. +8), and row y of dz (pixel x0 + (t & 63), channels
     // 8 (t >> 6) .. +8); rows outside the image read as zero.
-    bf16x8 va[2], vd;
-    auto fetch_a = [&](int64_t img, int x0, int iy) {
+    // Register buffers: P holds the rows at an even distance from the unit's
+    // first row, Q those at an odd one; with the loop unrolled by two rows the
+    // buffer of every row is known at compile time, and two rows of each input
+    // are in flight while a row is worked.
+    struct Buf {
+        bf16x8 va[2], vd;
+    } P, Q;
+    auto fetch_a = [&](Buf &bf, int64_t img, int x0, int iy) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int item = t + 256 * i;
             const int px = item % 66, cg = item / 66;
             const int xa = x0 - 1 + px;
             const bool ok = item < kARowItems && xa >= 0 && xa < W && iy >= 0 && iy < H;
-            va[i] = ok ? *reinterpret_cast<const bf16x8 *>(a + ((img + iy) * W + xa) * 32 + cg * 8) : zero;
+            bf.va[i] = ok ? *reinterpret_cast<const bf16x8 *>(a + ((img + iy) * W + xa) * 32 + cg * 8) : zero;
         }
     };
-    auto store_a = [&](int slot) {
+    auto store_a = [&](const Buf &bf, int slot) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int item = t + 256 * i;
             if (item < kARowItems) {
                 const int px = item % 66, cg = item / 66;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) aT[slot][cg * 8 + e][px + 7] = va[i][e];
+                for (int e = 0; e < 8; ++e) aT[slot][cg * 8 + e][px + 7] = bf.va[i][e];
             }
         }
     };
-    auto fetch_d = [&](int64_t img, int x0, int y) {
+    auto fetch_d = [&](Buf &bf, int64_t img, int x0, int y) {
         const int x = x0 + (t & 63);
-        vd = x < W ? *reinterpret_cast<const bf16x8 *>(dz + ((img + y) * W + x) * 32 + (t >> 6) * 8) : zero;
+        bf.vd = x < W ? *reinterpret_cast<const bf16x8 *>(dz + ((img + y) * W + x) * 32 + (t >> 6) * 8) : zero;
     };
-    auto store_d = [&]() {
+    auto store_d = [&](const Buf &bf) {
         const int px = t & 63, cg = t >> 6;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = vd[i];
+        for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = bf.vd[i];
+    };
+    auto products = [&](int y) {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int pxb = kk * 32 + kb * 8;       // this lane's 8 pixels: x0 + pxb .. +8
+            const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&dT[cb * 16 + m][pxb]);
+            if (cib == 0) {
+                float sb = 0.f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sb += (float)A[e];
+                bacc += sb;
+            }
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const __bf16 *rp = &aT[ring_slot(y - 1 + r)][cib * 16 + m][0];
+                const u32x4w pv = *reinterpret_cast<const u32x4w *>(rp + pxb);        // pixels pxb-8 ..
+                const u32x4w c = *reinterpret_cast<const u32x4w *>(rp + pxb + 8);     // pixels pxb ..
+                const u32x4w nx = *reinterpret_cast<const u32x4w *>(rp + pxb + 16);   // pixels pxb+8 ..
+                u32x4w lft, rgt;                                                      // shifted by -1 / +1
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    lft[k] = __builtin_amdgcn_alignbit(c[k], k ? c[k - 1] : pv[3], 16);
+                    rgt[k] = __builtin_amdgcn_alignbit(k < 3 ? c[k + 1] : nx[0], c[k], 16);
+                }
+                acc[3 * r + 0] = mfma16(A, __builtin_bit_cast(bf16x8, lft), acc[3 * r + 0]);
+                acc[3 * r + 1] = mfma16(A, __builtin_bit_cast(bf16x8, c), acc[3 * r + 1]);
+                acc[3 * r + 2] = mfma16(A, __builtin_bit_cast(bf16x8, rgt), acc[3 * r + 2]);
+            }
+        }
+    };
+    // Row y (k = y - y_begin): a-row y+1 comes from the buffer of parity k+1,
+    // d-row y from that of parity k; a-row y+3 and d-row y+2 are then fetched
+    // into the buffers just emptied.
+    auto step = [&](Buf &even, Buf &odd, int64_t img, int x0, int y, int y_end) {
+        __syncthreads();                            // readers of row y-2's slot and of dT are done
+        store_a(odd, ring_slot(y + 1));
+        store_d(even);
+        __syncthreads();
+        if (y + 2 < y_end) {
+            fetch_a(odd, img, x0, y + 3);
+            fetch_d(even, img, x0, y + 2);
+        }
+        products(y);
     };
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int x0 = (int)(u % segs_x) * kSegPx;
@@ -447,48 +454,17 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
         const int y_begin = (int)(q % runs_y) * rows, y_end = min(H, y_begin + rows);
         const int64_t img = (q / runs_y) * H;
         __syncthreads();                            // the previous unit's readers are done
-        fetch_a(img, x0, y_begin - 1);
-        store_a(ring_slot(y_begin - 1));
-        fetch_a(img, x0, y_begin);
-        store_a(ring_slot(y_begin));
-        fetch_a(img, x0, y_begin + 1);
-        fetch_d(img, x0, y_begin);
-        for (int y = y_begin; y < y_end; ++y) {
-            __syncthreads();                        // readers of row y-2's slot and of dT are done
-            store_a(ring_slot(y + 1));
-            store_d();
-            __syncthreads();
-            if (y + 1 < y_end) {
-                fetch_a(img, x0, y + 2);
-                fetch_d(img, x0, y + 1);
-            }
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                const int pxb = kk * 32 + kb * 8;       // this lane's 8 pixels: x0 + pxb .. +8
-                const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&dT[cb * 16 + m][pxb]);
-                if (cib == 0) {
-                    float sb = 0.f;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) sb += (float)A[e];
-                    bacc += sb;
-                }
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const __bf16 *rp = &aT[ring_slot(y - 1 + r)][cib * 16 + m][0];
-                    const u32x4w pv = *reinterpret_cast<const u32x4w *>(rp + pxb);        // pixels pxb-8 ..
-                    const u32x4w c = *reinterpret_cast<const u32x4w *>(rp + pxb + 8);     // pixels pxb ..
-                    const u32x4w nx = *reinterpret_cast<const u32x4w *>(rp + pxb + 16);   // pixels pxb+8 ..
-                    u32x4w lft, rgt;                                                      // shifted by -1 / +1
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        lft[k] = __builtin_amdgcn_alignbit(c[k], k ? c[k - 1] : pv[3], 16);
-                        rgt[k] = __builtin_amdgcn_alignbit(k < 3 ? c[k + 1] : nx[0], c[k], 16);
-                    }
-                    acc[3 * r + 0] = mfma16(A, __builtin_bit_cast(bf16x8, lft), acc[3 * r + 0]);
-                    acc[3 * r + 1] = mfma16(A, __builtin_bit_cast(bf16x8, c), acc[3 * r + 1]);
-                    acc[3 * r + 2] = mfma16(A, __builtin_bit_cast(bf16x8, rgt), acc[3 * r + 2]);
-                }
-            }
+        fetch_a(P, img, x0, y_begin - 1);
+        store_a(P, ring_slot(y_begin - 1));
+        fetch_a(P, img, x0, y_begin);
+        store_a(P, ring_slot(y_begin));
+        fetch_a(Q, img, x0, y_begin + 1);           // a-rows y_begin+1 (odd), y_begin+2 (even)
+        fetch_a(P, img, x0, y_begin + 2);
+        fetch_d(P, img, x0, y_begin);               // d-rows y_begin (even), y_begin+1 (odd)
+        if (y_begin + 1 < y_end) fetch_d(Q, img, x0, y_begin + 1);
+        for (int y = y_begin; y < y_end; y += 2) {
+            step(P, Q, img, x0, y, y_end);
+            if (y + 1 < y_end) step(Q, P, img, x0, y + 1, y_end);
         }
     }
     float *pb = part + (int64_t)blockIdx.x * kW32Row;
@@ -509,14 +485,16 @@ __global__ __launch_bounds__(256) void dw32_kernel(const __bf16 *__restrict__ a,
 // Input layer (2 -> 32) weight and bias gradients on the matrix cores:
 // dW1[tap][ci][co] = sum_px x0[px + tap][ci] dz1[px][co] with M = co, N = the
 // 18 (tap, ci) pairs in two 16-column blocks, K = 32 pixels; db1[co] = sum_px
-// dz1[px][co].  Staged like dw32_kernel: dz1 transposed dT[co][px] and the
-// three input rows transposed xT[r][ci][px].  Wave w: co block w & 1, column
-// block w >> 1; each lane's column (tap, ci) picks the shifted pixel window of
-// its tap.  Partial rows part[block][608]: W1 then b1 (the canonical order).
+// dz1[px][co].  Staged like dw32_kernel (vertical strips, a three-slot ring of
+// input rows, two rows of each input in flight): dz1 transposed dT[co][px]
+// and the input rows transposed xT[slot][ci][px].  Wave w: co block w & 1,
+// column block w >> 1; each lane's column (tap, ci) picks the shifted pixel
+// window of its tap.  Partial rows part[block][608]: W1 then b1 (the
+// canonical order).
 constexpr int kW1Row = 576 + 32;
 
 __global__ __launch_bounds__(256) void dw1_kernel(const __bf16 *__restrict__ x, const __bf16 *__restrict__ dz, int B,
-                                                  int H, int W, float *__restrict__ part) {
+                                                  int H, int W, int rows, float *__restrict__ part) {
     __shared__ __align__(16) __bf16 xT[3][2][kAStride];
     __shared__ __align__(16) __bf16 dT[32][kDStride];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
@@ -524,43 +502,39 @@ __global__ __launch_bounds__(256) void dw1_kernel(const __bf16 *__restrict__ x, 
     const int n = nb * 16 + m;                       // column: tap n / 2, input channel n % 2
     const bool col_ok = n < 18;
     const int tap = col_ok ? n >> 1 : 0, ch = n & 1;
-    const int r = tap / 3, dx = tap % 3 - 1;
-    const int segs_x = (W + kSegPx - 1) / kSegPx;
-    const int64_t n_seg = (int64_t)B * H * segs_x;
+    const int tr = tap / 3, dx = tap % 3 - 1;
+    const int segs_x = (W + kSegPx - 1) / kSegPx, runs_y = (H + rows - 1) / rows;
+    const int64_t n_units = (int64_t)B * segs_x * runs_y;
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
     const bf16x8 zero = zero8();
-    // A segment's global loads (its dz1 chunk; lanes t < 198: the two input
-    // channels of pixel x0 - 1 + t % 66 in row y - 1 + t / 66), the next
-    // segment's issued before the current one's matrix products.
-    bf16x8 vd;
-    uint32_t vx = 0;                                 // bf16 pair (channel 0 low)
-    auto fetch = [&](int64_t sg) {
-        const int x0 = (int)(sg % segs_x) * kSegPx;
-        const int64_t row = sg / segs_x;
-        const int y = (int)(row % H);
-        const int xx = x0 + (t & 63);
-        vd = xx < W ? *reinterpret_cast<const bf16x8 *>(dz + (row * W + xx) * 32 + (t >> 6) * 8) : zero;
-        const int px = t % 66, rr = t / 66;
-        const int xi = x0 - 1 + px, iy = y + rr - 1;
-        const bool ok = t < 3 * 66 && xi >= 0 && xi < W && iy >= 0 && iy < H;
-        vx = ok ? *reinterpret_cast<const uint32_t *>(x + ((row - y + iy) * W + xi) * 2) : 0u;
+    // Row iy of x (lanes t < 66: both channels of pixel x0 - 1 + t, one bf16
+    // pair) and row y of dz1 (pixel x0 + (t & 63), channels 8 (t >> 6) .. +8).
+    struct Buf {
+        uint32_t vx;
+        bf16x8 vd;
+    } P, Q;
+    auto fetch_x = [&](Buf &bf, int64_t img, int x0, int iy) {
+        const int xi = x0 - 1 + t;
+        const bool ok = t < 66 && xi >= 0 && xi < W && iy >= 0 && iy < H;
+        bf.vx = ok ? *reinterpret_cast<const uint32_t *>(x + ((img + iy) * W + xi) * 2) : 0u;
     };
-    if ((int64_t)blockIdx.x < n_seg) fetch(blockIdx.x);
-    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
-        __syncthreads();
-        {
-            const int px = t & 63, cg = t >> 6;
+    auto store_x = [&](const Buf &bf, int slot) {
+        if (t < 66) {
+            xT[slot][0][t + 7] = __builtin_bit_cast(__bf16, (uint16_t)(bf.vx & 0xffffu));
+            xT[slot][1][t + 7] = __builtin_bit_cast(__bf16, (uint16_t)(bf.vx >> 16));
+        }
+    };
+    auto fetch_d = [&](Buf &bf, int64_t img, int x0, int y) {
+        const int xx = x0 + (t & 63);
+        bf.vd = xx < W ? *reinterpret_cast<const bf16x8 *>(dz + ((img + y) * W + xx) * 32 + (t >> 6) * 8) : zero;
+    };
+    auto store_d = [&](const Buf &bf) {
+        const int px = t & 63, cg = t >> 6;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = vd[i];
-        }
-        if (t < 3 * 66) {
-            const int px = t % 66, rr = t / 66;
-            xT[rr][0][px + 7] = __builtin_bit_cast(__bf16, (uint16_t)(vx & 0xffffu));
-            xT[rr][1][px + 7] = __builtin_bit_cast(__bf16, (uint16_t)(vx >> 16));
-        }
-        __syncthreads();
-        if (sg + gridDim.x < n_seg) fetch(sg + gridDim.x);
+        for (int i = 0; i < 8; ++i) dT[cg * 8 + i][px] = bf.vd[i];
+    };
+    auto products = [&](int y) {
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             const int pxb = kk * 32 + kb * 8;
@@ -571,7 +545,7 @@ __global__ __launch_bounds__(256) void dw1_kernel(const __bf16 *__restrict__ x, 
                 for (int e = 0; e < 8; ++e) sb += (float)A[e];
                 bacc += sb;
             }
-            const __bf16 *rp = &xT[r][ch][0];
+            const __bf16 *rp = &xT[ring_slot(y - 1 + tr)][ch][0];
             const u32x4w pv = *reinterpret_cast<const u32x4w *>(rp + pxb);
             const u32x4w c = *reinterpret_cast<const u32x4w *>(rp + pxb + 8);
             const u32x4w nx = *reinterpret_cast<const u32x4w *>(rp + pxb + 16);
@@ -583,6 +557,37 @@ __global__ __launch_bounds__(256) void dw1_kernel(const __bf16 *__restrict__ x, 
                 bv[k] = !col_ok ? 0u : (dx < 0 ? lft : (dx > 0 ? rgt : c[k]));
             }
             acc = mfma16(A, __builtin_bit_cast(bf16x8, bv), acc);
+        }
+    };
+    // Buffers by parity of the distance from the unit's first row, as in dw32_kernel.
+    auto step = [&](Buf &even, Buf &odd, int64_t img, int x0, int y, int y_end) {
+        __syncthreads();
+        store_x(odd, ring_slot(y + 1));
+        store_d(even);
+        __syncthreads();
+        if (y + 2 < y_end) {
+            fetch_x(odd, img, x0, y + 3);
+            fetch_d(even, img, x0, y + 2);
+        }
+        products(y);
+    };
+    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const int x0 = (int)(u % segs_x) * kSegPx;
+        const int64_t q = u / segs_x;
+        const int y_begin = (int)(q % runs_y) * rows, y_end = min(H, y_begin + rows);
+        const int64_t img = (q / runs_y) * H;
+        __syncthreads();
+        fetch_x(P, img, x0, y_begin - 1);
+        store_x(P, ring_slot(y_begin - 1));
+        fetch_x(P, img, x0, y_begin);
+        store_x(P, ring_slot(y_begin));
+        fetch_x(Q, img, x0, y_begin + 1);
+        fetch_x(P, img, x0, y_begin + 2);
+        fetch_d(P, img, x0, y_begin);
+        if (y_begin + 1 < y_end) fetch_d(Q, img, x0, y_begin + 1);
+        for (int y = y_begin; y < y_end; y += 2) {
+            step(P, Q, img, x0, y, y_end);
+            if (y + 1 < y_end) step(Q, P, img, x0, y + 1, y_end);
         }
     }
     float *pb = part + (int64_t)blockIdx.x * kW1Row;
@@ -596,74 +601,145 @@ __global__ __launch_bounds__(256) void dw1_kernel(const __bf16 *__restrict__ x, 
     }
 }
 
-// Output layer (32 -> 1) weight and bias gradients on the VALU:
-// dW4[tap][ci] = sum_px a3[px + tap][ci] dy[px], db4 = sum_px dy[px].  Staged
-// like dw32_kernel (a3 rows transposed in LDS, dy of the segment in LDS);
-// thread (ci, r, half) slides along its 32 pixels of row r and accumulates
-// the three taps of that row.  Partial rows part[2 block + half][289].
+// Output layer (32 -> 1) backward in one pass over a3 and dy:
+//   dW4[tap][ci] = sum_px a3[px + tap][ci] dy[px],  db4 = sum_px dy[px]   (VALU)
+//   dz3[q][c] = bf16((sum_tap dy[q - tap] w4[tap][c]) * (a3[q][c] > 0))
+// Work units are vertical runs of `rows` rows of one 64-pixel strip, walked
+// top to bottom like dw32_kernel: a three-slot ring holds rows y-1, y, y+1
+// of a3 (transposed, aT[slot][ci][px]) and of dy (pixels x0-1 .. x0+64), and
+// the next row of each is in flight while row y is worked.  For row y,
+// thread (ci, r, half) (t < 192) slides along its 32 pixels of row y-1+r and
+// accumulates the three taps of that row against dy of row y; thread 192
+// sums dy of row y for db4; and every lane (pixel t / 4, channel group t % 4)
+// forms its 8 channels of dz3 from the ring's dy and its own ReLU mask.  Each
+// work-group writes partial rows part[2 block + half][289] (dW4 in canonical
+// order, then db4 in row 2 block), summed later in a fixed order.
 constexpr int kOutRow = 289;
 
-__global__ __launch_bounds__(256) void dw_out_kernel(const __bf16 *__restrict__ a, const float *__restrict__ dy, int B,
-                                                     int H, int W, float *__restrict__ part) {
+__global__ __launch_bounds__(256) void out_grad_kernel(const __bf16 *__restrict__ a, const float *__restrict__ dy,
+                                                       const __bf16 *__restrict__ w4, int B, int H, int W, int rows,
+                                                       __bf16 *__restrict__ dz, float *__restrict__ part) {
     __shared__ __align__(16) __bf16 aT[3][32][kAStride];
-    __shared__ float dyS[kSegPx];
+    __shared__ __align__(16) float dyS[3][72];   // pixels x0-1 .. x0+64 at 3 .. 68 (x0 16-byte aligned)
     const int t = threadIdx.x;
-    const int ci = t & 31, q = t >> 5, r = q % 3, half = q / 3;   // q < 6 for t < 192
-    const int segs_x = (W + kSegPx - 1) / kSegPx;
-    const int64_t n_seg = (int64_t)B * H * segs_x;
+    const int ci = t & 31, q6 = t >> 5, r = q6 % 3, half = q6 / 3;   // q6 < 6 for t < 192
+    const int pl = t >> 2, cg = t & 3;                                 // dz3 lane: pixel, channel group
+    const int segs_x = (W + kSegPx - 1) / kSegPx, runs_y = (H + rows - 1) / rows;
+    const int64_t n_units = (int64_t)B * segs_x * runs_y;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, bacc = 0.f;
     const bf16x8 zero = zero8();
-    // A segment's global loads (dy of its 64 pixels, the a3 items of
-    // dw32_kernel), the next segment's issued before the current one's sums.
-    constexpr int kAItems = 3 * 4 * 66;
-    float vdy = 0.f;
-    bf16x8 va[4];
-    auto fetch = [&](int64_t sg) {
-        const int x0 = (int)(sg % segs_x) * kSegPx;
-        const int64_t row = sg / segs_x;
-        const int y = (int)(row % H);
-        vdy = t < kSegPx && x0 + t < W ? dy[row * W + x0 + t] : 0.f;
+    bf16x8 wv[9];                                 // w4[tap][8 cg .. +8]
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+    for (int k = 0; k < 9; ++k) wv[k] = *reinterpret_cast<const bf16x8 *>(w4 + k * 32 + cg * 8);
+    // Register buffers by parity of the distance from the unit's first row
+    // (as in dw32_kernel): two rows of a3 and dy in flight while a row is worked.
+    struct Buf {
+        bf16x8 va[2];
+        float vdy;
+    } P, Q;
+    auto fetch = [&](Buf &bf, int64_t img, int x0, int iy) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
             const int item = t + 256 * i;
-            const int px = item % 66, qq = item / 66, cg = qq & 3, rr = qq >> 2;
-            const int x = x0 - 1 + px, iy = y + rr - 1;
-            const bool ok = item < kAItems && x >= 0 && x < W && iy >= 0 && iy < H;
-            va[i] = ok ? *reinterpret_cast<const bf16x8 *>(a + ((row - y + iy) * W + x) * 32 + cg * 8) : zero;
+            const int px = item % 66, g = item / 66;
+            const int xa = x0 - 1 + px;
+            const bool ok = item < kARowItems && xa >= 0 && xa < W && iy >= 0 && iy < H;
+            bf.va[i] = ok ? *reinterpret_cast<const bf16x8 *>(a + ((img + iy) * W + xa) * 32 + g * 8) : zero;
         }
+        const int xd = x0 - 1 + t;
+        bf.vdy = t < 66 && xd >= 0 && xd < W && iy >= 0 && iy < H ? dy[(img + iy) * W + xd] : 0.f;
     };
-    if ((int64_t)blockIdx.x < n_seg) fetch(blockIdx.x);
-    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
-        __syncthreads();
-        if (t < kSegPx) dyS[t] = vdy;
+    auto store = [&](const Buf &bf, int slot) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 2; ++i) {
             const int item = t + 256 * i;
-            if (item < kAItems) {
-                const int px = item % 66, qq = item / 66, cg = qq & 3, rr = qq >> 2;
+            if (item < kARowItems) {
+                const int px = item % 66, g = item / 66;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) aT[rr][cg * 8 + e][px + 7] = va[i][e];
+                for (int e = 0; e < 8; ++e) aT[slot][g * 8 + e][px + 7] = bf.va[i][e];
             }
         }
-        __syncthreads();
-        if (sg + gridDim.x < n_seg) fetch(sg + gridDim.x);
+        if (t < 66) dyS[slot][t + 3] = bf.vdy;
+    };
+    auto work = [&](int64_t img, int x0, int y) {
+        const int x = x0 + pl;
+        const int64_t o = ((img + y) * W + x) * 32 + cg * 8;
+        const bf16x8 mask = x < W ? *reinterpret_cast<const bf16x8 *>(a + o) : zero;
+        const float *dyc = dyS[ring_slot(y)];
         if (t < 192) {
-            const __bf16 *rp = &aT[r][ci][0];
+            // Pixels p0-1 .. p0+32 of row y-1+r (aT columns p0+7 .. p0+40)
+            // and dy of pixels p0 .. p0+31, read in 16-byte pieces.
+            const __bf16 *rp = &aT[ring_slot(y - 1 + r)][ci][0];
             const int p0 = half * 32;
-            float vm = (float)rp[p0 + 7], v0 = (float)rp[p0 + 8];
-#pragma unroll 8
-            for (int px = p0; px < p0 + 32; ++px) {
-                const float vp = (float)rp[px + 9], g = dyS[px];
-                acc0 = fmaf(vm, g, acc0);
-                acc1 = fmaf(v0, g, acc1);
-                acc2 = fmaf(vp, g, acc2);
-                vm = v0;
-                v0 = vp;
+            float av[34], gv[32];
+            {
+                const bf16x8 c0 = *reinterpret_cast<const bf16x8 *>(rp + p0);
+                av[0] = (float)c0[7];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const bf16x8 ck = *reinterpret_cast<const bf16x8 *>(rp + p0 + 8 + 8 * k);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) av[1 + 8 * k + e] = (float)ck[e];
+                }
+                const bf16x8 c5 = *reinterpret_cast<const bf16x8 *>(rp + p0 + 40);
+                av[33] = (float)c5[0];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const f32x4 gk = *reinterpret_cast<const f32x4 *>(dyc + 4 + p0 + 4 * k);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) gv[4 * k + e] = gk[e];
+                }
+            }
+#pragma unroll
+            for (int px = 0; px < 32; ++px) {
+                acc0 = fmaf(av[px], gv[px], acc0);
+                acc1 = fmaf(av[px + 1], gv[px], acc1);
+                acc2 = fmaf(av[px + 2], gv[px], acc2);
             }
         } else if (t == 192) {
             float sb = 0.f;
-            for (int px = 0; px < kSegPx; ++px) sb += dyS[px];
+            for (int px = 0; px < kSegPx; ++px) sb += dyc[px + 4];
             bacc += sb;
+        }
+        // dz3 of (y, x): tap (dy_t, dx_t) takes dy at (y - dy_t, x - dx_t).
+        float dacc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) dacc[c] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const float g = dyS[ring_slot(y - tap_dy(k))][pl + 4 - tap_dx(k)];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) dacc[c] = fmaf(g, (float)wv[k][c], dacc[c]);
+        }
+        if (x < W) {
+            bf16x8 ov;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) ov[c] = (__bf16)((float)mask[c] > 0.f ? dacc[c] : 0.f);
+            *reinterpret_cast<bf16x8 *>(dz + o) = ov;
+        }
+    };
+    auto step = [&](Buf &even, Buf &odd, int64_t img, int x0, int y, int y_end) {
+        __syncthreads();                            // readers of row y-2's slot are done
+        store(odd, ring_slot(y + 1));
+        __syncthreads();
+        if (y + 2 < y_end) fetch(odd, img, x0, y + 3);
+        work(img, x0, y);
+    };
+    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const int x0 = (int)(u % segs_x) * kSegPx;
+        const int64_t q = u / segs_x;
+        const int y_begin = (int)(q % runs_y) * rows, y_end = min(H, y_begin + rows);
+        const int64_t img = (q / runs_y) * H;
+        __syncthreads();                            // the previous unit's readers are done
+        fetch(P, img, x0, y_begin - 1);
+        store(P, ring_slot(y_begin - 1));
+        fetch(P, img, x0, y_begin);
+        store(P, ring_slot(y_begin));
+        fetch(Q, img, x0, y_begin + 1);
+        fetch(P, img, x0, y_begin + 2);
+        for (int y = y_begin; y < y_end; y += 2) {
+            step(P, Q, img, x0, y, y_end);
+            if (y + 1 < y_end) step(Q, P, img, x0, y + 1, y_end);
         }
     }
     if (t < 192) {
@@ -850,17 +926,19 @@ struct qld_denoiser {
 namespace qld {
 namespace {
 
-constexpr int kGradBlocks = 512;     // work-groups of the MFMA weight-gradient reductions (dw1)
-constexpr int kW32Blocks = 1024;     // work-groups of dw32_kernel
+constexpr int kW32Blocks = 1024;     // work-groups of dw32_kernel (four resident per CU)
+constexpr int kW1Blocks = 2048;      // work-groups of dw1_kernel (eight resident per CU)
 
 // Rows per work unit of dw32_kernel: enough units for every work-group, at
 // least 4 rows (each unit loads two halo rows of `a` beyond its own).
-int dw32_rows(int B, int H, int W) {
+int dw32_rows(int B, int H, int W, int blocks = kW32Blocks) {
     const int64_t strips = (int64_t)B * ceil_div(W, kSegPx);
-    const int64_t want = ceil_div(strips * H, kW32Blocks);
+    const int64_t want = ceil_div(strips * H, blocks);
     return (int)std::min<int64_t>(H, std::max<int64_t>(4, want));
 }
-constexpr int kSmallBlocks = 1024;   // work-groups of the output-layer gradient
+
+// out_grad_kernel: two work-groups per CU are resident (189 VGPRs), one unit each.
+int out_grad_blocks() { return std::max(8, 2 * device_cu_count() / 8 * 8); }
 constexpr int kLossBlocks = 256;
 
 template <typename T>
@@ -922,17 +1000,18 @@ qld_status dw32(qld_denoiser *d, const __bf16 *a, const __bf16 *dz, int B, int64
 
 // Weights and bias of the input layer.
 qld_status dw1(qld_denoiser *d, int B, hipStream_t s) {
-    hipLaunchKernelGGL(dw1_kernel, dim3(kGradBlocks), dim3(256), 0, s, d->x0, d->dzC, B, d->H, d->W, d->part);
+    hipLaunchKernelGGL(dw1_kernel, dim3(kW1Blocks), dim3(256), 0, s, d->x0, d->dzC, B, d->H, d->W,
+                       dw32_rows(B, d->H, d->W, kW1Blocks), d->part);
     QLD_TRY(check_hip(hipGetLastError(), "dw1 launch"));
-    return reduce_rows(d, d->part, kGradBlocks, kW1Row, d->grads + OFF_W1, s);
+    return reduce_rows(d, d->part, kW1Blocks, kW1Row, d->grads + OFF_W1, s);
 }
 
-// Weights and bias of the output layer.
-qld_status dw_out(qld_denoiser *d, int B, hipStream_t s) {
-    const int64_t n_seg = (int64_t)B * d->H * ceil_div(d->W, kSegPx);
-    const int blocks = (int)std::min<int64_t>(kSmallBlocks, n_seg);
-    hipLaunchKernelGGL(dw_out_kernel, dim3(blocks), dim3(256), 0, s, d->a3, d->dy, B, d->H, d->W, d->part);
-    QLD_TRY(check_hip(hipGetLastError(), "dw_out launch"));
+// Output layer backward: dW4, db4 and dz3 (into dzA) in one pass.
+qld_status out_grad(qld_denoiser *d, int B, hipStream_t s) {
+    const int blocks = out_grad_blocks();
+    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks), dim3(256), 0, s, d->a3, d->dy, d->w4, B, d->H, d->W,
+                       dw32_rows(B, d->H, d->W, blocks), d->dzA, d->part);
+    QLD_TRY(check_hip(hipGetLastError(), "out_grad launch"));
     return reduce_rows(d, d->part, 2 * blocks, kOutRow, d->grads + OFF_W4, s);
 }
 
@@ -1129,9 +1208,7 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, s, d->y, t, d->dy, npx, d->lpart);
     hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, d->lpart, kLossBlocks, npx, d->loss);
     // Output layer: dW4, db4, and dz3 = bf16(d a3 * (a3 > 0)).
-    QLD_TRY(dw_out(d, B, s));
-    hipLaunchKernelGGL(out_back_kernel, dim3((unsigned)ceil_div(4 * npx, 256)), dim3(256), 0, s, d->dy, d->w4,
-                       d->a3, d->dzA, B, H, W);
+    QLD_TRY(out_grad(d, B, s));
     const int g = conv_grid(B, H, W), gp = conv_persistent_grid(g);
     // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
     QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));   // and b3
