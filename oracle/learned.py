@@ -9,7 +9,8 @@ window (M_S cycles) to the lock-in amplitude of a long window (M_L cycles)
 of the same scene, with plain QLD as its fallback and judge.
 
 Network (NHWC, 3x3 kernels, zero "same" padding, correlation):
-    x  = (I_S, Q_S) / (sigma * sqrt(M_S)),  sigma^2 = 2 * mean sample level of the short window
+    x  = (I_S, Q_S) / sqrt(P_S / 2) per pixel, P_S = the pixel's sample sum over the short window
+    s  = sigma / sqrt(M_S),  sigma^2 = 2 * mean sample level of the tile's short window
     a1 = relu(conv(x,  W1) + b1)        2 -> 32
     a2 = relu(conv(a1, W2) + b2)       32 -> 32
     a3 = relu(conv(a2, W3) + b3)       32 -> 32
@@ -92,7 +93,7 @@ def gen_pairs(mask, rates, M_S, M_L, tile0, seed, bits=12):
     sample sums of both windows.  Returns dict of int64 arrays [n][H][W] / [n]."""
     fr = gen_frames(mask, rates, M_L, tile0, seed, bits)
     n = fr.shape[0]
-    out = {k: [] for k in ("I_S", "Q_S", "I_L", "Q_L", "sum_S", "sum_L")}
+    out = {k: [] for k in ("I_S", "Q_S", "I_L", "Q_L", "sum_S", "sum_L", "psum_S", "psum_L")}
     for i in range(n):
         I, Q = _o.qld(fr[i, :4 * M_S])
         out["I_S"].append(I)
@@ -100,8 +101,10 @@ def gen_pairs(mask, rates, M_S, M_L, tile0, seed, bits=12):
         I, Q = _o.qld(fr[i])
         out["I_L"].append(I)
         out["Q_L"].append(Q)
-        out["sum_S"].append(int(fr[i, :4 * M_S].astype(np.int64).sum()))
-        out["sum_L"].append(int(fr[i].astype(np.int64).sum()))
+        out["psum_S"].append(fr[i, :4 * M_S].astype(np.int64).sum(axis=0))
+        out["psum_L"].append(fr[i].astype(np.int64).sum(axis=0))
+        out["sum_S"].append(int(out["psum_S"][-1].sum()))
+        out["sum_L"].append(int(out["psum_L"][-1].sum()))
     return {k: np.array(v) for k, v in out.items()}
 
 
@@ -116,22 +119,34 @@ def a_star(mask, rates):
     return np.sqrt(I * I + Q * Q)
 
 
-def normalise(I_S, Q_S, sum_S, M_S, H, W):
-    """Network input [n][H][W][2] and output scale s (per tile) from the short window."""
-    b = np.asarray(sum_S, dtype=np.float64) / (H * W * 4 * M_S)       # mean sample level
+def normalise(I_S, Q_S, psum_S, sum_S, M_S, H, W):
+    """Network input [n][H][W][2] and output scale s (per tile) from the short window.
+
+    Input: each pixel's (I, Q) over the noise standard deviation of its own
+    quadrature sums.  For Poisson light of rate lam at a pixel, every cycle
+    adds S0 - S2 of variance 2 lam to I (and S1 - S3 to Q): Var(I) = Var(Q) =
+    2 M_S lam; the pixel's sample sum P over the window's 4 M_S frames
+    estimates 4 M_S lam, so the divisor is sqrt(P / 2) (x = 0 where P = 0).
+    Output scale: sigma / sqrt(M_S), sigma^2 = 2 b, b = the tile's mean sample
+    level (its sample sum over H * W * 4 * M_S samples)."""
+    ps = np.asarray(psum_S, dtype=np.float64)
+    den = np.sqrt(ps / 2.0)
+    ok = den > 0
+    safe = np.where(ok, den, 1.0)
+    x = np.stack([np.where(ok, np.asarray(I_S, dtype=np.float64) / safe, 0.0),
+                  np.where(ok, np.asarray(Q_S, dtype=np.float64) / safe, 0.0)], axis=-1)
+    b = np.asarray(sum_S, dtype=np.float64) / (H * W * 4 * M_S)       # mean sample level of the tile
     sigma = np.sqrt(2.0 * b)
-    den = sigma * math.sqrt(M_S)
-    x = np.stack([np.asarray(I_S) / den[:, None, None], np.asarray(Q_S) / den[:, None, None]], axis=-1)
     return x, sigma / math.sqrt(M_S)
 
 
-def target(I_L, Q_L, sum_L, M_L, H, W, scale):
+def target(I_L, Q_L, psum_L, M_L, scale):
     """Bias-reduced long-window amplitude per cycle, in units of ``scale``:
-    sqrt(max(I^2 + Q^2 - 4 M_L b, 0)) / M_L, b = mean sample level (the noise
-    power of I^2 + Q^2 for Poisson light is 4 M_L b)."""
-    b = np.asarray(sum_L, dtype=np.float64) / (H * W * 4 * M_L)
+    sqrt(max(I^2 + Q^2 - P_L, 0)) / M_L per pixel, P_L = the pixel's sample sum
+    over the long window (for Poisson light of rate lam, E[I^2 + Q^2] without
+    signal is 4 M_L lam, which P_L estimates)."""
     r2 = np.asarray(I_L, dtype=np.float64) ** 2 + np.asarray(Q_L, dtype=np.float64) ** 2
-    t = np.sqrt(np.maximum(r2 - 4.0 * M_L * b[:, None, None], 0.0)) / M_L
+    t = np.sqrt(np.maximum(r2 - np.asarray(psum_L, dtype=np.float64), 0.0)) / M_L
     return t / np.asarray(scale)[:, None, None]
 
 

@@ -96,70 +96,97 @@ def test_pairs_short_window_is_prefix_and_mean_matches():
     assert np.allclose(a[mask > 0], 2 * A, rtol=1e-12) and np.allclose(a[mask == 0], 0.0, atol=1e-9)
 
 
+def test_pairs_pixel_sums():
+    mask, rates, p = small_tiles(n=2)
+    d = L.gen_pairs(mask, rates, M_S=2, M_L=8, tile0=0, seed=5)
+    fr = L.gen_frames(mask, rates, 8, tile0=0, seed=5)
+    for i in range(2):
+        assert np.array_equal(d["psum_S"][i], fr[i, :8].astype(np.int64).sum(axis=0))
+        assert np.array_equal(d["psum_L"][i], fr[i].astype(np.int64).sum(axis=0))
+        assert d["sum_S"][i] == d["psum_S"][i].sum() and d["sum_L"][i] == d["psum_L"][i].sum()
+
+
 def test_target_bias_reduction_closed_form():
-    # Without signal, E[I^2 + Q^2] = 4 M b: the bias-reduced target is ~0 on average.
-    M, b, H, W = 64, 2000.0, 64, 64
+    # Without signal, E[I^2 + Q^2] = 4 M lam = the pixel's expected sample sum:
+    # the bias-reduced target is ~0 on average.
+    M, lam, H, W = 64, 2000.0, 64, 64
     rng = np.random.default_rng(3)
-    I = rng.normal(0, math.sqrt(2 * M * b), (1, H, W))
-    Q = rng.normal(0, math.sqrt(2 * M * b), (1, H, W))
-    t = L.target(I, Q, np.array([b * H * W * 4 * M]), M, H, W, np.array([1.0]))
+    I = rng.normal(0, math.sqrt(2 * M * lam), (1, H, W))
+    Q = rng.normal(0, math.sqrt(2 * M * lam), (1, H, W))
+    t = L.target(I, Q, np.full((1, H, W), 4 * M * lam), M, np.array([1.0]))
     plain = np.sqrt(I ** 2 + Q ** 2) / M
     assert t.mean() < 0.45 * plain.mean()
 
 
 def test_normalise_hand_built():
-    # Reading L17: x = (I, Q) / (sigma sqrt(M_S)), sigma^2 = 2 b, b = the mean
-    # sample level over the window's H * W * 4 * M_S samples; scale = sigma / sqrt(M_S).
-    # H = W = 2, M_S = 4: 64 samples summing to 512 give b = 8, sigma = 4, so the
-    # divisor is 4 * 2 = 8 and the scale 4 / 2 = 2.
+    # Reading L17: x = (I, Q) / sqrt(P / 2) with P the pixel's sample sum;
+    # scale = sigma / sqrt(M_S), sigma^2 = 2 b, b the tile's mean sample level.
+    # P = 128, 32, 72, 280 give divisors 8, 4, 6, sqrt(140); H = W = 2, M_S = 4:
+    # the tile's 64 samples summing to 512 give b = 8, sigma = 4, scale 4 / 2 = 2.
     I = np.array([[[8, -16], [24, 0]]])
-    Q = np.array([[[0, 4], [-8, 40]]])
-    x, scale = L.normalise(I, Q, np.array([512]), 4, 2, 2)
+    Q = np.array([[[0, 4], [-12, 0]]])
+    P = np.array([[[128, 32], [72, 280]]])
+    x, scale = L.normalise(I, Q, P, np.array([512]), 4, 2, 2)
     assert x.shape == (1, 2, 2, 2)
-    assert np.array_equal(x[0, :, :, 0], [[1.0, -2.0], [3.0, 0.0]])
-    assert np.array_equal(x[0, :, :, 1], [[0.0, 0.5], [-1.0, 5.0]])
+    assert np.array_equal(x[0, :, :, 0], [[1.0, -4.0], [4.0, 0.0]])
+    assert np.array_equal(x[0, :, :, 1], [[0.0, 1.0], [-2.0, 0.0]])
     assert np.array_equal(scale, [2.0])
+    # A pixel with no light (P = 0) gives x = 0.
+    x0, _ = L.normalise(np.zeros((1, 1, 1)), np.zeros((1, 1, 1)), np.zeros((1, 1, 1)), np.array([8]), 1, 1, 1)
+    assert np.array_equal(x0, np.zeros((1, 1, 1, 2)))
 
 
 def test_normalise_unit_variance_on_signal_free_poisson():
     # Unmodulated Poisson light of rate lam: each cycle adds S0 - S2 of variance
-    # 2 lam to I (and S1 - S3 to Q), so Var(I) = 2 M lam while the window's mean
-    # level estimates lam: x has unit variance per channel, zero mean, and the
-    # scale equals the standard deviation of I / M.
+    # 2 lam to I (and S1 - S3 to Q), so Var(I) = 2 M lam while the pixel's
+    # sample sum estimates 4 M lam: x has unit variance per channel and zero
+    # mean, in each half of a tile whose halves differ tenfold in rate (a
+    # tile-wide level would give variances 2 lam_half / (lam_1 + lam_2)).
     rng = np.random.default_rng(11)
-    lam, M, H, W = 300.0, 16, 128, 128
+    M, H, W = 16, 128, 128
+    lam = np.where(np.arange(W)[None, :] < W // 2, 300.0, 3000.0) * np.ones((H, 1))
     fr = rng.poisson(lam, size=(4 * M, H, W)).astype(np.uint16)
     I, Q = oracle.qld(fr)
-    x, scale = L.normalise(I[None], Q[None], np.array([int(fr.astype(np.int64).sum())]), M, H, W)
-    for ch in range(2):
-        assert abs(x[0, :, :, ch].var() - 1.0) < 0.03, ch
-        assert abs(x[0, :, :, ch].mean()) < 0.02, ch
-    assert abs((I / M).std() / scale[0] - 1.0) < 0.03
+    P = fr.astype(np.int64).sum(axis=0)
+    x, scale = L.normalise(I[None], Q[None], P[None], np.array([int(P.sum())]), M, H, W)
+    for half in (slice(0, W // 2), slice(W // 2, W)):
+        for ch in range(2):
+            v = x[0, :, half, ch]
+            assert abs(v.var() - 1.0) < 0.04, (half, ch, v.var())
+            assert abs(v.mean()) < 0.03, (half, ch)
+    # The scale is the tile's: the standard deviation of I / M at the mean rate.
+    assert abs(scale[0] - math.sqrt(2 * 1650.0 / M)) / scale[0] < 0.01
 
 
 def test_target_hand_built():
-    # t = sqrt(max(I^2 + Q^2 - 4 M_L b, 0)) / M_L / scale, b the mean level.
-    # H = 1, W = 2, M_L = 5: 40 samples summing to 4000 give b = 100, so the
-    # noise power is 4 * 5 * 100 = 2000.  (30, 40): sqrt(2500 - 2000) / 5 / 0.5
-    # = sqrt(80); (10, 0): 100 < 2000, clipped to 0.
-    t = L.target(np.array([[[30, 10]]]), np.array([[[40, 0]]]), np.array([4000]), 5, 1, 2, np.array([0.5]))
-    assert t.shape == (1, 1, 2)
+    # t = sqrt(max(I^2 + Q^2 - P, 0)) / M_L / scale, P the pixel's sample sum.
+    # M_L = 5, scale 0.5: (30, 40) with P = 2000: sqrt(500) / 5 / 0.5 = sqrt(80);
+    # (10, 0) with P = 2000: 100 < 2000, clipped to 0; (30, 40) with P = 100:
+    # sqrt(2400) / 2.5.
+    t = L.target(np.array([[[30, 10, 30]]]), np.array([[[40, 0, 40]]]), np.array([[[2000, 2000, 100]]]), 5,
+                 np.array([0.5]))
+    assert t.shape == (1, 1, 3)
     assert abs(t[0, 0, 0] - math.sqrt(80.0)) < 1e-12 and t[0, 0, 1] == 0.0
+    assert abs(t[0, 0, 2] - math.sqrt(2400.0) / 2.5) < 1e-12
 
 
 def test_target_signal_free_closed_form():
     # Without signal, I and Q are (to a very good approximation) independent
     # Gaussians of variance 2 M lam, so r^2 = I^2 + Q^2 is 4 M lam times a unit
     # exponential E, and M^2 t^2 = 4 M lam max(E - 1, 0) with E[max(E - 1, 0)]
-    # = 1/e: mean(t^2) = (4 lam / M) / e.  (Removing 2 M b instead would give
-    # e^-1/2, i.e. 65% more; 8 M b, e^-2.)
+    # = 1/e: mean(t^2) = (4 lam / M) / e in each half of a tile whose halves
+    # differ tenfold in rate.  (Removing 2 M lam instead would give e^-1/2,
+    # i.e. 65% more; 8 M lam, e^-2; the tile's mean level, 1.6x or 0.2x.)
     rng = np.random.default_rng(12)
-    lam, M, H, W = 300.0, 32, 256, 256
+    M, H, W = 32, 256, 256
+    lam = np.where(np.arange(W)[None, :] < W // 2, 300.0, 3000.0) * np.ones((H, 1))
     fr = rng.poisson(lam, size=(4 * M, H, W)).astype(np.uint16)
     I, Q = oracle.qld(fr)
-    t = L.target(I[None], Q[None], np.array([int(fr.astype(np.int64).sum())]), M, H, W, np.array([1.0]))
-    ratio = float((t ** 2).mean()) / (4 * lam / M / math.e)
-    assert abs(ratio - 1.0) < 0.03, ratio
+    P = fr.astype(np.int64).sum(axis=0)
+    t = L.target(I[None], Q[None], P[None], M, np.array([1.0]))
+    for half, lh in ((slice(0, W // 2), 300.0), (slice(W // 2, W), 3000.0)):
+        ratio = float((t[0, :, half] ** 2).mean()) / (4 * lh / M / math.e)
+        assert abs(ratio - 1.0) < 0.04, (lh, ratio)
 
 
 def test_bf16_rounding():
