@@ -416,9 +416,9 @@ typedef struct qld_denoiser qld_denoiser;
  * qld_server_drain, and the caller must not use it while the server may).
  * For each cycle c of the window (c = 0 after a reset) the server, on its
  * compute stream after the window update:
- *   - if c + 1 >= M_short: x = qld_denoise_prepare(short-window I/Q, the
- *     short window's sample sum), runs the forward (batch 1) and serves
- *     y * scale when gate <= gate_threshold;
+ *   - if c + 1 >= M_short: x = qld_denoise_prepare(short-window I/Q, each
+ *     pixel's and the frame's sample sums over the short window), runs the
+ *     forward (batch 1) and serves y * scale when gate <= gate_threshold;
  *   - otherwise, or when the gate is above the threshold, serves the plain
  *     long-window amplitude per cycle, R / min(c + 1, M_cycles).
  * Submissions to a LEARNED stream without a denoiser fail with QLD_E_STATE.
@@ -525,33 +525,41 @@ qld_status qld_server_stats(const qld_server *s, int64_t *batches, int64_t *cycl
  * Poisson inversion defined in the library source.  The lock-in sums of its
  * first M_short cycles go to I_S, Q_S and of its first M_long cycles to
  * I_L, Q_L (Methods, R(j,k)); sum_S / sum_L receive the tile's sample sums
- * over the same windows.
+ * over the same windows, and psum_S / psum_L (each may be NULL) each pixel's.
  *   mask       device uint8 [n_tiles][H][W] (0 or 1)
  *   rates_host HOST double [n_tiles][2][4], each in (0, 6000]
- *   outputs    device int32 [n_tiles][H][W]; uint64 [n_tiles] (overwritten)
+ *   outputs    device int32 [n_tiles][H][W]; uint64 [n_tiles]; uint32
+ *              [n_tiles][H][W] (overwritten)
  * QLD_E_OVERFLOW if M_long * 4 * (2^bits - 1) >= 2^32.
  */
 qld_status qld_gen_pairs(const uint8_t *mask, const double *rates_host, int32_t n_tiles, int32_t H,
                          int32_t W, int32_t M_short, int32_t M_long, uint32_t tile0, uint64_t seed,
                          int32_t bits, int32_t *I_S, int32_t *Q_S, int32_t *I_L, int32_t *Q_L,
-                         uint64_t *sum_S, uint64_t *sum_L, qld_hip_stream stream);
+                         uint64_t *sum_S, uint64_t *sum_L, uint32_t *psum_S, uint32_t *psum_L,
+                         qld_hip_stream stream);
 
 /*
- * Network input of the denoiser from a short window: x = (I, Q) / (sigma sqrt(M)),
- * sigma^2 = 2 b, b = sum / (H W 4 M) the mean sample level (the Poisson noise
- * of one quadrature per cycle has variance 2 b); scale[i] = sigma / sqrt(M)
- * converts the network output to counts per cycle.
- *   I_S, Q_S device int32 [B][H][W]; sum_S device uint64 [B];
- *   x device float [B][H][W][2]; scale device float [B]  (overwritten)
+ * Network input of the denoiser from a short window of M cycles: each
+ * pixel's (I, Q) over the noise standard deviation of its own quadrature
+ * sums, x = (I, Q) / sqrt(P / 2), P = psum_S the pixel's sample sum over the
+ * window (for Poisson light of rate lam, Var(I) = Var(Q) = 2 M lam and P
+ * estimates 4 M lam); x = 0 where P = 0.  scale[i] = sigma / sqrt(M), sigma^2 =
+ * 2 b, b = sum_S / (H W 4 M) the tile's mean sample level, converts the
+ * network output to counts per cycle.
+ *   I_S, Q_S device int32 [B][H][W]; psum_S device uint32 [B][H][W];
+ *   sum_S device uint64 [B]; x device float [B][H][W][2]; scale device float [B]
+ *   (overwritten)
  */
-qld_status qld_denoise_prepare(const int32_t *I_S, const int32_t *Q_S, const uint64_t *sum_S,
-                               int32_t M_S, int32_t B, int32_t H, int32_t W, float *x, float *scale,
-                               qld_hip_stream stream);
+qld_status qld_denoise_prepare(const int32_t *I_S, const int32_t *Q_S, const uint32_t *psum_S,
+                               const uint64_t *sum_S, int32_t M_S, int32_t B, int32_t H, int32_t W, float *x,
+                               float *scale, qld_hip_stream stream);
 
-/* Training target: long-window amplitude per cycle with its noise power
- * removed, in network units: t = sqrt(max(I^2 + Q^2 - 4 M b, 0)) / M / scale.
- *   t device float [B][H][W] (overwritten) */
-qld_status qld_denoise_target(const int32_t *I_L, const int32_t *Q_L, const uint64_t *sum_L,
+/* Training target: long-window amplitude per cycle with each pixel's noise
+ * power removed, in network units: t = sqrt(max(I^2 + Q^2 - P, 0)) / M / scale,
+ * P = psum_L the pixel's sample sum over the long window (E[I^2 + Q^2] is
+ * 4 M lam without signal).
+ *   psum_L device uint32 [B][H][W]; t device float [B][H][W] (overwritten) */
+qld_status qld_denoise_target(const int32_t *I_L, const int32_t *Q_L, const uint32_t *psum_L,
                               int32_t M_L, const float *scale, int32_t B, int32_t H, int32_t W,
                               float *t, qld_hip_stream stream);
 

@@ -130,8 +130,8 @@ _sig("qld_frame_stride_hint", _i64, _i32, _i32, _i64, ctypes.c_int)
 _sig("qld_read_probe", ctypes.c_int, _vp, _i64, _vp, _vp)
 _fp = ctypes.POINTER(ctypes.c_float)
 _sig("qld_gen_pairs", ctypes.c_int, _vp, _vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_uint32, ctypes.c_uint64, _i32,
-     _vp, _vp, _vp, _vp, _vp, _vp, _vp)
-_sig("qld_denoise_prepare", ctypes.c_int, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp)
+     _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("qld_denoise_prepare", ctypes.c_int, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp)
 _sig("qld_denoise_target", ctypes.c_int, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, _vp, _vp)
 _sig("qld_clean_amplitude", ctypes.c_int, _vp, _vp, _i32, _i32, _i32, _vp, _vp)
 _sig("qld_judge_nrmse", ctypes.c_int, _vp, _vp, _vp, _i32, _i64, _vp, _vp)
@@ -550,31 +550,33 @@ def _host_f64(a):
 
 def gen_pairs(mask, rates, M_short, M_long, tile0, seed, bits=12, stream=None):
     """Training pairs of n tiles: mask device uint8 [n][H][W], rates host [n][2][4].
-    Returns device tensors (I_S, Q_S, I_L, Q_L, sum_S, sum_L)."""
+    Returns device tensors (I_S, Q_S, I_L, Q_L, sum_S, sum_L, psum_S, psum_L):
+    the per-pixel sample sums psum_* hold uint32 values in int32 tensors."""
     n, H, W = mask.shape
     dev = mask.device
     outs = [torch.empty((n, H, W), dtype=torch.int32, device=dev) for _ in range(4)]
     sums = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(2)]
+    psums = [torch.empty((n, H, W), dtype=torch.int32, device=dev) for _ in range(2)]
     keep, rp = _host_f64(rates)
     _check(_lib.qld_gen_pairs(_ptr(mask), rp, int(n), int(H), int(W), int(M_short), int(M_long), int(tile0),
                               int(seed), int(bits), *[_ptr(o) for o in outs], _ptr(sums[0]), _ptr(sums[1]),
-                              _stream(stream)), "qld_gen_pairs")
-    return (*outs, *sums)
+                              _ptr(psums[0]), _ptr(psums[1]), _stream(stream)), "qld_gen_pairs")
+    return (*outs, *sums, *psums)
 
 
-def denoise_prepare(I_S, Q_S, sum_S, M_S, stream=None):
+def denoise_prepare(I_S, Q_S, psum_S, sum_S, M_S, stream=None):
     B, H, W = I_S.shape
     x = torch.empty((B, H, W, 2), dtype=torch.float32, device=I_S.device)
     scale = torch.empty(B, dtype=torch.float32, device=I_S.device)
-    _check(_lib.qld_denoise_prepare(_ptr(I_S), _ptr(Q_S), _ptr(sum_S), int(M_S), int(B), int(H), int(W), _ptr(x),
-                                    _ptr(scale), _stream(stream)), "qld_denoise_prepare")
+    _check(_lib.qld_denoise_prepare(_ptr(I_S), _ptr(Q_S), _ptr(psum_S), _ptr(sum_S), int(M_S), int(B), int(H), int(W),
+                                    _ptr(x), _ptr(scale), _stream(stream)), "qld_denoise_prepare")
     return x, scale
 
 
-def denoise_target(I_L, Q_L, sum_L, M_L, scale, stream=None):
+def denoise_target(I_L, Q_L, psum_L, M_L, scale, stream=None):
     B, H, W = I_L.shape
     t = torch.empty((B, H, W), dtype=torch.float32, device=I_L.device)
-    _check(_lib.qld_denoise_target(_ptr(I_L), _ptr(Q_L), _ptr(sum_L), int(M_L), _ptr(scale), int(B), int(H), int(W),
+    _check(_lib.qld_denoise_target(_ptr(I_L), _ptr(Q_L), _ptr(psum_L), int(M_L), _ptr(scale), int(B), int(H), int(W),
                                    _ptr(t), _stream(stream)), "qld_denoise_target")
     return t
 

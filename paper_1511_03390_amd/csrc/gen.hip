@@ -148,6 +148,7 @@ struct GenArgs {
     uint32_t top;
     int32_t *I_S, *Q_S, *I_L, *Q_L;
     unsigned long long *sum_S, *sum_L;
+    uint32_t *psum_S, *psum_L;        // per-pixel sample sums (may be NULL)
 };
 
 // X(u) = lo + #{k : thr[k] <= u}.  The count lies between the guide entries of
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void gen_pairs_kernel(GenArgs a) {
         const int mk = valid ? (a.mask[(int64_t)tile * npx + p] ? 1 : 0) : 0;
         const int j0 = mk * 4;
         int32_t I = 0, Q = 0, Is = 0, Qs = 0;
-        uint32_t s32 = 0;
+        uint32_t s32 = 0, s32S = 0;
         if (valid) {
             for (int c = 0; c < a.M_L; ++c) {
                 uint32_t r[4];
@@ -229,6 +230,7 @@ __global__ __launch_bounds__(kBlock) void gen_pairs_kernel(GenArgs a) {
                 if (c + 1 == a.M_S) {
                     Is = I;
                     Qs = Q;
+                    s32S = s32;
                     sS += s32;
                 }
             }
@@ -238,6 +240,8 @@ __global__ __launch_bounds__(kBlock) void gen_pairs_kernel(GenArgs a) {
             a.Q_S[o] = Qs;
             a.I_L[o] = I;
             a.Q_L[o] = Q;
+            if (a.psum_S) a.psum_S[o] = s32S;
+            if (a.psum_L) a.psum_L[o] = s32;
         }
     }
     sS = wave_sum_u64(sS);
@@ -261,7 +265,7 @@ using namespace qld;
 extern "C" qld_status qld_gen_pairs(const uint8_t *mask, const double *rates_host, int32_t n_tiles, int32_t H, int32_t W,
                                     int32_t M_short, int32_t M_long, uint32_t tile0, uint64_t seed, int32_t bits,
                                     int32_t *I_S, int32_t *Q_S, int32_t *I_L, int32_t *Q_L, uint64_t *sum_S,
-                                    uint64_t *sum_L, qld_hip_stream stream) {
+                                    uint64_t *sum_L, uint32_t *psum_S, uint32_t *psum_L, qld_hip_stream stream) {
     clear_error();
     if (n_tiles < 0 || H < 0 || W < 0 || M_short < 1 || M_long < M_short || bits < 1 || bits > 16) {
         set_error("invalid generator arguments");
@@ -322,6 +326,8 @@ extern "C" qld_status qld_gen_pairs(const uint8_t *mask, const double *rates_hos
     a.Q_L = Q_L;
     a.sum_S = reinterpret_cast<unsigned long long *>(sum_S);
     a.sum_L = reinterpret_cast<unsigned long long *>(sum_L);
+    a.psum_S = psum_S;
+    a.psum_L = psum_L;
     int32_t max_n = 1;
     for (int64_t i = 0; i < (int64_t)n_tiles * 8; ++i) max_n = std::max(max_n, table_size(rates_host[i]));
     a.thr_stride = std::min(kTableMax, max_n + 4);   // + 4: margin over the host's recomputation of n

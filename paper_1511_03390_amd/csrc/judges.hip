@@ -20,34 +20,37 @@
 namespace qld {
 namespace {
 
+// x = (I, Q) / sqrt(P / 2) per pixel (0 where P = 0); scale = sigma / sqrt(M),
+// sigma^2 = 2 * the tile's mean sample level.
 __global__ void prepare_kernel(const int32_t *__restrict__ I, const int32_t *__restrict__ Q,
-                               const unsigned long long *__restrict__ sum, int32_t M, int64_t npx,
-                               float *__restrict__ x, float *__restrict__ scale) {
+                               const uint32_t *__restrict__ psum, const unsigned long long *__restrict__ sum,
+                               int32_t M, int64_t npx, float *__restrict__ x, float *__restrict__ scale) {
     const int b = blockIdx.y;
-    const double mean = (double)sum[b] / (double)(npx * 4 * (int64_t)M);
-    const double sigma = sqrt(2.0 * mean);
-    const double den = sigma * sqrt((double)M);
-    if (blockIdx.x == 0 && threadIdx.x == 0) scale[b] = (float)(sigma / sqrt((double)M));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double mean = (double)sum[b] / (double)(npx * 4 * (int64_t)M);
+        scale[b] = (float)(sqrt(2.0 * mean) / sqrt((double)M));
+    }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
         const int64_t o = (int64_t)b * npx + p;
-        x[2 * o] = (float)((double)I[o] / den);
-        x[2 * o + 1] = (float)((double)Q[o] / den);
+        const double den = sqrt((double)psum[o] * 0.5);
+        const bool ok = den > 0.0;
+        x[2 * o] = ok ? (float)((double)I[o] / den) : 0.0f;
+        x[2 * o + 1] = ok ? (float)((double)Q[o] / den) : 0.0f;
     }
 }
 
+// t = sqrt(max(I^2 + Q^2 - P, 0)) / M / scale per pixel, P the pixel's sample sum.
 __global__ void target_kernel(const int32_t *__restrict__ I, const int32_t *__restrict__ Q,
-                              const unsigned long long *__restrict__ sum, int32_t M, const float *__restrict__ scale,
+                              const uint32_t *__restrict__ psum, int32_t M, const float *__restrict__ scale,
                               int64_t npx, float *__restrict__ t) {
     const int b = blockIdx.y;
-    const double mean = (double)sum[b] / (double)(npx * 4 * (int64_t)M);
-    const double noise = 4.0 * (double)M * mean;
     const double sc = (double)scale[b];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
         const int64_t o = (int64_t)b * npx + p;
         const double i = I[o], q = Q[o];
-        const double r2 = i * i + q * q - noise;
+        const double r2 = i * i + q * q - (double)psum[o];
         t[o] = (float)(sqrt(r2 > 0.0 ? r2 : 0.0) / (double)M / sc);
     }
 }
@@ -187,31 +190,31 @@ dim3 pix_grid(int64_t npx, int B) { return dim3((unsigned)std::min<int64_t>(ceil
 
 using namespace qld;
 
-extern "C" qld_status qld_denoise_prepare(const int32_t *I_S, const int32_t *Q_S, const uint64_t *sum_S, int32_t M_S,
-                                          int32_t B, int32_t H, int32_t W, float *x, float *scale,
-                                          qld_hip_stream stream) {
+extern "C" qld_status qld_denoise_prepare(const int32_t *I_S, const int32_t *Q_S, const uint32_t *psum_S,
+                                          const uint64_t *sum_S, int32_t M_S, int32_t B, int32_t H, int32_t W,
+                                          float *x, float *scale, qld_hip_stream stream) {
     clear_error();
-    if (!I_S || !Q_S || !sum_S || !x || !scale || M_S < 1 || B < 1 || B > 65535 || H < 1 || W < 1) {
+    if (!I_S || !Q_S || !psum_S || !sum_S || !x || !scale || M_S < 1 || B < 1 || B > 65535 || H < 1 || W < 1) {
         set_error("prepare: bad arguments");
         return QLD_E_INVAL;
     }
     const int64_t npx = (int64_t)H * W;
     hipLaunchKernelGGL(prepare_kernel, pix_grid(npx, B), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), I_S, Q_S,
-                       reinterpret_cast<const unsigned long long *>(sum_S), M_S, npx, x, scale);
+                       psum_S, reinterpret_cast<const unsigned long long *>(sum_S), M_S, npx, x, scale);
     return check_hip(hipGetLastError(), "prepare_kernel launch");
 }
 
-extern "C" qld_status qld_denoise_target(const int32_t *I_L, const int32_t *Q_L, const uint64_t *sum_L, int32_t M_L,
+extern "C" qld_status qld_denoise_target(const int32_t *I_L, const int32_t *Q_L, const uint32_t *psum_L, int32_t M_L,
                                          const float *scale, int32_t B, int32_t H, int32_t W, float *t,
                                          qld_hip_stream stream) {
     clear_error();
-    if (!I_L || !Q_L || !sum_L || !scale || !t || M_L < 1 || B < 1 || B > 65535 || H < 1 || W < 1) {
+    if (!I_L || !Q_L || !psum_L || !scale || !t || M_L < 1 || B < 1 || B > 65535 || H < 1 || W < 1) {
         set_error("target: bad arguments");
         return QLD_E_INVAL;
     }
     const int64_t npx = (int64_t)H * W;
     hipLaunchKernelGGL(target_kernel, pix_grid(npx, B), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), I_L, Q_L,
-                       reinterpret_cast<const unsigned long long *>(sum_L), M_L, scale, npx, t);
+                       psum_L, M_L, scale, npx, t);
     return check_hip(hipGetLastError(), "target_kernel launch");
 }
 

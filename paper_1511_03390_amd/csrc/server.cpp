@@ -78,6 +78,8 @@ struct StreamRec {
     float *scale = nullptr;         // [1]
     uint64_t *sumS = nullptr;       // [1] short-window sample sum
     uint64_t *csum = nullptr;       // [ring][kCycleSumBlocks] per-cycle partial sums
+    uint32_t *pcs = nullptr;        // [ring][H][W] per-pixel cycle sums
+    uint32_t *psS = nullptr;        // [H][W] per-pixel short-window sums
     float *gate_dev = nullptr;      // [out_slots]
     float *gate_host = nullptr;     // pinned [out_slots]
     int ring = 0;
@@ -180,7 +182,7 @@ size_t stream_bytes(const qld_server *s, const qld_frame_desc *d, int M, int Ms,
     size_t learned = 0;
     if (mode == QLD_MODE_LEARNED)
         learned = (size_t)s->out_slots * npx * 4 + npx * 8 + (size_t)learned_ring(Ms) * kCycleSumBlocks * 8 +
-                  (size_t)s->out_slots * 4 + 64;
+                  (size_t)s->out_slots * 4 + 64 + ((size_t)learned_ring(Ms) + 1) * npx * 4;
     return wb + stage + out + iq + learned;
 }
 
@@ -194,12 +196,14 @@ void free_stream_mem(StreamRec *r) {
     if (r->served) (void)hipFree(r->served);
     if (r->x) (void)hipFree(r->x);
     if (r->csum) (void)hipFree(r->csum);
+    if (r->pcs) (void)hipFree(r->pcs);
     if (r->gate_host) (void)hipHostFree(r->gate_host);
     r->stage = r->pin = nullptr;
     r->out_amp = nullptr;
     r->out_iq = r->Io = r->Qo = r->Iso = r->Qso = nullptr;
     r->served = r->x = r->scale = r->gate_dev = r->gate_host = nullptr;
     r->csum = r->sumS = nullptr;
+    r->pcs = r->psS = nullptr;
     for (auto &e : r->pin_ev)
         if (e) (void)hipEventDestroy(e), e = nullptr;
     for (auto &e : r->slot_ev)
@@ -247,6 +251,10 @@ qld_status alloc_stream(qld_server *srv, StreamRec *r) {
         }
         if (e == hipSuccess) {
             r->sumS = r->csum + (size_t)r->ring * kCycleSumBlocks;
+            e = hipMalloc(&r->pcs, ((size_t)r->ring + 1) * npx * 4 + 16);
+        }
+        if (e == hipSuccess) {
+            r->psS = r->pcs + (size_t)r->ring * npx;
             e = hipHostMalloc(&r->gate_host, (size_t)srv->out_slots * 4 + 16, hipHostMallocDefault);
         }
     }
@@ -300,6 +308,9 @@ hipError_t run_learned(qld_server *srv, const LearnedJob &L) {
     const int64_t npx = (int64_t)r->d.H * r->d.W;
     hipError_t e = launch_cycle_sums(r->stage, r->slot_b, kStageCycles, L.stage0, L.n, r->eb, r->csum, r->ring, L.c0,
                                      kCycleSumBlocks, s);
+    if (e == hipSuccess)
+        e = launch_pixel_cycle_sums(r->stage, r->slot_b, r->fs_b, r->rp_b, kStageCycles, L.stage0, L.n, r->eb, r->d.H,
+                                    r->d.W, r->pcs, r->ring, L.c0, s);
     for (int i = 0; i < L.n && e == hipSuccess; ++i) {
         const int64_t c = L.c0 + i;
         const int o = (L.out0 + i) % srv->out_slots;
@@ -308,9 +319,10 @@ hipError_t run_learned(qld_server *srv, const LearnedJob &L) {
         const float inv_n = 1.0f / (float)std::min<int64_t>(c + 1, r->M);
         if (c + 1 >= r->Ms) {
             e = launch_window_sum(r->csum, r->ring, kCycleSumBlocks, c, r->Ms, r->sumS, s);
+            if (e == hipSuccess) e = launch_pixel_window_sum(r->pcs, r->ring, npx, c, r->Ms, r->psS, s);
             if (e == hipSuccess &&
-                (qld_denoise_prepare(r->Iso + (size_t)o * npx, r->Qso + (size_t)o * npx, r->sumS, r->Ms, 1, r->d.H,
-                                     r->d.W, r->x, r->scale, s) != QLD_OK ||
+                (qld_denoise_prepare(r->Iso + (size_t)o * npx, r->Qso + (size_t)o * npx, r->psS, r->sumS, r->Ms, 1,
+                                     r->d.H, r->d.W, r->x, r->scale, s) != QLD_OK ||
                  qld_denoiser_forward(L.dn, r->x, 1, nullptr, nullptr, s) != QLD_OK))
                 e = hipErrorLaunchFailure;
             if (e == hipSuccess) e = launch_serve(L.y, r->scale, L.gate, plain, npx, L.thr, inv_n, served,

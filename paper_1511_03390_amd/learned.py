@@ -44,10 +44,10 @@ class Batch:
         self.mask = torch.from_numpy(params["mask"]).cuda()
         self.rates = params["rates"]
         self.M_S, self.M_L = M_S, M_L
-        self.I_S, self.Q_S, self.I_L, self.Q_L, self.sum_S, self.sum_L = qld.gen_pairs(
-            self.mask, self.rates, M_S, M_L, tile0, seed, bits)
-        self.x, self.scale = qld.denoise_prepare(self.I_S, self.Q_S, self.sum_S, M_S)
-        self.t = qld.denoise_target(self.I_L, self.Q_L, self.sum_L, M_L, self.scale)
+        (self.I_S, self.Q_S, self.I_L, self.Q_L, self.sum_S, self.sum_L, self.psum_S,
+         self.psum_L) = qld.gen_pairs(self.mask, self.rates, M_S, M_L, tile0, seed, bits)
+        self.x, self.scale = qld.denoise_prepare(self.I_S, self.Q_S, self.psum_S, self.sum_S, M_S)
+        self.t = qld.denoise_target(self.I_L, self.Q_L, self.psum_L, M_L, self.scale)
         self.clean = qld.clean_amplitude(self.mask, self.rates)
         B, H, W = self.I_S.shape
         self.B, self.H, self.W = B, H, W
@@ -100,7 +100,18 @@ def evaluate(d, n_batches=2, batch=8, H=512, W=512, M_S=8, M_L=512, seed=1511033
     y = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
     gate = torch.empty(batch, dtype=torch.float32, device="cuda")
     acc = {k: [] for k in ("learned", "plain_S", "plain_L", "plain_L_bias_reduced", "served", "gate",
-                           "learned_vs_noisy_L")}
+                           "learned_vs_noisy_L", "cnr_learned", "cnr_plain_S", "cnr_plain_L")}
+
+    def tile_cnr(img, m):
+        """(mean over the mask - mean outside) / std outside, per tile: the
+        contrast a detector sees (0 for an image that ignores the scene)."""
+        m = m.bool()
+        out = []
+        for i in range(img.shape[0]):
+            a, bg = img[i][m[i]], img[i][~m[i]]
+            out.append(float(((a.mean() - bg.mean()) / bg.std()).item()) if a.numel() and bg.numel() > 1 else 0.0)
+        return np.array(out)
+
     for k in range(n_batches):
         b = tile_batch(first_step + k, batch, H, W, M_S, M_L, seed, tiles)
         d.forward(b.x, y, gate)
@@ -108,6 +119,9 @@ def evaluate(d, n_batches=2, batch=8, H=512, W=512, M_S=8, M_L=512, seed=1511033
         acc["plain_S"].append(qld.judge_nrmse(b.ampS, b.clean, b.invS).cpu().numpy())
         acc["plain_L"].append(qld.judge_nrmse(b.ampL, b.clean, b.invL).cpu().numpy())
         acc["plain_L_bias_reduced"].append(qld.judge_nrmse(b.t, b.clean, b.scale).cpu().numpy())
+        acc["cnr_learned"].append(tile_cnr(y, b.mask))
+        acc["cnr_plain_S"].append(tile_cnr(b.ampS, b.mask))
+        acc["cnr_plain_L"].append(tile_cnr(b.ampL, b.mask))
         ampL_pc = b.ampL * b.invL[:, None, None]
         acc["learned_vs_noisy_L"].append(qld.judge_nrmse(y, ampL_pc, b.scale).cpu().numpy())
         g = gate.cpu().numpy()

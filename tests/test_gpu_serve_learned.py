@@ -5,7 +5,7 @@ choice between its image and the plain long-window amplitude per cycle.
 Bars: the plain amplitude within 2 ulp and the short-window I/Q bit-exact
 against the oracle's brute-force windows (resets included); the served image,
 gate and flag bit-exact against the same library entry points called one by
-one on the same inputs (qld_denoise_prepare with the exact host sample sum,
+one on the same inputs (qld_denoise_prepare with the exact host sample sums,
 qld_denoiser_forward), whose own parity against the oracle is tested in
 test_gpu_learned.py; a PLAIN stream in the same launches unchanged.
 """
@@ -78,13 +78,20 @@ def run(H, W, M, Ms, cycles, thr, gap_after=None, out_slots=32, seed=3, with_pla
     return out, pout, dn
 
 
-def reproduce(dn, Is, Qs, sum_S, Ms):
+def window_sums(cycles, c, Ms):
+    """Each pixel's and the frame's sample sums over window cycles c - Ms + 1 .. c."""
+    P = sum(cycles[j].astype(np.int64).sum(axis=0) for j in range(c - Ms + 1, c + 1))
+    return P, int(P.sum())
+
+
+def reproduce(dn, Is, Qs, psum_S, sum_S, Ms):
     """The served image of one cycle from the library's entry points, called one by one."""
     H, W = Is.shape
     I_d = torch.from_numpy(Is[None]).cuda()
     Q_d = torch.from_numpy(Qs[None]).cuda()
+    p_d = torch.from_numpy(psum_S.astype(np.uint32).view(np.int32)[None]).cuda()
     s_d = torch.tensor([sum_S], dtype=torch.int64).cuda()
-    x, scale = qld.denoise_prepare(I_d, Q_d, s_d, Ms)
+    x, scale = qld.denoise_prepare(I_d, Q_d, p_d, s_d, Ms)
     y = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
     g = torch.empty(1, dtype=torch.float32, device="cuda")
     dn.forward(x, y, g)
@@ -106,8 +113,8 @@ def check(out, cycles, M, Ms, thr, resets=(), dn=None):
         inv_n = np.float32(1.0) / np.float32(min(c + 1, M))
         plain_pc = r["plain"].astype(np.float32) * inv_n
         if c + 1 >= Ms:
-            sum_S = int(sum(cycles[j].astype(np.int64).sum() for j in range(k - Ms + 1, k + 1)))
-            y, g = reproduce(dn, r["Is"], r["Qs"], sum_S, Ms)
+            P, sum_S = window_sums(cycles, k, Ms)
+            y, g = reproduce(dn, r["Is"], r["Qs"], P, sum_S, Ms)
             assert r["gate"] == g, (k, r["gate"], g)
             use = g <= thr
             assert r["learned"] == int(use), k
@@ -183,8 +190,8 @@ def test_learned_stream_full_size_sampled():
         r = got[c]
         assert np.array_equal(r["Is"][ys, xs], shortw[c][0][0]) and np.array_equal(r["Qs"][ys, xs], shortw[c][1][0]), c
         assert amp_ulps(r["plain"][ys, xs], oracle.amplitude(longw[c][0][0], longw[c][1][0])).max() <= 2.0, c
-        sum_S = int(sum(bank[j % nb].astype(np.int64).sum() for j in range(c - Ms + 1, c + 1)))
-        y, g = reproduce(dn, r["Is"], r["Qs"], sum_S, Ms)
+        P, sum_S = window_sums([bank[j % nb] for j in range(c + 1)], c, Ms)
+        y, g = reproduce(dn, r["Is"], r["Qs"], P, sum_S, Ms)
         assert r["gate"] == g and r["learned"] == 1, c
         assert np.array_equal(r["served"], y), c
         assert r["warm"] == (1 if c + 1 >= M else 0), c
