@@ -434,7 +434,9 @@ qld_status qld_stream_set_denoiser(qld_server *s, int32_t stream_id, qld_denoise
  * stream and camera cycle in qld_stream_poll).  Frame
  * index f has lock-in phase f mod 4; a cycle is the four frames 4m..4m+3.
  * The frame is copied into pinned staging before the call returns, so the
- * caller may reuse its buffer at once.  frame_index must be the previous
+ * caller may reuse its buffer at once; a frame already in page-locked host
+ * memory (hipHostMalloc) is copied to the device straight from the caller's
+ * buffer instead, and the call returns once that copy is done.  frame_index must be the previous
  * index + 1: a larger index resets the window (the partial cycle is dropped,
  * frames are skipped until the next index that is a multiple of 4) and the
  * call returns QLD_E_GAP; a smaller one is rejected (QLD_E_INVAL).  A pending

@@ -86,6 +86,7 @@ struct StreamRec {
     uint8_t *pin = nullptr;         // [kPinnedCycles][4][H][W]: frame (k, phase) at k % kPinnedCycles
     size_t frame_bytes = 0;
     hipEvent_t pin_ev[kPinnedFrames] = {};   // last copy out of each pinned frame
+    hipEvent_t direct_ev = nullptr;          // copy straight from a caller's page-locked frames
     bool pin_used[kPinnedFrames] = {};
     hipEvent_t slot_ev[kStageCycles] = {};
     uint64_t slot_tarr[kStageCycles] = {};
@@ -208,6 +209,7 @@ void free_stream_mem(StreamRec *r) {
         if (e) (void)hipEventDestroy(e), e = nullptr;
     for (auto &e : r->slot_ev)
         if (e) (void)hipEventDestroy(e), e = nullptr;
+    if (r->direct_ev) (void)hipEventDestroy(r->direct_ev), r->direct_ev = nullptr;
 }
 
 // Allocate the device/pinned memory of an admitted stream (mu held).
@@ -263,6 +265,7 @@ qld_status alloc_stream(qld_server *srv, StreamRec *r) {
         e = hipEventCreateWithFlags(&r->pin_ev[i], hipEventDisableTiming);
     for (int i = 0; e == hipSuccess && i < kStageCycles; ++i)
         e = hipEventCreateWithFlags(&r->slot_ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->direct_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_stream_mem(r);
@@ -697,21 +700,38 @@ qld_status wait_slot(qld_server *s, StreamRec *r, std::unique_lock<std::mutex> &
     return QLD_OK;
 }
 
+// True if p lies in page-locked host memory (hipHostMalloc), which the copy
+// engine reads directly.  Pageable memory makes the query fail; the error is
+// cleared so that the next call does not report it.
+bool page_locked(const void *p) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) == hipSuccess) return at.type == hipMemoryTypeHost;
+    (void)hipGetLastError();
+    return false;
+}
+
 // Copies n frames (phases phase .. phase + n - 1 of the stream's next cycle)
-// from host memory into pinned staging and enqueues one host-to-device copy
-// of them on the copy stream; the cycle goes to the scheduler once its last
-// frame is in.  mu is held on entry and exit and released around the copies.
+// to the stream's device staging with one host-to-device copy on the copy
+// stream; the cycle goes to the scheduler once its last frame is in.  Frames
+// in pageable memory are first copied into the stream's pinned staging (so
+// the caller may reuse its buffer at once); frames already in page-locked
+// memory are copied straight from the caller's buffer, and the call waits for
+// that copy before it returns (same ownership rule, one copy fewer).  mu is
+// held on entry and exit and released around the copies.
 qld_status stage_frames(qld_server *s, StreamRec *r, std::unique_lock<std::mutex> &lk, const void *host, int phase,
                         int n, int64_t cam_cycle, uint64_t t_arrival_ns) {
     const int64_t k = r->submitted;
     const int slot = (int)(k % kStageCycles);
+    const bool direct = page_locked(host);
     const int p0 = (int)(k % kPinnedCycles) * 4 + phase;
-    bool used[4];
-    hipEvent_t pev[4];
-    for (int i = 0; i < n; ++i) {
-        used[i] = r->pin_used[p0 + i];
-        r->pin_used[p0 + i] = true;
-        pev[i] = r->pin_ev[p0 + i];
+    bool used[4] = {};
+    hipEvent_t pev[4] = {};
+    if (!direct) {
+        for (int i = 0; i < n; ++i) {
+            used[i] = r->pin_used[p0 + i];
+            r->pin_used[p0 + i] = true;
+            pev[i] = r->pin_ev[p0 + i];
+        }
     }
     uint8_t *pin = r->pin + (size_t)p0 * r->frame_bytes;
     uint8_t *dst = r->stage + (size_t)slot * r->slot_b + (size_t)phase * r->fs_b;
@@ -719,17 +739,25 @@ qld_status stage_frames(qld_server *s, StreamRec *r, std::unique_lock<std::mutex
     lk.unlock();
 
     hipError_t e = hipSuccess;
-    for (int i = 0; i < n && e == hipSuccess; ++i)
-        if (used[i]) e = hipEventSynchronize(pev[i]);   // the pinned frame's previous copy is done
-    if (e == hipSuccess) {
-        memcpy(pin, host, (size_t)n * r->frame_bytes);
-        // The staged frames of a cycle are consecutive [H][Wp] planes, so n
-        // frames are one copy of n * H rows.
-        e = hipMemcpy2DAsync(dst, (size_t)r->rp_b, pin, row, row, (size_t)n * r->d.H, hipMemcpyHostToDevice,
+    if (direct) {
+        e = hipMemcpy2DAsync(dst, (size_t)r->rp_b, host, row, row, (size_t)n * r->d.H, hipMemcpyHostToDevice,
                              s->copy);
+        if (e == hipSuccess && phase + n == 4) e = hipEventRecord(r->slot_ev[slot], s->copy);
+        if (e == hipSuccess) e = hipEventRecord(r->direct_ev, s->copy);
+        if (e == hipSuccess) e = hipEventSynchronize(r->direct_ev);   // the caller's buffer is free again
+    } else {
+        for (int i = 0; i < n && e == hipSuccess; ++i)
+            if (used[i]) e = hipEventSynchronize(pev[i]);   // the pinned frame's previous copy is done
+        if (e == hipSuccess) {
+            memcpy(pin, host, (size_t)n * r->frame_bytes);
+            // The staged frames of a cycle are consecutive [H][Wp] planes, so n
+            // frames are one copy of n * H rows.
+            e = hipMemcpy2DAsync(dst, (size_t)r->rp_b, pin, row, row, (size_t)n * r->d.H, hipMemcpyHostToDevice,
+                                 s->copy);
+        }
+        for (int i = 0; i < n && e == hipSuccess; ++i) e = hipEventRecord(pev[i], s->copy);
+        if (e == hipSuccess && phase + n == 4) e = hipEventRecord(r->slot_ev[slot], s->copy);
     }
-    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipEventRecord(pev[i], s->copy);
-    if (e == hipSuccess && phase + n == 4) e = hipEventRecord(r->slot_ev[slot], s->copy);
 
     lk.lock();
     if (e != hipSuccess) {

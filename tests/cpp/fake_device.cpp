@@ -13,6 +13,8 @@
 
 #include <atomic>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -35,8 +37,43 @@ hipError_t hipFree(void *p) {
     std::free(p);
     return hipSuccess;
 }
-hipError_t hipHostMalloc(void **p, size_t bytes, unsigned) { return hipMalloc(p, bytes); }
-hipError_t hipHostFree(void *p) { return hipFree(p); }
+namespace {
+std::mutex g_host_mu;
+std::map<uintptr_t, size_t> g_host;        // page-locked allocations: start -> bytes
+thread_local hipError_t g_last = hipSuccess;
+}  // namespace
+
+hipError_t hipHostMalloc(void **p, size_t bytes, unsigned) {
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_host_mu);
+        g_host[reinterpret_cast<uintptr_t>(*p)] = bytes;
+    }
+    return e;
+}
+hipError_t hipHostFree(void *p) {
+    {
+        std::lock_guard<std::mutex> lk(g_host_mu);
+        g_host.erase(reinterpret_cast<uintptr_t>(p));
+    }
+    return hipFree(p);
+}
+hipError_t hipPointerGetAttributes(hipPointerAttribute_t *attr, const void *p) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    std::lock_guard<std::mutex> lk(g_host_mu);
+    auto it = g_host.upper_bound(a);
+    if (it != g_host.begin()) {
+        --it;
+        if (a < it->first + it->second) {
+            *attr = hipPointerAttribute_t{};
+            attr->type = hipMemoryTypeHost;
+            attr->hostPointer = const_cast<void *>(p);
+            return hipSuccess;
+        }
+    }
+    g_last = hipErrorInvalidValue;
+    return hipErrorInvalidValue;
+}
 hipError_t hipMemset(void *p, int v, size_t bytes) {
     std::memset(p, v, bytes);
     return hipSuccess;
@@ -82,7 +119,11 @@ hipError_t hipGetDevice(int *dev) {
     *dev = 0;
     return hipSuccess;
 }
-hipError_t hipGetLastError() { return hipSuccess; }
+hipError_t hipGetLastError() {
+    const hipError_t e = g_last;
+    g_last = hipSuccess;
+    return e;
+}
 const char *hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "fake device error"; }
 hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int) {
     *v = 256;

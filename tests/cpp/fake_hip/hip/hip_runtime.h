@@ -34,6 +34,21 @@ typedef enum {
 
 typedef enum { hipDeviceAttributeMultiprocessorCount = 63 } hipDeviceAttribute_t;
 
+typedef enum hipMemoryType {
+    hipMemoryTypeUnregistered = 0,
+    hipMemoryTypeHost = 1,
+    hipMemoryTypeDevice = 2,
+} hipMemoryType;
+
+typedef struct hipPointerAttribute_t {
+    enum hipMemoryType type;
+    int device;
+    void *devicePointer;
+    void *hostPointer;
+    int isManaged;
+    unsigned allocationFlags;
+} hipPointerAttribute_t;
+
 constexpr unsigned hipEventDisableTiming = 0x2;
 constexpr unsigned hipStreamNonBlocking = 0x1;
 constexpr unsigned hipHostMallocDefault = 0x0;
@@ -67,3 +82,6 @@ hipError_t hipGetDevice(int *dev);
 hipError_t hipGetLastError();
 const char *hipGetErrorString(hipError_t e);
 hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t attr, int dev);
+// hipMemoryTypeHost inside a hipHostMalloc allocation; hipErrorInvalidValue
+// (and a sticky last error, as the runtime leaves) for any other host pointer.
+hipError_t hipPointerGetAttributes(hipPointerAttribute_t *attr, const void *p);

@@ -11,7 +11,8 @@
 // a held server launches nothing and then takes the three streams' cycles in
 // one launch; submits while held and staging is full return QLD_E_AGAIN and
 // take nothing; admission by budget in FIFO order; a frame-index gap resets
-// the window; whole-cycle submits from three threads share launches.
+// the window; whole-cycle submits from three threads share launches; frames
+// in page-locked memory take the direct copy.
 // Exit status 0 on success; messages name the failed check.
 #include <atomic>
 #include <chrono>
@@ -24,6 +25,8 @@
 #include <random>
 #include <thread>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "../../include/qld.h"
 
@@ -324,6 +327,38 @@ void test_flood(const std::vector<Cam> &cams) {
     CHECK(qld_server_destroy(s) == QLD_OK, "destroy");
 }
 
+// Frames in page-locked memory are copied straight from the caller's buffer;
+// the call returns once that copy is done, so the buffer may be refilled at once.
+void test_pinned_submit(const std::vector<Cam> &cams) {
+    const Cam &c = cams[1];
+    const size_t bytes = 4 * (size_t)c.H * c.W * sizeof(uint16_t);
+    void *pin = nullptr;
+    CHECK(hipHostMalloc(&pin, bytes, hipHostMallocDefault) == hipSuccess, "page-locked buffer");
+    qld_server *s = nullptr;
+    CHECK(qld_server_create((size_t)1 << 30, 64, 0, &s) == QLD_OK, "create");
+    int32_t id = 0;
+    const qld_frame_desc d = desc(c.H, c.W);
+    CHECK(qld_stream_open(s, &d, c.M, 0, QLD_MODE_PLAIN, &id) == QLD_OK, "open");
+    Poller poll(s);
+    const int n = 20;
+    for (int k = 0; k < n; ++k) {
+        std::memcpy(pin, c.cycles[k].data(), bytes);
+        CHECK(qld_stream_submit_cycle(s, id, pin, 4 * k, now_ns()) == QLD_OK, "pinned submit_cycle");
+    }
+    // Per frame from page-locked memory too.
+    const size_t fb = (size_t)c.H * c.W * sizeof(uint16_t);
+    for (int k = n; k < n + 4; ++k)
+        for (int f = 0; f < 4; ++f) {
+            std::memcpy(pin, c.cycles[k].data() + f * (size_t)c.H * c.W, fb);
+            CHECK(qld_stream_submit(s, id, pin, 4 * k + f, now_ns()) == QLD_OK, "pinned submit");
+        }
+    CHECK(qld_server_drain(s) == QLD_OK, "drain");
+    poll.finish();
+    check_stream("pinned", c, poll.got[id], n + 4);
+    CHECK(qld_server_destroy(s) == QLD_OK, "destroy");
+    CHECK(hipHostFree(pin) == hipSuccess, "free");
+}
+
 }  // namespace
 
 int main() {
@@ -332,6 +367,7 @@ int main() {
     test_hold_one_launch(cams);
     test_admission_and_gap(cams);
     test_flood(cams);
+    test_pinned_submit(cams);
     if (g_fail) {
         std::fprintf(stderr, "%d checks failed\n", g_fail);
         return 1;

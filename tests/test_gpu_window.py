@@ -283,6 +283,44 @@ def test_server_whole_cycle_submit_and_result_validity():
     srv.close()
 
 
+def test_server_submit_from_page_locked_frames():
+    """Frames in page-locked host memory are copied straight from the
+    caller's buffer (one copy fewer); the call waits for that copy, so the
+    buffer can be refilled at once.  One reused page-locked buffer, per cycle
+    and per frame, gives the oracle's window every cycle."""
+    need_gpu()
+    H, W, M, n = 33, 104, 4, 10
+    srv = qld.Server(1 << 32, out_slots=16, keep_iq=True)
+    sid, ok = srv.open(H, W, M, bits=16)
+    assert ok
+    cam = scenes.CameraStream(H, W, 77, bits=16, bank=8)
+    cyc = [np.ascontiguousarray(cam.cycle(c)) for c in range(n)]
+    pin = torch.empty((4, H, W), dtype=torch.int16, pin_memory=True)
+    pv = pin.numpy().view(np.uint16)
+    got = {}
+
+    def collect():
+        for r in srv.poll():
+            pI, pQ, _, _ = srv.result_iq(r)
+            got[r.cycle] = (qld.device_view(pI, (H, W), torch.int32).cpu().numpy(),
+                            qld.device_view(pQ, (H, W), torch.int32).cpu().numpy())
+
+    for c in range(n):
+        if c % 2 == 0:
+            pv[...] = cyc[c]
+            assert srv.submit_cycle(sid, pv, 4 * c, 0) == qld.OK
+        else:
+            for j in range(4):
+                pv[0] = cyc[c][j]
+                assert srv.submit(sid, pv[0], 4 * c + j, 0) == qld.OK
+        srv.drain()
+        collect()
+    ref = list(oracle.window_series(cyc, M))
+    for c in range(n):
+        assert np.array_equal(got[c][0], ref[c][0]) and np.array_equal(got[c][1], ref[c][1]), c
+    srv.close()
+
+
 def test_server_short_window_shares_ring():
     need_gpu()
     M, Ms, n = 8, 3, 14
