@@ -520,8 +520,8 @@ def bench_bank(qld, torch, frames, dft_ms, F=32, reps=5):
             "mfma_tflops_executed": round(6 * flop / (ms * 1e-3) / 1e12, 1), "bf16_mfma_peak_tflops": 2500.0,
             "frac": round(6 * flop / (ms * 1e-3) / 2500e12, 4),
             "frame_bytes_gbs": round(2.0 * T * H * W / (ms * 1e-3) / 1e9, 1),
-            "single_frequency_x%d_ms" % F: round(F * dft_ms, 3),
-            "speedup_vs_single_frequency": round(F * dft_ms / ms, 1),
+            "single_frequency_x%d_ms" % F: round(F * dft_ms, 3) if dft_ms else None,
+            "speedup_vs_single_frequency": round(F * dft_ms / ms, 1) if dft_ms else None,
             "full_fft": fft}
 
 
@@ -968,8 +968,10 @@ def main():
                     help="lay the stack out with frame stride H*W instead of qld_frame_stride_hint")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprofv3 byte counters)")
-    ap.add_argument("--leg", choices=("all", "learned_step"), default="all",
-                    help="learned_step: only the learned path's kernels at 8 x 512^2 (for profiling)")
+    ap.add_argument("--leg", choices=("all", "learned_step", "bank", "windows"), default="all",
+                    help="for profiling one part alone: learned_step (the learned path's kernels at 8 x 512^2), "
+                         "bank (the 32-frequency bank over the 1024^3 stack), windows (the per-frame and cycle "
+                         "windows)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; "
@@ -988,12 +990,27 @@ def main():
             out["copy_calibration"] = copy_calibration(torch)
         print(json.dumps(out), flush=True)
         return
+    if args.leg == "windows":
+        log("per-frame window, then cycle window with device-resident frames")
+        out = {"leg": "windows", "frame_window": bench_frame_window(qld, torch),
+               "window_device": bench_window_device(qld, torch)}
+        if args.copy_calibration:
+            out["copy_calibration"] = copy_calibration(torch)
+        print(json.dumps(out), flush=True)
+        return
     fstride = H * W if args.dense else qld.frame_stride_hint(H, W)
     log("generating the 1024x1024x1024 uint16 stack on the GPU (frame stride %d elements)" % fstride)
     st = scenes.diffuse_scene_u16(device="cuda", frame_stride=fstride)
     frames = st.frames
     torch.cuda.synchronize()
 
+    if args.leg == "bank":
+        log("lock-in bank over the stack")
+        out = {"leg": "bank", "lockin_bank": bench_bank(qld, torch, frames, None)}
+        if args.copy_calibration:
+            out["copy_calibration"] = copy_calibration(torch)
+        print(json.dumps(out), flush=True)
+        return
     log("batch QLD: %d warmup + %d timed steps" % (args.warmup, args.steps))
     elapsed, kern_ms, _ = bench_batch(qld, torch, frames, args.steps, args.warmup)
     ms_step = elapsed / args.steps * 1e3
