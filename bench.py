@@ -7,7 +7,7 @@ seeded diffuse scene -- Poisson background ~2000 counts with a linear +-50
 ambient drift and a weak modulated mask of 5 rectangles.  A step is one
 qld_lockin_image call: I/Q, the amplitude image and the per-frame sum /
 saturation count of the stack, in one pass over the frames.  The stack is
-laid out with the frame stride qld_frame_stride_hint gives (a 256-byte gap
+laid out with the frame stride qld_frame_stride_hint gives (a 4 KiB gap
 after each 2 MiB frame; --dense for frame stride H*W).
 
 Printed: one JSON line with the pixel-frames/s of the step, the roofline of

@@ -87,10 +87,12 @@ typedef struct {
  * qld_frame_stride_hint -- host-side helper: the frame stride (in ELEMENTS)
  * to allocate a [T][H][row_pitch] stack with, for frames of H rows of
  * row_pitch elements of `dtype`.  It is the frame size rounded up to 256
- * bytes, plus 256 bytes when that size is a multiple of 64 KiB: with such
- * sizes (1024 x 1024 uint16 frames are 2 MiB) the same pixel of consecutive
- * frames falls on the same HBM bank, and the batch kernels, which read four
- * consecutive frames of a pixel at once, measured 2-5% slower on MI355X.
+ * bytes, plus a gap when that size is a multiple of 64 KiB: with such sizes
+ * (1024 x 1024 uint16 frames are 2 MiB) the same pixel of consecutive frames
+ * falls on the same HBM bank, and the batch kernels, which read four
+ * consecutive frames of a pixel at once, measured 2-7% slower on MI355X.
+ * The gap is 4 KiB for frames of 2 MiB and more, 256 bytes for smaller ones
+ * (the faster of the two measured at each size).
  * Any stride >= the frame size works with every call; this one is faster.
  * Returns 0 for invalid arguments (H or W < 0, row_pitch < W, unknown dtype)
  * and for empty frames (H = 0 or row_pitch = 0), which need no stride.

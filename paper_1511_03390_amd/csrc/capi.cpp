@@ -165,8 +165,9 @@ int64_t qld_frame_stride_hint(int32_t H, int32_t W, int64_t row_pitch, qld_dtype
     int64_t bytes = (int64_t)H * row_pitch * eb;
     bytes = (bytes + 255) / 256 * 256;
     // Frames whose size is a multiple of 64 KiB put the same pixel of
-    // consecutive frames on the same HBM bank; a 256-byte gap moves them apart.
-    if (bytes > 0 && bytes % 65536 == 0) bytes += 256;
+    // consecutive frames on the same HBM bank; a gap moves them apart: 4 KiB
+    // for frames of 2 MiB and more, 256 bytes below that (measured best).
+    if (bytes > 0 && bytes % 65536 == 0) bytes += bytes >= (2 << 20) ? 4096 : 256;
     return bytes / eb;
 }
 

@@ -62,9 +62,13 @@ def test_accumulate_argument_errors():
 
 
 def test_frame_stride_hint():
-    # 1024 x 1024 uint16 frames are 2 MiB, a multiple of 64 KiB: a 256-byte gap.
-    assert q.frame_stride_hint(1024, 1024) == 1024 * 1024 + 128
+    # Sizes that are multiples of 64 KiB get a gap: 4 KiB from 2 MiB up
+    # (1024 x 1024 and 2048 x 2048 uint16), 256 bytes below (1 MiB and less).
+    assert q.frame_stride_hint(1024, 1024) == 1024 * 1024 + 2048
+    assert q.frame_stride_hint(2048, 2048) == 2048 * 2048 + 2048
+    assert q.frame_stride_hint(1024, 2048, dtype=q.U8) == 1024 * 2048 + 4096
     assert q.frame_stride_hint(256, 256) == 256 * 256 + 128
+    assert q.frame_stride_hint(512, 512) == 512 * 512 + 128
     assert q.frame_stride_hint(1024, 1024, dtype=q.U8) == 1024 * 1024 + 256
     # Other sizes: rounded up to 256 bytes only.
     assert q.frame_stride_hint(2160, 2160) == 2160 * 2160          # 9 331 200 B, a multiple of 256
