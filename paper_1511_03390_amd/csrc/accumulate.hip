@@ -62,9 +62,10 @@ struct AccumArgs {
     int32_t rot;           // phase of frame 0, mod 4
     int32_t x_begin;       // first column this kernel covers
     int32_t ncols;         // columns it covers (vector kernel: whole lanes only)
-    int32_t n_tiles;       // work-group tiles over its lanes
+    int32_t n_tiles;       // work-group tiles over its lanes (vector kernel: wide tiles of tk tiles)
+    int32_t tk;            // vector kernel: 256-lane tiles per wide tile (1, 2 or 4)
     int32_t n_units;       // (tile, split) work units, tiles rounded up to a multiple of kXcds
-    int32_t row_base;      // first stats-partial row of this kernel (vector: one per tile, scalar: per wave)
+    int32_t row_base;      // first stats-partial row of this kernel (vector: one per wide tile, scalar: per wave)
     uint32_t top;          // 2^bits - 1
     int32_t *I;
     int32_t *Q;
@@ -278,28 +279,6 @@ __device__ __forceinline__ uint32_t count_top(const u32x4 &d, uint32_t top) {
     return c;
 }
 
-// Statistics of one frame: its lane sum into the LDS buffer; a packed max tells
-// whether any sample is clipped, and only then are they counted with ballots.
-// (Checking once per cycle instead measured slower on MI355X.)
-template <int ELEM>
-__device__ __forceinline__ void frame_stats(const u32x4 &d, uint32_t top, StatsLds &st) {
-    const int j = st.slot;
-    st.put(lane_sum16<ELEM>(d));
-    const u16x2 mx = lane_max16<ELEM>(d);
-    if (__ballot(max((uint32_t)mx[0], (uint32_t)mx[1]) >= top)) st.sat(j, count_top<ELEM>(d, top));
-}
-
-// Statistics of one cycle (four frames) of the vector kernel.
-template <int ELEM>
-__device__ __forceinline__ void cycle_stats(const u32x4 &d0, const u32x4 &d1, const u32x4 &d2, const u32x4 &d3,
-                                            uint32_t top, StatsLds &st) {
-    frame_stats<ELEM>(d0, top, st);
-    frame_stats<ELEM>(d1, top, st);
-    frame_stats<ELEM>(d2, top, st);
-    frame_stats<ELEM>(d3, top, st);
-    if (st.slot == kStatsSlots) st.flush();
-}
-
 // Accumulators of one lane: int32 I/Q per pixel plus packed 16-bit partials.
 template <int ELEM>
 struct Acc {
@@ -381,38 +360,82 @@ __device__ __forceinline__ u32x4 ld16(const uint8_t *p) {
     return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
 }
 
+// Statistics of one frame of a lane's TK 16-byte groups: their lane sum into
+// the LDS buffer; a packed max tells whether any sample is clipped, and only
+// then are they counted with ballots.
+template <int ELEM, int TK>
+__device__ __forceinline__ void frame_stats_k(const u32x4 (&d)[TK], uint32_t top, StatsLds &st) {
+    const int j = st.slot;
+    uint32_t sum = lane_sum16<ELEM>(d[0]);
+    u16x2 mx = lane_max16<ELEM>(d[0]);
+#pragma unroll
+    for (int k = 1; k < TK; ++k) {
+        sum += lane_sum16<ELEM>(d[k]);
+        mx = __builtin_elementwise_max(mx, lane_max16<ELEM>(d[k]));
+    }
+    st.put(sum);
+    if (__ballot(max((uint32_t)mx[0], (uint32_t)mx[1]) >= top)) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < TK; ++k) c += count_top<ELEM>(d[k], top);
+        st.sat(j, c);
+    }
+}
+
 // PACKED: 16-bit partials hold `fold_every` cycles without overflow
 // (fold_every * (2^bits - 1) <= 32767); otherwise every cycle goes to int32.
 // MASKED: some lanes of this work-group are past the last vector; they read
 // a valid address and zero what they read.
+// TK: the work-group's unit is a wide tile of TK adjacent 256-lane tiles; a
+// lane owns one 16-byte group in each (TK loads per frame).  Large images
+// then fit the persistent grid in one round: every work-group sweeps the
+// frames from the first to the last once, together, where several rounds of
+// one tile per unit let the work-groups drift apart in the stack (2048 x
+// 2048 x 256: 4 rounds at 68-72% of 8 TB/s against 82-85% for one round at
+// the same frame stride).
 // stats_parity: the comb half of the work-group's next statistics flush.  It
 // is carried from one persistent-grid unit to the next (every wave of the
 // work-group flushes equally often, so it is uniform): a unit that ends on an
 // odd number of flushes must not start the next unit on the half whose read
 // by wave 0 only the next flush's barrier orders.
-template <int ELEM, bool STATS, bool PACKED, bool MASKED>
+template <int ELEM, bool STATS, bool PACKED, bool MASKED, int TK>
 __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split, int S, uint32_t *stats_lds,
                                          uint32_t *stats_comb, int &stats_parity) {
     constexpr int kPx = 16 / ELEM;
     const int nvx = a.ncols / kPx;
     const int64_t n_vec = (int64_t)nvx * a.H;
-    const int64_t g = (int64_t)tile * kBlock + threadIdx.x;
-    const bool valid = !MASKED || g < n_vec;
-    const int64_t gc = valid ? g : (int64_t)tile * kBlock;     // lane 0 of the tile is always valid
-    const int64_t y = gc / nvx;
-    const int x0 = a.x_begin + (int)(gc % nvx) * kPx;
-    const uint32_t vmask = valid ? 0xffffffffu : 0u;
-
     // This work-group owns cycles split, split + S, split + 2S, ... of its
-    // tile, so all work-groups sweep the stack together.
+    // tiles, so all work-groups sweep the stack together.
     const int64_t n_cyc_all = a.n_frames >> 2;
     const int64_t my = split < n_cyc_all ? (n_cyc_all - split + S - 1) / S : 0;
     const int64_t fs = a.fs_b;
     const int64_t step = 4 * S * fs;
-    const uint8_t *p = a.frames + y * a.rp_b + (int64_t)x0 * ELEM + 4 * (int64_t)split * fs;
 
-    Acc<ELEM> acc;
-    acc.zero();
+    // Group k of the lane: its vector (row y, first column x0), recomputed
+    // where needed rather than kept live through the frame loop.  A lane past
+    // the last vector reads one that exists and zeroes what it reads.
+    auto coords = [&](int k, int64_t &y, int &x0) {
+        const int64_t t0 = ((int64_t)tile * TK + k) * kBlock;          // first vector of 256-lane tile k
+        const int64_t g = t0 + threadIdx.x;
+        const bool ok = !MASKED || g < n_vec;
+        const int64_t gc = ok ? g : (t0 < n_vec ? t0 : 0);
+        y = gc / nvx;
+        x0 = a.x_begin + (int)(gc % nvx) * kPx;
+        return ok;
+    };
+    uint32_t vmask[TK];
+    const uint8_t *p[TK];
+#pragma unroll
+    for (int k = 0; k < TK; ++k) {
+        int64_t y;
+        int x0;
+        vmask[k] = coords(k, y, x0) ? 0xffffffffu : 0u;
+        p[k] = a.frames + y * a.rp_b + (int64_t)x0 * ELEM + 4 * (int64_t)split * fs;
+    }
+
+    Acc<ELEM> acc[TK];
+#pragma unroll
+    for (int k = 0; k < TK; ++k) acc[k].zero();
     StatsLds st;
     if constexpr (STATS) {
         st.part_sum = a.part_sum;
@@ -424,49 +447,73 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
         st.split = split;
         st.S = S;
     }
-    auto load = [&](const uint8_t *q) {
+    auto load = [&](int k, const uint8_t *q) {
         u32x4 d = ld16(q);
-        if constexpr (MASKED) d &= vmask;
+        if constexpr (MASKED) d &= vmask[k];
         return d;
     };
     const int fold_every = ELEM == 2 ? (int)(32767u / max(a.top, 1u)) : 128;
 
     int since_fold = 0;
-    auto process = [&](const u32x4 &s0, const u32x4 &s1, const u32x4 &s2, const u32x4 &s3) {
-        if constexpr (PACKED) {
-            acc.cycle(s0, s1, s2, s3);
-            if (++since_fold == fold_every) {
-                acc.fold();
-                since_fold = 0;
-            }
-        } else {
-            acc.frame32(s0, 1, 0);
-            acc.frame32(s1, 0, 1);
-            acc.frame32(s2, -1, 0);
-            acc.frame32(s3, 0, -1);
-        }
-        if constexpr (STATS) cycle_stats<ELEM>(s0, s1, s2, s3, a.top, st);
-    };
-    // One cycle (four frames, 4 x 16 B per lane) per iteration.  The four
+    // One cycle (four frames, 4 x TK x 16 B per lane) per iteration.  The
     // loads are kept together ahead of the arithmetic (left to itself the
     // compiler issued three, waited, then the fourth).  Measured on MI355X:
     // four frames in flight per wave stream faster than deeper software
     // pipelining with two register sets.
-    for (int64_t k = 0; k < my; ++k) {
-        const u32x4 s0 = load(p), s1 = load(p + fs), s2 = load(p + 2 * fs), s3 = load(p + 3 * fs);
+    for (int64_t c = 0; c < my; ++c) {
+        u32x4 s[4][TK];
+#pragma unroll
+        for (int k = 0; k < TK; ++k) {
+            s[0][k] = load(k, p[k]);
+            s[1][k] = load(k, p[k] + fs);
+            s[2][k] = load(k, p[k] + 2 * fs);
+            s[3][k] = load(k, p[k] + 3 * fs);
+        }
         __builtin_amdgcn_sched_barrier(0);
-        p += step;
-        process(s0, s1, s2, s3);
+#pragma unroll
+        for (int k = 0; k < TK; ++k) {
+            p[k] += step;
+            if constexpr (PACKED) {
+                acc[k].cycle(s[0][k], s[1][k], s[2][k], s[3][k]);
+            } else {
+                acc[k].frame32(s[0][k], 1, 0);
+                acc[k].frame32(s[1][k], 0, 1);
+                acc[k].frame32(s[2][k], -1, 0);
+                acc[k].frame32(s[3][k], 0, -1);
+            }
+        }
+        if constexpr (PACKED) {
+            if (++since_fold == fold_every) {
+#pragma unroll
+                for (int k = 0; k < TK; ++k) acc[k].fold();
+                since_fold = 0;
+            }
+        }
+        if constexpr (STATS) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) frame_stats_k<ELEM, TK>(s[j], a.top, st);
+            if (st.slot == kStatsSlots) st.flush();
+        }
     }
-    if constexpr (PACKED) acc.fold();
+    if constexpr (PACKED) {
+#pragma unroll
+        for (int k = 0; k < TK; ++k) acc[k].fold();
+    }
     // Partial cycle at the end of the stack: taken by the split next in turn.
     const int rem = (int)(a.n_frames & 3);
     if (rem && split == (int)(n_cyc_all % S)) {
-        const uint8_t *q = a.frames + y * a.rp_b + (int64_t)x0 * ELEM + 4 * n_cyc_all * fs;
         for (int j = 0; j < rem; ++j) {
-            const u32x4 s = load(q + j * fs);
-            acc.frame32(s, j == 0 ? 1 : (j == 2 ? -1 : 0), j == 1 ? 1 : 0);
-            if constexpr (STATS) frame_stats<ELEM>(s, a.top, st);
+            u32x4 sj[TK];
+#pragma unroll
+            for (int k = 0; k < TK; ++k) {
+                int64_t y;
+                int x0;
+                coords(k, y, x0);
+                const uint8_t *q = a.frames + y * a.rp_b + (int64_t)x0 * ELEM + (4 * n_cyc_all + j) * fs;
+                sj[k] = load(k, q);
+                acc[k].frame32(sj[k], j == 0 ? 1 : (j == 2 ? -1 : 0), j == 1 ? 1 : 0);
+            }
+            if constexpr (STATS) frame_stats_k<ELEM, TK>(sj, a.top, st);
         }
     }
     if constexpr (STATS) {
@@ -474,21 +521,26 @@ __device__ __forceinline__ void vec_body(const AccumArgs &a, int tile, int split
         stats_parity = st.parity;
     }
 
-    if (!valid) return;
-    int32_t *Ip = S > 1 ? a.part_iq + 2 * a.part_n * split + (y * a.W + x0 - a.part_p0) : a.I + y * a.W + x0;
-    int32_t *Qp = S > 1 ? Ip + a.part_n : a.Q + y * a.W + x0;
 #pragma unroll
-    for (int k = 0; k < kPx; ++k) {
-        int32_t oi, oq;
-        rotate_iq(a.rot, acc.I[k], acc.Q[k], oi, oq);
-        if (S > 1) {
-            Ip[k] = oi;
-            Qp[k] = oq;
-        } else {
-            const int32_t ni = a.overwrite ? oi : add_wrap(Ip[k], oi), nq = a.overwrite ? oq : add_wrap(Qp[k], oq);
-            Ip[k] = ni;
-            Qp[k] = nq;
-            if (a.amp) a.amp[y * a.W + x0 + k] = amp_exact(ni, nq);
+    for (int k = 0; k < TK; ++k) {
+        int64_t y;
+        int x0;
+        if (!coords(k, y, x0)) continue;
+        int32_t *Ip = S > 1 ? a.part_iq + 2 * a.part_n * split + (y * a.W + x0 - a.part_p0) : a.I + y * a.W + x0;
+        int32_t *Qp = S > 1 ? Ip + a.part_n : a.Q + y * a.W + x0;
+#pragma unroll
+        for (int i = 0; i < kPx; ++i) {
+            int32_t oi, oq;
+            rotate_iq(a.rot, acc[k].I[i], acc[k].Q[i], oi, oq);
+            if (S > 1) {
+                Ip[i] = oi;
+                Qp[i] = oq;
+            } else {
+                const int32_t ni = a.overwrite ? oi : add_wrap(Ip[i], oi), nq = a.overwrite ? oq : add_wrap(Qp[i], oq);
+                Ip[i] = ni;
+                Qp[i] = nq;
+                if (a.amp) a.amp[y * a.W + x0 + i] = amp_exact(ni, nq);
+            }
         }
     }
 }
@@ -510,8 +562,8 @@ __device__ __forceinline__ void tile_and_split(const AccumArgs &a, int b, int &t
     tile = a.n_full + (q / S) * kXcds + xcd;
 }
 
-template <int ELEM, bool STATS, bool PACKED>
-__global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
+template <int ELEM, bool STATS, bool PACKED, int TK>
+__global__ __launch_bounds__(kBlock, 2) void qld_accum_kernel(AccumArgs a) {
     clear_stats_once(a);
     const int64_t n_vec = (int64_t)(a.ncols / (16 / ELEM)) * a.H;
     uint32_t *lds = nullptr, *comb = nullptr;
@@ -528,9 +580,9 @@ __global__ __launch_bounds__(kBlock) void qld_accum_kernel(AccumArgs a) {
         int tile, split, S;
         tile_and_split(a, u, tile, split, S);
         if (tile >= a.n_tiles) continue;
-        if ((int64_t)(tile + 1) * kBlock <= n_vec)
-            vec_body<ELEM, STATS, PACKED, false>(a, tile, split, S, lds, comb, parity);
-        else vec_body<ELEM, STATS, PACKED, true>(a, tile, split, S, lds, comb, parity);
+        if ((int64_t)(tile + 1) * TK * kBlock <= n_vec)
+            vec_body<ELEM, STATS, PACKED, false, TK>(a, tile, split, S, lds, comb, parity);
+        else vec_body<ELEM, STATS, PACKED, true, TK>(a, tile, split, S, lds, comb, parity);
     }
 }
 
@@ -665,11 +717,23 @@ __global__ __launch_bounds__(256) void qld_amplitude_kernel(const int32_t *__res
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) amp[i] = amp_exact(I[i], Q[i]);
 }
 
+template <int ELEM, bool STATS, bool PACKED>
+hipError_t launch_vec_p(const AccumArgs &a, int grid, hipStream_t s) {
+    // Four tiles per unit only for 16-bit packed data (the other variants
+    // would not fit two waves per SIMD); the host chooses tk accordingly.
+    if constexpr (ELEM == 2 && PACKED)
+        if (a.tk == 4) {
+            hipLaunchKernelGGL((qld_accum_kernel<ELEM, STATS, PACKED, 4>), dim3(grid), dim3(kBlock), 0, s, a);
+            return hipGetLastError();
+        }
+    if (a.tk == 2) hipLaunchKernelGGL((qld_accum_kernel<ELEM, STATS, PACKED, 2>), dim3(grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((qld_accum_kernel<ELEM, STATS, PACKED, 1>), dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int ELEM, bool STATS>
 hipError_t launch_vec(const AccumArgs &a, bool packed, int grid, hipStream_t s) {
-    if (packed) hipLaunchKernelGGL((qld_accum_kernel<ELEM, STATS, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((qld_accum_kernel<ELEM, STATS, false>), dim3(grid), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    return packed ? launch_vec_p<ELEM, STATS, true>(a, grid, s) : launch_vec_p<ELEM, STATS, false>(a, grid, s);
 }
 
 template <int ELEM, bool STATS>
@@ -806,31 +870,44 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
         set_error("image too large");
         return QLD_E_SHAPE;
     }
+    // Wide tiles: with more 256-lane tiles than the persistent grid holds,
+    // each work-group unit takes 2 or 4 adjacent tiles, so that one round
+    // covers the image (or as much of it as 4 tiles per unit reach).
+    const int64_t G = accum_grid_cap();
+    // 16-bit partial sums hold at least two cycles for data of up to 14 bits.
+    const bool packed = eb == 1 || top <= 16383;
+    // Four tiles per unit only for packed 16-bit data (registers).
+    const int tk = vt <= G ? 1 : (vt <= 2 * G || eb == 1 || !packed ? 2 : 4);
+    const int64_t vw = ceil_div(vt, (int64_t)tk);          // wide tiles of the vector kernel
     av.x_begin = 0;
     av.ncols = vcols;
-    av.n_tiles = (int32_t)vt;
+    av.n_tiles = (int32_t)vw;
+    av.tk = tk;
     av.row_base = 0;
     as.x_begin = vcols;
     as.ncols = scols;
     as.n_tiles = (int32_t)st;
-    as.row_base = (int32_t)vt;
-    av.n_split = choose_split(vt + st, n_frames);
+    as.tk = 1;
+    as.row_base = (int32_t)vw;
+    // A frame split fills the grid when an image has fewer tiles than
+    // work-groups; wide tiles (tk > 1) keep as many bytes in flight as tk
+    // times as many work-groups would, so they are left unsplit.
+    av.n_split = tk == 1 ? choose_split(vw + st, n_frames) : 1;
     as.n_split = av.n_split;
-    // Tail of the persistent grid: with more tiles than work-groups and no
-    // scalar columns (the vector lanes then cover the pixels in flat order),
-    // the tiles past the last whole round are split over the frames so that
-    // round ends sooner; only their pixels take the partials' reduction.
-    // 2160 x 2160: 2279 tiles on 512 work-groups = 4 rounds + 231 tiles split
-    // 2 ways (4.5 rounds instead of 5).
+    // Tail of the persistent grid: with more wide tiles than work-groups and
+    // no scalar columns (the vector lanes then cover the pixels in flat
+    // order), the wide tiles past the last whole round are split over the
+    // frames so that round ends sooner; only their pixels take the partials'
+    // reduction.  2160 x 2160: 2279 tiles = 570 wide tiles of 4 on 512
+    // work-groups: one round, then 58 wide tiles split 8 ways.
     int64_t p_split = 0;                    // first pixel of the split tiles
     if (st == 0 && av.n_split == 1) {
-        const int64_t G = accum_grid_cap();
-        const int64_t full = (vt / G) * G, rest = vt - full;
+        const int64_t full = (vw / G) * G, rest = vw - full;
         const int64_t s2 = rest > 0 ? std::min<int64_t>(G / rest, std::max<int64_t>(1, (n_frames / 4) / 16)) : 1;
         if (full > 0 && s2 >= 2) {
             av.n_full = (int32_t)full;
             av.n_split = (int32_t)s2;
-            p_split = full * kBlock * lw;
+            p_split = full * tk * kBlock * lw;
         }
     }
     // With a frame split the splits store I/Q partials and
@@ -846,8 +923,8 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
     }
 
     const bool stats = frame_sum || frame_sat;
-    // Statistics partial rows: one per vector tile, one per scalar-kernel wave.
-    const int64_t n_rows = vt + st * kWavesPerBlock;
+    // Statistics partial rows: one per wide vector tile, one per scalar-kernel wave.
+    const int64_t n_rows = vw + st * kWavesPerBlock;
     const size_t stats_b = stats ? ((sizeof(uint32_t) * 2 * (size_t)n_rows * (size_t)n_frames + 255) / 256) * 256 : 0;
     av.part_p0 = as.part_p0 = p_split;
     av.part_n = as.part_n = npx - p_split;
@@ -872,9 +949,7 @@ qld_status accumulate_impl(const void *frames, const qld_frame_desc *d, int32_t 
         }
         if (split) av.part_iq = as.part_iq = reinterpret_cast<int32_t *>(ws + stats_b);
     }
-    // 16-bit partial sums hold at least two cycles for data of up to 14 bits.
-    const bool packed = eb == 1 || top <= 16383;
-    const int64_t uv = av.n_full + ceil_div(vt - av.n_full, kXcds) * kXcds * av.n_split;
+    const int64_t uv = av.n_full + ceil_div(vw - av.n_full, kXcds) * kXcds * av.n_split;
     const int64_t gs = ceil_div(st, kXcds) * kXcds * as.n_split;
     if (uv > 0x7fffffff || gs > 0x7fffffff) {
         set_error("grid too large");

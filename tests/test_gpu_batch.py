@@ -63,8 +63,8 @@ CASES = [
     (np.uint8, 33, 7, 31, 1, 1, 8, 0),
     (np.uint8, 2000, 8, 48, 16, 2, 8, 0),
     (np.uint8, 9, 13, 17, 0, 0, 8, 3),
-    # More tiles than work-groups with a frame-split tail: u8 (16 pixels per
-    # lane, 550 tiles), and u16 with padded rows (600 tiles).
+    # More tiles than work-groups, taken two per unit (wide tiles): u8 (16
+    # pixels per lane, 550 tiles), and u16 with padded rows (600 tiles).
     (np.uint8, 130, 1100, 2048, 0, 1, 8, 0),
     (np.uint16, 134, 600, 2048, 8, 3, 12, 0),
 ]
@@ -149,8 +149,8 @@ def test_full_range_16bit_and_overflow_edge():
 
 @pytest.mark.parametrize("T,H,W,bits,phase0", [(64, 17, 40, 12, 1), (4096, 16, 16, 12, 0), (9, 5, 1003, 16, 3),
                                                (1024, 64, 64, 12, 2),
-                                               # more pixel tiles than work-groups: 550 tiles, unsplit,
-                                               # two rounds of the persistent grid
+                                               # more pixel tiles than work-groups: 550 tiles, two
+                                               # per unit (275 wide tiles, one round, unsplit)
                                                (64, 1100, 1024, 12, 3),
                                                # 520 tiles plus a 4-column scalar tail, ragged
                                                # last cycle
@@ -158,9 +158,16 @@ def test_full_range_16bit_and_overflow_edge():
                                                # 300 tiles split in two: 608 units on 512
                                                # work-groups (some take two units)
                                                (256, 300, 2048, 12, 2),
-                                               # 600 tiles: one whole round of 512, the other 88
-                                               # split 4 ways (partials from row 512 on)
-                                               (262, 600, 2048, 12, 1)])
+                                               # 600 tiles, two per unit
+                                               (262, 600, 2048, 12, 1),
+                                               # 2048 tiles, four per unit: one round of 512
+                                               # wide tiles
+                                               (64, 2048, 2048, 12, 0),
+                                               # 2100 tiles, four per unit: one round of 512
+                                               # wide tiles, the other 13 split 2 ways over
+                                               # the frames (partials from row 2048 on),
+                                               # ragged last cycle
+                                               (130, 2100, 2048, 12, 1)])
 def test_lockin_image_overwrites_and_matches_accumulate(T, H, W, bits, phase0):
     """qld_lockin_image (one pass: I/Q, amplitude and statistics overwritten)
     on garbage-filled outputs equals clearing them, qld_accumulate and
@@ -195,13 +202,14 @@ def test_lockin_image_overwrites_and_matches_accumulate(T, H, W, bits, phase0):
 
 def test_statistics_over_odd_flush_counts_and_grid_rounds():
     """Per-frame statistics when each persistent-grid unit ends on an odd
-    number of statistics flushes (808 frames: 13 flushes of 64 frames per
-    unit) and work-groups take several units (520 tiles on 512 work-groups:
-    a whole round, then the 8-tile tail split over the frames): the sums
-    and counts stay exact across the units of a work-group."""
+    number of statistics flushes and work-groups take several units: 300
+    tiles split 2 ways over 808 frames make 608 units on 512 work-groups
+    (96 of them take two), each unit 404 frames, 7 flushes of up to 64
+    frames.  The sums and counts stay exact across the units of a
+    work-group."""
     need_gpu()
     rng = np.random.default_rng(808)
-    T, H, W, bits = 808, 1040, 1024, 12
+    T, H, W, bits = 808, 300, 2048, 12
     f = rng.integers(0, 1 << bits, size=(T, H, W), dtype=np.uint16)
     f[:, ::9, ::4] = (1 << bits) - 1
     say("statistics case", T, H, W)

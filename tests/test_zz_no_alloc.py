@@ -38,12 +38,13 @@ def both(frames, bits, phase0, stats=True):
 
 
 # Calls in this order share the scratch array; each is smaller than the one
-# before.  (dtype, T, H, W, phase0, bits): a split tail over more tiles than
-# work-groups (statistics and I/Q partials), a small image split over the
+# before.  (dtype, T, H, W, phase0, bits): a split tail past one round of
+# wide tiles (1050 tiles of 4096 8-bit pixels, 525 wide tiles of 2 on 512
+# work-groups: statistics and I/Q partials), a small image split over the
 # frames (I/Q partials from many splits), and a ragged image with a scalar
 # column tail (both kernels' statistics rows).
 SEQUENCE = [
-    (np.uint8, 130, 1100, 2048, 1, 8),
+    (np.uint8, 130, 2100, 2048, 1, 8),
     (np.uint16, 1029, 40, 64, 3, 12),
     (np.uint16, 67, 300, 257, 2, 12),
 ]
