@@ -87,6 +87,7 @@ struct StreamRec {
     size_t frame_bytes = 0;
     hipEvent_t pin_ev[kPinnedFrames] = {};   // last copy out of each pinned frame
     hipEvent_t direct_ev = nullptr;          // copy straight from a caller's page-locked frames
+    hipStream_t copy = nullptr;              // this stream's host-to-device copies
     bool pin_used[kPinnedFrames] = {};
     hipEvent_t slot_ev[kStageCycles] = {};
     uint64_t slot_tarr[kStageCycles] = {};
@@ -139,7 +140,7 @@ struct qld_server {
     int flags = 0;
     int device = 0;
     size_t in_use = 0;
-    hipStream_t copy = nullptr, compute = nullptr;
+    hipStream_t compute = nullptr;
 
     std::mutex mu;
     std::condition_variable cv_sched, cv_done, cv_complete;
@@ -210,6 +211,11 @@ void free_stream_mem(StreamRec *r) {
     for (auto &e : r->slot_ev)
         if (e) (void)hipEventDestroy(e), e = nullptr;
     if (r->direct_ev) (void)hipEventDestroy(r->direct_ev), r->direct_ev = nullptr;
+    if (r->copy) {
+        (void)hipStreamSynchronize(r->copy);
+        (void)hipStreamDestroy(r->copy);
+        r->copy = nullptr;
+    }
 }
 
 // Allocate the device/pinned memory of an admitted stream (mu held).
@@ -266,6 +272,9 @@ qld_status alloc_stream(qld_server *srv, StreamRec *r) {
     for (int i = 0; e == hipSuccess && i < kStageCycles; ++i)
         e = hipEventCreateWithFlags(&r->slot_ev[i], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r->direct_ev, hipEventDisableTiming);
+    // One copy stream per camera: a small camera's frames do not queue behind
+    // a large camera's (default priority, like every stream here).
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&r->copy, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_stream_mem(r);
@@ -546,10 +555,8 @@ extern "C" qld_status qld_server_create(size_t hbm_budget_bytes, int32_t out_slo
     s->out_slots = out_slots;
     s->flags = flags;
     (void)hipGetDevice(&s->device);
-    qld_status st = check_hip(hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking), "copy stream");
-    if (st == QLD_OK) st = check_hip(hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking), "compute stream");
+    const qld_status st = check_hip(hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking), "compute stream");
     if (st != QLD_OK) {
-        if (s->copy) (void)hipStreamDestroy(s->copy);
         delete s;
         return st;
     }
@@ -711,8 +718,8 @@ bool page_locked(const void *p) {
 }
 
 // Copies n frames (phases phase .. phase + n - 1 of the stream's next cycle)
-// to the stream's device staging with one host-to-device copy on the copy
-// stream; the cycle goes to the scheduler once its last frame is in.  Frames
+// to the stream's device staging with one host-to-device copy on the
+// stream's own copy stream; the cycle goes to the scheduler once its last frame is in.  Frames
 // in pageable memory are first copied into the stream's pinned staging (so
 // the caller may reuse its buffer at once); frames already in page-locked
 // memory are copied straight from the caller's buffer, and the call waits for
@@ -741,10 +748,14 @@ qld_status stage_frames(qld_server *s, StreamRec *r, std::unique_lock<std::mutex
     hipError_t e = hipSuccess;
     if (direct) {
         e = hipMemcpy2DAsync(dst, (size_t)r->rp_b, host, row, row, (size_t)n * r->d.H, hipMemcpyHostToDevice,
-                             s->copy);
-        if (e == hipSuccess && phase + n == 4) e = hipEventRecord(r->slot_ev[slot], s->copy);
-        if (e == hipSuccess) e = hipEventRecord(r->direct_ev, s->copy);
-        if (e == hipSuccess) e = hipEventSynchronize(r->direct_ev);   // the caller's buffer is free again
+                             r->copy);
+        if (e == hipSuccess && phase + n == 4) e = hipEventRecord(r->slot_ev[slot], r->copy);
+        if (e == hipSuccess) e = hipEventRecord(r->direct_ev, r->copy);
+        // The caller's buffer is free again once the copy is done.  Waiting
+        // before the cycle is queued also keeps a cycle whose copy is still in
+        // flight out of the next batched launch, which would hold every other
+        // stream's image in that launch until this copy lands.
+        if (e == hipSuccess) e = hipEventSynchronize(r->direct_ev);
     } else {
         for (int i = 0; i < n && e == hipSuccess; ++i)
             if (used[i]) e = hipEventSynchronize(pev[i]);   // the pinned frame's previous copy is done
@@ -753,10 +764,10 @@ qld_status stage_frames(qld_server *s, StreamRec *r, std::unique_lock<std::mutex
             // The staged frames of a cycle are consecutive [H][Wp] planes, so n
             // frames are one copy of n * H rows.
             e = hipMemcpy2DAsync(dst, (size_t)r->rp_b, pin, row, row, (size_t)n * r->d.H, hipMemcpyHostToDevice,
-                                 s->copy);
+                                 r->copy);
         }
-        for (int i = 0; i < n && e == hipSuccess; ++i) e = hipEventRecord(pev[i], s->copy);
-        if (e == hipSuccess && phase + n == 4) e = hipEventRecord(r->slot_ev[slot], s->copy);
+        for (int i = 0; i < n && e == hipSuccess; ++i) e = hipEventRecord(pev[i], r->copy);
+        if (e == hipSuccess && phase + n == 4) e = hipEventRecord(r->slot_ev[slot], r->copy);
     }
 
     lk.lock();
@@ -955,7 +966,7 @@ extern "C" qld_status qld_stream_close(qld_server *s, int32_t stream_id) {
                                      [&](const qld_result &q) { return q.stream_id == stream_id; }),
                      s->results.end());
     lk.unlock();
-    (void)hipStreamSynchronize(s->copy);
+    if (r->copy) (void)hipStreamSynchronize(r->copy);
     lk.lock();
     free_stream_mem(r);
     s->in_use -= r->bytes;
@@ -984,13 +995,11 @@ extern "C" qld_status qld_server_destroy(qld_server *s) {
     if (s->sched.joinable()) s->sched.join();
     if (s->complete.joinable()) s->complete.join();
     (void)hipStreamSynchronize(s->compute);
-    (void)hipStreamSynchronize(s->copy);
-    for (auto &kv : s->streams) free_stream_mem(kv.second.get());
+    for (auto &kv : s->streams) free_stream_mem(kv.second.get());   // each stream's copies finish first
     for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
     for (auto &f : s->inflight)
         if (f.ev) (void)hipEventDestroy(f.ev);
     (void)hipStreamDestroy(s->compute);
-    (void)hipStreamDestroy(s->copy);
     delete s;
     return QLD_OK;
 }
