@@ -115,7 +115,12 @@ __device__ __forceinline__ bool tile_of(int H, int W, int &b, int &y, int &x0) {
 // MODE 0 (forward):        out = bf16(relu(sum_tap in[p + tap] W[tap] + bias))
 // MODE 1 (input gradient): out = bf16((sum_tap in[p - tap] W^T[tap]) * (act[p] > 0))
 // MODE 2 (output layer):   y   = sum_tap in[p + tap] . w4[tap] + b4 (fp32; the
-//                          weights form one 16-column block with column 0 used)
+//                          weights form one 16-column block with column 0 used);
+//                          with pool_part, also each wave's channel sums of its
+//                          row of the input (the gate's pooling, read from the
+//                          LDS tile instead of a second pass over a3):
+//                          pool_part[tile][wave][32], 64 pixels each, zeros
+//                          past the image's edge included.
 // ---------------------------------------------------------------------------
 constexpr int kTileItems = (kRows + 2) * (kCols + 2) * 4;   // 16-byte items of an input tile
 constexpr int kTilePer = (kTileItems + 255) / 256;          // per lane
@@ -123,7 +128,8 @@ constexpr int kTilePer = (kTileItems + 255) / 256;          // per lane
 template <int MODE>
 __global__ __launch_bounds__(256, 2) void conv_tile_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
                                                         const float *__restrict__ bias, const __bf16 *__restrict__ act,
-                                                        void *__restrict__ out, int H, int W, int n_tiles) {
+                                                        void *__restrict__ out, int H, int W, int n_tiles,
+                                                        float *__restrict__ pool_part) {
     constexpr int NCB = MODE == 2 ? 1 : 2;          // 16-channel output blocks
     __shared__ __align__(16) __bf16 tile[kRows + 2][kCols + 2][32];
     const int tx = (W + kCols - 1) / kCols, ty = (H + kRows - 1) / kRows;
@@ -165,6 +171,31 @@ __global__ __launch_bounds__(256, 2) void conv_tile_kernel(const __bf16 *__restr
         }
         __syncthreads();
         if (tl + (int)gridDim.x < n_tiles) fetch(tl + gridDim.x);
+        if constexpr (MODE == 2) {
+            if (pool_part) {
+                // Lane (channel pair c2, quarter q): channels 2 c2, 2 c2 + 1 over
+                // pixels 16 q .. 16 q + 15 of the wave's row (one 4-byte LDS read
+                // per pixel), in order; the quarters added pairwise, one store
+                // per channel.
+                const int c2 = lane & 15, q = lane >> 4;
+                float p0 = 0.f, p1 = 0.f;
+#pragma unroll 8
+                for (int p = 0; p < 16; ++p) {
+                    const uint32_t u = *reinterpret_cast<const uint32_t *>(&tile[wave + 1][1 + 16 * q + p][2 * c2]);
+                    p0 += __uint_as_float(u << 16);
+                    p1 += __uint_as_float(u & 0xffff0000u);
+                }
+                p0 += __shfl_xor(p0, 16);
+                p1 += __shfl_xor(p1, 16);
+                p0 += __shfl_xor(p0, 32);
+                p1 += __shfl_xor(p1, 32);
+                if (q == 0) {
+                    float *dst = pool_part + ((int64_t)tl * kRows + wave) * 32 + 2 * c2;
+                    dst[0] = p0;
+                    dst[1] = p1;
+                }
+            }
+        }
         // MODE 1: the ReLU mask of this wave's outputs, loaded ahead of the products.
         bf16x8 am[4];
         if constexpr (MODE == 1) {
@@ -782,34 +813,27 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float *__restric
 }
 
 // Gate: pool[b][c] = mean_p a3[b][p][c]; gate[b] = pool[b] . Wg + bg.
-// Stage 1: each work-group sums a contiguous chunk of a tile's pixels (a lane
-// reads 8 channels of a pixel with one 16-byte load; 64 pixels per step) into
-// 32 per-chunk sums; stage 2 adds a tile's chunks in order, so the pooled
-// values do not depend on timing.
-int pool_chunks(int B) { return (int)std::max<int64_t>(64, std::min<int64_t>(1024, ceil_div(4096, B))); }
-
-__global__ __launch_bounds__(256) void pool_kernel(const __bf16 *__restrict__ a3, int64_t npx, int chunks,
-                                                   float *__restrict__ part) {
-    __shared__ float red[64][33];
-    const int b = blockIdx.y, ch = blockIdx.x;
-    const int g = threadIdx.x & 3, r = threadIdx.x >> 2;
-    const int64_t per = ceil_div(npx, (int64_t)chunks);
-    const int64_t p0 = ch * per, p1 = std::min<int64_t>(npx, p0 + per);
-    const bf16x8 *src = reinterpret_cast<const bf16x8 *>(a3 + (int64_t)b * npx * 32) + g;
-    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 2
-    for (int64_t p = p0 + r; p < p1; p += 64) {
-        const bf16x8 v = src[p * 4];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) red[r][g * 8 + i] = acc[i];
+// The output layer's kernel leaves one row of 32 channel sums per tile row
+// (a few thousand per image); gate_fwd_kernel adds an image's rows in a fixed
+// order, so the pooled values do not depend on timing.
+// First stage of the gate's pooling: work-group (s, b) adds rows s*64 ..
+// s*64 + 63 of image b's rows[b][rows][32] in order (4 groups of 16 rows,
+// combined in order) into slab[b][s][32].
+__global__ __launch_bounds__(256) void pool_rows_kernel(const float *__restrict__ rows, int n_rows,
+                                                        float *__restrict__ slab) {
+    __shared__ float red[8][32];
+    const int s = blockIdx.x, b = blockIdx.y, c = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int r0 = s * 64 + g * 8, r1 = min(n_rows, r0 + 8);
+    const float *src = rows + (int64_t)b * n_rows * 32 + c;
+    float v = 0.f;
+    for (int r = r0; r < r1; ++r) v += src[(int64_t)r * 32];
+    red[g][c] = v;
     __syncthreads();
     if (threadIdx.x < 32) {
         float t = 0.f;
-        for (int k = 0; k < 64; ++k) t += red[k][threadIdx.x];
-        part[((int64_t)b * chunks + ch) * 32 + threadIdx.x] = t;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += red[k][c];
+        slab[((int64_t)b * gridDim.x + s) * 32 + c] = t;
     }
 }
 
@@ -1032,8 +1056,10 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     d->W = W;
     d->max_batch = max_batch;
     const size_t npx = (size_t)max_batch * H * W;
+    // Largest user of the partials: the 32 -> 32 weight gradient, or the
+    // gate's row sums (one row of 32 channel sums per tile row).
     d->part_floats = std::max<int64_t>((int64_t)kW32Blocks * kW32Row,
-                                       ((int64_t)max_batch * 64 + 4096 + max_batch) * 32);   // >= B * pool_chunks(B) * 32
+                                       (int64_t)conv_grid(max_batch, H, W) * kRows * 32);
     qld_status st = QLD_OK;
     if (st == QLD_OK) st = dalloc(d, &d->params, N_ALL);
     if (st == QLD_OK) st = dalloc(d, &d->grads, N_ALL);
@@ -1177,15 +1203,17 @@ extern "C" qld_status qld_denoiser_forward(qld_denoiser *d, const float *x, int3
     hipLaunchKernelGGL(conv1_kernel, dim3(g), dim3(256), 0, s, d->x0, d->w1f, d->params + OFF_B1, d->a1, H, W);
     const int gp = conv_persistent_grid(g);
     hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(gp), dim3(256), 0, s, d->a1, d->w2f, d->params + OFF_B2, nullptr,
-                       d->a2, H, W, g);
+                       d->a2, H, W, g, nullptr);
     hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(gp), dim3(256), 0, s, d->a2, d->w3f, d->params + OFF_B3, nullptr,
-                       d->a3, H, W, g);
+                       d->a3, H, W, g, nullptr);
+    // The output layer also leaves the gate's per-row channel sums of a3.
     hipLaunchKernelGGL((conv_tile_kernel<2>), dim3(gp), dim3(256), 0, s, d->a3, d->w4f, d->params + OFF_B4, nullptr,
-                       d->y, H, W, g);
+                       d->y, H, W, g, d->part);
     if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
-    const int chunks = pool_chunks(B);
-    hipLaunchKernelGGL(pool_kernel, dim3(chunks, B), dim3(256), 0, s, d->a3, (int64_t)H * W, chunks, d->part);
-    hipLaunchKernelGGL(gate_fwd_kernel, dim3(B), dim3(256), 0, s, d->part, chunks, (int64_t)H * W, d->params, d->pool,
+    // Per image: its tiles' row sums in tile order, added in slabs of 64, then the slabs.
+    const int rows = (g / B) * kRows, slabs = (int)ceil_div(rows, 64);
+    hipLaunchKernelGGL(pool_rows_kernel, dim3(slabs, B), dim3(256), 0, s, d->part, rows, d->part2);
+    hipLaunchKernelGGL(gate_fwd_kernel, dim3(B), dim3(256), 0, s, d->part2, slabs, (int64_t)H * W, d->params, d->pool,
                        d->gate);
     QLD_TRY(check_hip(hipGetLastError(), "forward launch"));
     if (y_out) QLD_TRY(check_hip(hipMemcpyAsync(y_out, d->y, npx * sizeof(float), hipMemcpyDeviceToDevice, s), "y copy"));
@@ -1213,11 +1241,11 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
     QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));   // and b3
     hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(gp), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W,
-                       g);
+                       g, nullptr);
     // Layer 2: dW2 from (a1, dz2); dz1 = bf16(conv^T(dz2, W2) * (a1 > 0)).
     QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));   // and b2
     hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(gp), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W,
-                       g);
+                       g, nullptr);
     // Layer 1: dW1 from (x0, dz1).
     QLD_TRY(dw1(d, B, s));   // and b1
     // Gate (its own loss; its gradient reaches only Wg, bg).
