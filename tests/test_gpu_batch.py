@@ -67,6 +67,14 @@ CASES = [
     # pixels per lane, 550 tiles), and u16 with padded rows (600 tiles).
     (np.uint8, 130, 1100, 2048, 0, 1, 8, 0),
     (np.uint16, 134, 600, 2048, 8, 3, 12, 0),
+    # 16-bit data without the packed partials (bits 16): two tiles per unit
+    # (600 tiles), then 1100 tiles = 550 wide tiles, one round of 512 and the
+    # other 38 split two ways over the frames.
+    (np.uint16, 40, 600, 2048, 0, 2, 16, 0),
+    (np.uint16, 130, 1100, 2048, 0, 1, 16, 0),
+    # u8, 1050 tiles two per unit: one round of 512 wide tiles, the other 13
+    # split two ways over the frames, ragged last cycle.
+    (np.uint8, 130, 2100, 2048, 0, 3, 8, 0),
 ]
 
 
