@@ -633,35 +633,82 @@ __global__ __launch_bounds__(256) void dw1_kernel(const __bf16 *__restrict__ x, 
 }
 
 // Output layer (32 -> 1) backward in one pass over a3 and dy:
-//   dW4[tap][ci] = sum_px a3[px + tap][ci] dy[px],  db4 = sum_px dy[px]   (VALU)
+//   dW4[tap][ci] = sum_px a3[px + tap][ci] dy[px],  db4 = sum_px dy[px]
 //   dz3[q][c] = bf16((sum_tap dy[q - tap] w4[tap][c]) * (a3[q][c] > 0))
-// Work units are vertical runs of `rows` rows of one 64-pixel strip, walked
-// top to bottom like dw32_kernel: a three-slot ring holds rows y-1, y, y+1
-// of a3 (transposed, aT[slot][ci][px]) and of dy (pixels x0-1 .. x0+64), and
-// the next row of each is in flight while row y is worked.  For row y,
-// thread (ci, r, half) (t < 192) slides along its 32 pixels of row y-1+r and
-// accumulates the three taps of that row against dy of row y; thread 192
-// sums dy of row y for db4; and every lane (pixel t / 4, channel group t % 4)
-// forms its 8 channels of dz3 from the ring's dy and its own ReLU mask.  Each
-// work-group writes partial rows part[2 block + half][289] (dW4 in canonical
-// order, then db4 in row 2 block), summed later in a fixed order.
+// Both contractions run on the matrix cores in bf16.  dy is split exactly
+// into three bf16 parts, dy = hi + mid + lo (its top 8 significant bits, the
+// next 8, the last 8), so every product is exact and only the fp32
+// accumulation rounds.  Work units are vertical runs of `rows` rows of one
+// 64-pixel strip, walked top to bottom like dw32_kernel: a three-slot ring
+// holds rows y-1, y, y+1 of a3 (transposed, aT[slot][ci][px]) and of dy (fp32
+// dyS[slot][px] and its parts dyP[slot][part][px], in aT's column order), and
+// two rows of each are in flight while row y is worked.  For row y:
+//  * dW4: wave w takes channel block w & 1 (M = 16 channels) and pixels
+//    32 (w >> 1) .. +32 of the strip (K); N = the three parts of dy at those
+//    pixels (one 16-byte read), A = a3 of row y-1+r at the pixels shifted by
+//    the tap's dx (16-bit funnel shifts of aligned chunks, the strip's halo
+//    columns included); one product per (r, dx), the parts added at the end.
+//  * dz3: wave w takes pixels 16w .. +16 of the strip (M), the channels in
+//    two blocks (N) and K = 16 with lane group kb holding dy row y+1-kb at
+//    the three column offsets (taps 3 kb .. 3 kb + 2; kb = 3 empty); one
+//    16x16x16 product per part.  The ReLU mask comes from a3 in the ring, and
+//    the results pass through a per-wave LDS tile so each lane stores 16
+//    contiguous bytes of a pixel.
+//  * db4: the lanes of wave 0 add dy of row y, one pixel each.
+// Each work-group writes partial rows part[2 block + half][289] (dW4 in
+// canonical order, then db4 in row 2 block), summed later in a fixed order.
 constexpr int kOutRow = 289;
+constexpr int kStgRow = 40;    // bf16 per row of the per-wave dz3 tile (32 channels + 8 pad)
 
-__global__ __launch_bounds__(256) void out_grad_kernel(const __bf16 *__restrict__ a, const float *__restrict__ dy,
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16k16(const s16x4 &a, const s16x4 &b, const f32x4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// x = hi + mid + lo exactly, each part a bf16 value (returned as its bits):
+// hi is x cut to its top 16 bits, mid the rest x - hi (exact) cut the same
+// way, lo = x - hi - mid (exact, at most 8 significant bits).
+__device__ __forceinline__ void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
+    const uint32_t xb = __float_as_uint(x);
+    const float r1 = x - __uint_as_float(xb & 0xffff0000u);
+    const uint32_t rb = __float_as_uint(r1);
+    const float lo = r1 - __uint_as_float(rb & 0xffff0000u);
+    h = (uint16_t)(xb >> 16);
+    m = (uint16_t)(rb >> 16);
+    l = (uint16_t)(__float_as_uint(lo) >> 16);
+}
+
+#ifndef QLD_OUT_GRAD_BLOCKS_PER_CU
+#define QLD_OUT_GRAD_BLOCKS_PER_CU 4
+#endif
+__global__ __launch_bounds__(256, QLD_OUT_GRAD_BLOCKS_PER_CU) void out_grad_kernel(const __bf16 *__restrict__ a, const float *__restrict__ dy,
                                                        const __bf16 *__restrict__ w4, int B, int H, int W, int rows,
                                                        __bf16 *__restrict__ dz, float *__restrict__ part) {
     __shared__ __align__(16) __bf16 aT[3][32][kAStride];
-    __shared__ __align__(16) float dyS[3][72];   // pixels x0-1 .. x0+64 at 3 .. 68 (x0 16-byte aligned)
-    const int t = threadIdx.x;
-    const int ci = t & 31, q6 = t >> 5, r = q6 % 3, half = q6 / 3;   // q6 < 6 for t < 192
-    const int pl = t >> 2, cg = t & 3;                                 // dz3 lane: pixel, channel group
+    __shared__ __align__(16) uint16_t dyP[4][3][kAStride];   // slot 3: zeros
+    __shared__ __align__(16) float dyS[3][72];               // pixels x0-1 .. x0+64 at 3 .. 68
+    __shared__ __align__(16) __bf16 stg[4][16][kStgRow];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
+    const int cib = wave & 1, kk = wave >> 1;
     const int segs_x = (W + kSegPx - 1) / kSegPx, runs_y = (H + rows - 1) / rows;
     const int64_t n_units = (int64_t)B * segs_x * runs_y;
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, bacc = 0.f;
     const bf16x8 zero = zero8();
-    bf16x8 wv[9];                                 // w4[tap][8 cg .. +8]
+    for (int i = t; i < 3 * kAStride; i += 256) dyP[3][i / kAStride][i % kAStride] = 0;
+    // dz3's B operand: lane (channel n = m, kb) holds w4[3 kb + i][16 cb + m]
+    // for i < 3 and kb < 3 (K slot 4 kb + i), zero elsewhere.
+    s16x4 bw[2];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) wv[k] = *reinterpret_cast<const bf16x8 *>(w4 + k * 32 + cg * 8);
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            bw[cb][i] = kb < 3 && i < 3 ? __builtin_bit_cast(short, w4[(3 * kb + i) * 32 + 16 * cb + m]) : (short)0;
+    f32x4 acc[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[r][d] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
     // Register buffers by parity of the distance from the unit's first row
     // (as in dw32_kernel): two rows of a3 and dy in flight while a row is worked.
     struct Buf {
@@ -690,64 +737,78 @@ __global__ __launch_bounds__(256) void out_grad_kernel(const __bf16 *__restrict_
                 for (int e = 0; e < 8; ++e) aT[slot][g * 8 + e][px + 7] = bf.va[i][e];
             }
         }
-        if (t < 66) dyS[slot][t + 3] = bf.vdy;
+        if (t < 66) {
+            dyS[slot][t + 3] = bf.vdy;
+            uint16_t h, md, l;
+            split3(bf.vdy, h, md, l);
+            dyP[slot][0][t + 7] = h;
+            dyP[slot][1][t + 7] = md;
+            dyP[slot][2][t + 7] = l;
+        }
     };
     auto work = [&](int64_t img, int x0, int y) {
-        const int x = x0 + pl;
-        const int64_t o = ((img + y) * W + x) * 32 + cg * 8;
-        const bf16x8 mask = x < W ? *reinterpret_cast<const bf16x8 *>(a + o) : zero;
-        const float *dyc = dyS[ring_slot(y)];
-        if (t < 192) {
-            // Pixels p0-1 .. p0+32 of row y-1+r (aT columns p0+7 .. p0+40)
-            // and dy of pixels p0 .. p0+31, read in 16-byte pieces.
-            const __bf16 *rp = &aT[ring_slot(y - 1 + r)][ci][0];
-            const int p0 = half * 32;
-            float av[34], gv[32];
-            {
-                const bf16x8 c0 = *reinterpret_cast<const bf16x8 *>(rp + p0);
-                av[0] = (float)c0[7];
+        // dW4: B = the parts of dy (row y) at this lane's 8 pixels.
+        const int col0 = 32 * kk + 8 * kb + 8;                  // aT / dyP column of pixel x0 + 32 kk + 8 kb
+        const uint16_t *bp = m < 3 ? &dyP[ring_slot(y)][m][col0] : &dyP[3][0][col0];
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const bf16x8 ck = *reinterpret_cast<const bf16x8 *>(rp + p0 + 8 + 8 * k);
+        for (int r = 0; r < 3; ++r) {
+            const __bf16 *rp = &aT[ring_slot(y - 1 + r)][16 * cib + m][0];
+            const u32x4w pv = *reinterpret_cast<const u32x4w *>(rp + col0 - 8);
+            const u32x4w c = *reinterpret_cast<const u32x4w *>(rp + col0);
+            const u32x4w nx = *reinterpret_cast<const u32x4w *>(rp + col0 + 8);
+            u32x4w lft, rgt;                                     // a3 at the pixels shifted by -1 / +1
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) av[1 + 8 * k + e] = (float)ck[e];
-                }
-                const bf16x8 c5 = *reinterpret_cast<const bf16x8 *>(rp + p0 + 40);
-                av[33] = (float)c5[0];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const f32x4 gk = *reinterpret_cast<const f32x4 *>(dyc + 4 + p0 + 4 * k);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) gv[4 * k + e] = gk[e];
-                }
+            for (int k = 0; k < 4; ++k) {
+                lft[k] = __builtin_amdgcn_alignbit(c[k], k ? c[k - 1] : pv[3], 16);
+                rgt[k] = __builtin_amdgcn_alignbit(k < 3 ? c[k + 1] : nx[0], c[k], 16);
             }
+            acc[r][0] = mfma16(__builtin_bit_cast(bf16x8, lft), bv, acc[r][0]);
+            acc[r][1] = mfma16(__builtin_bit_cast(bf16x8, c), bv, acc[r][1]);
+            acc[r][2] = mfma16(__builtin_bit_cast(bf16x8, rgt), bv, acc[r][2]);
+        }
+        // db4: pixel x0 + lane of row y.
+        if (wave == 0) bacc += dyS[ring_slot(y)][lane + 4];
+        // dz3 of pixel x0 + 16 wave + m: K slot 4 kb + i holds the parts of dy
+        // at (y + 1 - kb, x + 1 - i), i < 3.
+        s16x4 ap[3];
+        {
+            const int sl = kb < 3 ? ring_slot(y + 1 - kb) : 3;
+            const int cq = 16 * wave + m + 9;                    // dyP column of pixel x + 1
 #pragma unroll
-            for (int px = 0; px < 32; ++px) {
-                acc0 = fmaf(av[px], gv[px], acc0);
-                acc1 = fmaf(av[px + 1], gv[px], acc1);
-                acc2 = fmaf(av[px + 2], gv[px], acc2);
+            for (int s = 0; s < 3; ++s) {
+                const uint16_t *rp = &dyP[sl][s][cq];
+                ap[s][0] = (short)rp[0];
+                ap[s][1] = (short)rp[-1];
+                ap[s][2] = (short)rp[-2];
+                ap[s][3] = 0;
             }
-        } else if (t == 192) {
-            float sb = 0.f;
-            for (int px = 0; px < kSegPx; ++px) sb += dyc[px + 4];
-            bacc += sb;
         }
-        // dz3 of (y, x): tap (dy_t, dx_t) takes dy at (y - dy_t, x - dx_t).
-        float dacc[8];
+        f32x4 dv[2];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) dacc[c] = 0.f;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const float g = dyS[ring_slot(y - tap_dy(k))][pl + 4 - tap_dx(k)];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) dacc[c] = fmaf(g, (float)wv[k][c], dacc[c]);
+        for (int cb = 0; cb < 2; ++cb) {
+            dv[cb] = mfma16k16(ap[0], bw[cb], f32x4{0.f, 0.f, 0.f, 0.f});
+            dv[cb] = mfma16k16(ap[1], bw[cb], dv[cb]);
+            dv[cb] = mfma16k16(ap[2], bw[cb], dv[cb]);
         }
-        if (x < W) {
-            bf16x8 ov;
+        // Lane (channel m, kb) holds pixels 16 wave + 4 kb + i of channels m
+        // and 16 + m: mask them with a3 > 0, round to bf16 into the wave's tile.
 #pragma unroll
-            for (int c = 0; c < 8; ++c) ov[c] = (__bf16)((float)mask[c] > 0.f ? dacc[c] : 0.f);
-            *reinterpret_cast<bf16x8 *>(dz + o) = ov;
+        for (int cb = 0; cb < 2; ++cb) {
+            const uint32_t *mp =
+                reinterpret_cast<const uint32_t *>(&aT[ring_slot(y)][16 * cb + m][16 * wave + 4 * kb + 8]);
+            const uint32_t mk[2] = {mp[0], mp[1]};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t mb = (mk[i >> 1] >> (16 * (i & 1))) & 0xffffu;
+                const bool pos = (mb & 0x8000u) == 0 && mb != 0;   // bf16 > 0 (a3 is never NaN)
+                stg[wave][4 * kb + i][16 * cb + m] = (__bf16)(pos ? dv[cb][i] : 0.f);
+            }
         }
+        const int px = lane >> 2, g = lane & 3;
+        const int x = x0 + 16 * wave + px;
+        const bf16x8 ov = *reinterpret_cast<const bf16x8 *>(&stg[wave][px][8 * g]);
+        if (x < W) *reinterpret_cast<bf16x8 *>(dz + ((img + y) * W + x) * 32 + 8 * g) = ov;
     };
     auto step = [&](Buf &even, Buf &odd, int64_t img, int x0, int y, int y_end) {
         __syncthreads();                            // readers of row y-2's slot are done
@@ -773,14 +834,27 @@ __global__ __launch_bounds__(256) void out_grad_kernel(const __bf16 *__restrict_
             if (y + 1 < y_end) step(Q, P, img, x0, y + 1, y_end);
         }
     }
-    if (t < 192) {
-        float *pb = part + ((int64_t)blockIdx.x * 2 + half) * kOutRow;
-        pb[(3 * r + 0) * 32 + ci] = acc0;
-        pb[(3 * r + 1) * 32 + ci] = acc1;
-        pb[(3 * r + 2) * 32 + ci] = acc2;
-    } else if (t == 192) {
-        part[(int64_t)blockIdx.x * 2 * kOutRow + 288] = bacc;
-        part[((int64_t)blockIdx.x * 2 + 1) * kOutRow + 288] = 0.f;
+    // Add the three parts (D columns 0, 1, 2) in order and write the
+    // partial row of this wave's pixel half: lane (0, kb) holds channels
+    // 16 cib + 4 kb + i.
+    float *pb = part + ((int64_t)blockIdx.x * 2 + kk) * kOutRow;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc[r][d][i];
+                const float s = (v + __shfl_down(v, 1)) + __shfl_down(v, 2);
+                if (m == 0) pb[(3 * r + d) * 32 + 16 * cib + 4 * kb + i] = s;
+            }
+    if (wave == 0) {
+        float s = bacc;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) pb[288] = s;
+    } else if (wave == 2 && lane == 0) {
+        pb[288] = 0.f;
     }
 }
 
@@ -961,8 +1035,9 @@ int dw32_rows(int B, int H, int W, int blocks = kW32Blocks) {
     return (int)std::min<int64_t>(H, std::max<int64_t>(4, want));
 }
 
-// out_grad_kernel: two work-groups per CU are resident (189 VGPRs), one unit each.
-int out_grad_blocks() { return std::max(8, 2 * device_cu_count() / 8 * 8); }
+// out_grad_kernel: QLD_OUT_GRAD_BLOCKS_PER_CU work-groups per CU (its launch
+// bound keeps that many resident), one unit each.
+int out_grad_blocks() { return std::max(8, QLD_OUT_GRAD_BLOCKS_PER_CU * device_cu_count() / 8 * 8); }
 constexpr int kLossBlocks = 256;
 
 template <typename T>
