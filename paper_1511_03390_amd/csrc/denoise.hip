@@ -125,8 +125,13 @@ __device__ __forceinline__ bool tile_of(int H, int W, int &b, int &y, int &x0) {
 constexpr int kTileItems = (kRows + 2) * (kCols + 2) * 4;   // 16-byte items of an input tile
 constexpr int kTilePer = (kTileItems + 255) / 256;          // per lane
 
+// Work-groups per CU of the output layer's persistent grid (it needs fewer
+// registers than the 32-channel layers, so more groups fit).
+#ifndef QLD_OUT_LAYER_GROUPS_PER_CU
+#define QLD_OUT_LAYER_GROUPS_PER_CU 3
+#endif
 template <int MODE>
-__global__ __launch_bounds__(256, 2) void conv_tile_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
+__global__ __launch_bounds__(256, MODE == 2 ? QLD_OUT_LAYER_GROUPS_PER_CU : 2) void conv_tile_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
                                                         const float *__restrict__ bias, const __bf16 *__restrict__ act,
                                                         void *__restrict__ out, int H, int W, int n_tiles,
                                                         float *__restrict__ pool_part) {
@@ -1060,8 +1065,8 @@ int conv_grid(int B, int H, int W) {
 // Persistent grid of conv_tile_kernel: at most kConvGroupsPerCU work-groups
 // per CU (a multiple of 8), looping over the tiles.
 constexpr int kConvGroupsPerCU = 2;
-int conv_persistent_grid(int n_tiles) {
-    const int64_t cap = std::max<int64_t>(8, (int64_t)kConvGroupsPerCU * device_cu_count() / 8 * 8);
+int conv_persistent_grid(int n_tiles, int per_cu = kConvGroupsPerCU) {
+    const int64_t cap = std::max<int64_t>(8, (int64_t)per_cu * device_cu_count() / 8 * 8);
     return (int)std::min<int64_t>(n_tiles, cap);
 }
 
@@ -1282,8 +1287,8 @@ extern "C" qld_status qld_denoiser_forward(qld_denoiser *d, const float *x, int3
     hipLaunchKernelGGL((conv_tile_kernel<0>), dim3(gp), dim3(256), 0, s, d->a2, d->w3f, d->params + OFF_B3, nullptr,
                        d->a3, H, W, g, nullptr);
     // The output layer also leaves the gate's per-row channel sums of a3.
-    hipLaunchKernelGGL((conv_tile_kernel<2>), dim3(gp), dim3(256), 0, s, d->a3, d->w4f, d->params + OFF_B4, nullptr,
-                       d->y, H, W, g, d->part);
+    hipLaunchKernelGGL((conv_tile_kernel<2>), dim3(conv_persistent_grid(g, QLD_OUT_LAYER_GROUPS_PER_CU)), dim3(256), 0,
+                       s, d->a3, d->w4f, d->params + OFF_B4, nullptr, d->y, H, W, g, d->part);
     if (ev1) QLD_TRY(check_hip(hipEventRecord(ev1, s), "timer stop"));
     // Per image: its tiles' row sums in tile order, added in slabs of 64, then the slabs.
     const int rows = (g / B) * kRows, slabs = (int)ceil_div(rows, 64);
