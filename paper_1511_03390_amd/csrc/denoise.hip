@@ -345,9 +345,26 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *__restrict__ y, 
                                                    float *__restrict__ dy, int64_t n, double *__restrict__ part) {
     __shared__ double red[256];
     double s = 0.0;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const float sc = (float)(2.0 / (double)n);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    // Groups of four pixels with 16-byte accesses (y and dy are the
+    // denoiser's own 16-byte aligned buffers; the caller's t may not be,
+    // and then every pixel takes the loop below), then the rest one by one.
+    const int64_t n4 = (reinterpret_cast<uintptr_t>(t) & 15) == 0 ? n / 4 : 0;
+    for (int64_t i = gid; i < n4; i += stride) {
+        const f32x4 yv = reinterpret_cast<const f32x4 *>(y)[i];
+        const f32x4 tv = reinterpret_cast<const f32x4 *>(t)[i];
+        f32x4 o;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float d = yv[k] - tv[k];
+            o[k] = sc * d;
+            s += (double)d * d;
+        }
+        reinterpret_cast<f32x4 *>(dy)[i] = o;
+    }
+    for (int64_t i = 4 * n4 + gid; i < n; i += stride) {
         const float d = y[i] - t[i];
         dy[i] = sc * d;
         s += (double)d * d;
@@ -973,20 +990,21 @@ __global__ void gate_back_kernel(const float *__restrict__ pool, const float *__
     }
 }
 
-__global__ void loss_finish_kernel(const double *__restrict__ part, int n_blocks, int64_t n, float *__restrict__ loss) {
-    if (threadIdx.x != 0) return;
-    // In block order; loads issued 16 at a time.
+// One wave: lane j adds partials j*c .. j*c+c-1 in order (c = n_blocks / 64,
+// n_blocks a multiple of 64), then lane 0 adds the 64 sums in lane order.
+__global__ __launch_bounds__(64) void loss_finish_kernel(const double *__restrict__ part, int n_blocks, int64_t n,
+                                                         float *__restrict__ loss) {
+    __shared__ double lane_sum[64];
+    const int j = threadIdx.x, c = n_blocks / 64;
     double s = 0.0;
-    int b = 0;
-    for (; b + 16 <= n_blocks; b += 16) {
-        double v[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = part[b + i];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) s += v[i];
+    for (int b = j * c; b < (j + 1) * c; ++b) s += part[b];
+    lane_sum[j] = s;
+    __syncthreads();
+    if (j == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < 64; ++i) tot += lane_sum[i];
+        loss[0] = (float)(tot / (double)n);
     }
-    for (; b < n_blocks; ++b) s += part[b];
-    loss[0] = (float)(s / (double)n);
 }
 
 __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
@@ -1043,7 +1061,7 @@ int dw32_rows(int B, int H, int W, int blocks = kW32Blocks) {
 // out_grad_kernel: QLD_OUT_GRAD_BLOCKS_PER_CU work-groups per CU (its launch
 // bound keeps that many resident), one unit each.
 int out_grad_blocks() { return std::max(8, QLD_OUT_GRAD_BLOCKS_PER_CU * device_cu_count() / 8 * 8); }
-constexpr int kLossBlocks = 256;
+constexpr int kLossBlocks = 1024;   // a multiple of 64 (loss_finish_kernel)
 
 template <typename T>
 qld_status dalloc(qld_denoiser *d, T **p, size_t count) {
