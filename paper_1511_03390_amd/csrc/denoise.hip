@@ -992,10 +992,14 @@ __global__ void gate_back_kernel(const float *__restrict__ pool, const float *__
 
 // One wave: lane j adds partials j*c .. j*c+c-1 in order (c = n_blocks / 64,
 // n_blocks a multiple of 64), then lane 0 adds the 64 sums in lane order.
+// Also clears zero_n floats at zero_out (the gate's gradient when the step
+// has no gate loss), or none.
 __global__ __launch_bounds__(64) void loss_finish_kernel(const double *__restrict__ part, int n_blocks, int64_t n,
-                                                         float *__restrict__ loss) {
+                                                         float *__restrict__ loss, float *__restrict__ zero_out,
+                                                         int zero_n) {
     __shared__ double lane_sum[64];
     const int j = threadIdx.x, c = n_blocks / 64;
+    for (int i = j; i < zero_n; i += 64) zero_out[i] = 0.f;
     double s = 0.0;
     for (int b = j * c; b < (j + 1) * c; ++b) s += part[b];
     lane_sum[j] = s;
@@ -1007,22 +1011,43 @@ __global__ __launch_bounds__(64) void loss_finish_kernel(const double *__restric
     }
 }
 
-__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
-                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
-                            float c2) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-}
-
-__global__ void zero_f32_kernel(float *p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.f;
+// One Adam step with the weights' bf16 copies refreshed in the same launch:
+// thread j updates parameter j (m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p -= lr (m / c1) / (sqrt(v / c2) + eps), c1 and c2 the bias corrections) and
+// writes its bf16 copy into each operand layout of pack_kernel it has an
+// entry in (the layouts' zero entries, written by the full pack when the
+// parameters are set, never change).
+__global__ void adam_pack_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                                 float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2,
+                                 __bf16 *w1f, __bf16 *w2f, __bf16 *w2b, __bf16 *w3f, __bf16 *w3b, __bf16 *w4,
+                                 __bf16 *w4f) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N_ALL) return;
+    const float gj = g[j];
+    const float mj = b1 * m[j] + (1.f - b1) * gj;
+    const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    float pj = p[j];
+    pj -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+    p[j] = pj;
+    const __bf16 h = (__bf16)pj;
+    if (j < OFF_B1) {                                   // W1[tap][ci][co] -> w1f[co][2 tap + ci]
+        const int r = j - OFF_W1;
+        w1f[(r % 32) * 32 + r / 32] = h;
+    } else if (j >= OFF_W2 && j < OFF_B2) {             // W[t][ci][co] -> wf[t][co][ci], wb[t][ci][co]
+        const int r = j - OFF_W2, t = r / 1024, ci = (r / 32) % 32, co = r % 32;
+        w2f[t * 1024 + co * 32 + ci] = h;
+        w2b[r] = h;
+    } else if (j >= OFF_W3 && j < OFF_B3) {
+        const int r = j - OFF_W3, t = r / 1024, ci = (r / 32) % 32, co = r % 32;
+        w3f[t * 1024 + co * 32 + ci] = h;
+        w3b[r] = h;
+    } else if (j >= OFF_W4 && j < OFF_B4) {             // W4[t][ci] -> w4[t][ci], w4f[t][0][ci]
+        const int r = j - OFF_W4;
+        w4[r] = h;
+        w4f[(r / 32) * 512 + r % 32] = h;
+    }
 }
 
 }  // namespace
@@ -1332,7 +1357,9 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     const int H = d->H, W = d->W;
     const int64_t npx = (int64_t)B * H * W;
     hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, s, d->y, t, d->dy, npx, d->lpart);
-    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, d->lpart, kLossBlocks, npx, d->loss);
+    // Without a gate loss the gate's gradient is zero (cleared here).
+    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, d->lpart, kLossBlocks, npx, d->loss,
+                       e_a ? nullptr : d->grads + OFF_WG, e_a ? 0 : 33);
     // Output layer: dW4, db4, and dz3 = bf16(d a3 * (a3 > 0)).
     QLD_TRY(out_grad(d, B, s));
     const int g = conv_grid(B, H, W), gp = conv_persistent_grid(g);
@@ -1350,8 +1377,6 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     if (e_a) {
         hipLaunchKernelGGL(gate_back_kernel, dim3(1), dim3(64), 0, s, d->pool, d->gate, e_a, e_b, gate_weight, B,
                            d->grads, d->loss);
-    } else {
-        hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, s, d->grads + OFF_WG, (int64_t)33);
     }
     QLD_TRY(check_hip(hipGetLastError(), "backward launch"));
     if (loss_out) QLD_TRY(check_hip(hipMemcpyAsync(loss_out, d->loss, 8, hipMemcpyDeviceToDevice, s), "loss copy"));
@@ -1369,8 +1394,8 @@ extern "C" qld_status qld_denoiser_adam(qld_denoiser *d, float lr, float beta1, 
     d->step += 1;
     const float c1 = (float)(1.0 - std::pow((double)beta1, (double)d->step));
     const float c2 = (float)(1.0 - std::pow((double)beta2, (double)d->step));
-    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)ceil_div(N_ALL, 256)), dim3(256), 0, s, d->params, d->grads, d->m,
-                       d->v, N_ALL, lr, beta1, beta2, eps, c1, c2);
-    QLD_TRY(check_hip(hipGetLastError(), "adam launch"));
-    return pack(d, s);
+    hipLaunchKernelGGL(adam_pack_kernel, dim3((unsigned)ceil_div(N_ALL, 256)), dim3(256), 0, s, d->params, d->grads,
+                       d->m, d->v, lr, beta1, beta2, eps, c1, c2, d->w1f, d->w2f, d->w2b, d->w3f, d->w3b, d->w4,
+                       d->w4f);
+    return check_hip(hipGetLastError(), "adam launch");
 }
