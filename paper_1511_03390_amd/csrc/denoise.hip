@@ -880,32 +880,49 @@ __global__ __launch_bounds__(256, QLD_OUT_GRAD_BLOCKS_PER_CU) void out_grad_kern
     }
 }
 
-// Column sums of part[R][n] in a fixed order.  Work-group (cx, slab): 64
-// columns x 4 row groups; group g adds rows slab*64 + g, +4, ... ; the four
-// groups are combined in order.  Output row `slab` of out[slabs][n].
-__global__ __launch_bounds__(256) void reduce_rows_kernel(const float *__restrict__ in, int R, int n,
-                                                          float *__restrict__ out) {
+// Column sums of several arrays part[R][n] in one launch, in a fixed order.
+// Segment i covers blocks b0 .. b0 + bx * by - 1 of the 1-D grid (bx column
+// blocks of 64, by slabs of 64 rows); block (cx, slab) of a segment takes 64
+// columns x 4 row groups: group g adds rows slab*64 + g, +4, ... (their loads
+// issued 16 at a time), and the four groups are combined in order into row
+// `slab` of out[slabs][n].
+constexpr int kMaxRedSegs = 4;
+struct RedSeg {
+    const float *in;
+    float *out;
+    int R, n, bx, b0;
+};
+struct RedJob {
+    int n_seg;
+    RedSeg seg[kMaxRedSegs];
+};
+
+__global__ __launch_bounds__(256) void reduce_segs_kernel(RedJob job) {
+    int si = 0;
+    while (si + 1 < job.n_seg && (int)blockIdx.x >= job.seg[si + 1].b0) ++si;
+    const RedSeg &S = job.seg[si];
+    const int lb = (int)blockIdx.x - S.b0, bx = lb % S.bx, by = lb / S.bx;
+    const int n = S.n;
     __shared__ float red[4][64];
-    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int c = bx * 64 + (threadIdx.x & 63);
     const int g = threadIdx.x >> 6;
-    const int r0 = blockIdx.y * 64, r1 = min(R, r0 + 64);
-    // Rows r0 + g, r0 + g + 4, ... in order; their loads issued together.
+    const int r0 = by * 64, r1 = min(S.R, r0 + 64);
     float s = 0.f;
     if (c < n) {
         int r = r0 + g;
         for (; r + 4 * 15 < r1; r += 4 * 16) {
             float v[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = in[(int64_t)(r + 4 * i) * n + c];
+            for (int i = 0; i < 16; ++i) v[i] = S.in[(int64_t)(r + 4 * i) * n + c];
 #pragma unroll
             for (int i = 0; i < 16; ++i) s += v[i];
         }
-        for (; r < r1; r += 4) s += in[(int64_t)r * n + c];
+        for (; r < r1; r += 4) s += S.in[(int64_t)r * n + c];
     }
     red[g][threadIdx.x & 63] = s;
     __syncthreads();
-    if (g == 0 && c < n) out[(int64_t)blockIdx.y * n + c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
-                                                             red[2][threadIdx.x]) + red[3][threadIdx.x];
+    if (g == 0 && c < n) S.out[(int64_t)by * n + c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                                       red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
 // Gate: pool[b][c] = mean_p a3[b][p][c]; gate[b] = pool[b] . Wg + bg.
@@ -1065,6 +1082,11 @@ struct qld_denoiser {
     float *y, *dy, *pool, *gate, *part, *part2, *loss;
     double *lpart;
     int64_t part_floats;
+    // Weight-gradient partial rows of the backward (W4, W3, W2, W1), each
+    // summed at the end of the backward: rows, columns, and the slab sums.
+    float *gpart[4], *gslab;
+    int gpart_R[4], gpart_n[4];
+    int64_t gslab_off[4];
     int last_B;
     std::vector<void *> allocs;
 };
@@ -1119,47 +1141,56 @@ qld_status pack(qld_denoiser *d, hipStream_t s) {
     return check_hip(hipGetLastError(), "pack_kernel launch");
 }
 
-// Sum the rows of part[R][n] into dst[n] (two stages, fixed order).
-qld_status reduce_rows(qld_denoiser *d, const float *part, int R, int n, float *dst, hipStream_t s) {
-    const float *in = part;
-    while (R > 64) {
-        const int slabs = (int)ceil_div(R, 64);
-        hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)ceil_div(n, 64), (unsigned)slabs), dim3(256), 0, s, in, R,
-                           n, d->part2);
-        in = d->part2;
-        R = slabs;
-        if (R > 64) {
-            set_error("reduction too large");
-            return QLD_E_INVAL;
-        }
-    }
-    hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)ceil_div(n, 64), 1), dim3(256), 0, s, in, R, n, dst);
-    return check_hip(hipGetLastError(), "reduce_rows launch");
-}
-
-// Weights and bias of a 32 -> 32 layer (the bias follows the weights in the canonical order).
-qld_status dw32(qld_denoiser *d, const __bf16 *a, const __bf16 *dz, int B, int64_t off, hipStream_t s) {
+// Weights and bias of a 32 -> 32 layer (the bias follows the weights in the
+// canonical order) into partial rows gpart[gi], summed by reduce_grads.
+qld_status dw32(qld_denoiser *d, const __bf16 *a, const __bf16 *dz, int B, int gi, hipStream_t s) {
     hipLaunchKernelGGL(dw32_kernel, dim3(kW32Blocks), dim3(256), 0, s, a, dz, B, d->H, d->W, dw32_rows(B, d->H, d->W),
-                       d->part);
-    QLD_TRY(check_hip(hipGetLastError(), "dw32 launch"));
-    return reduce_rows(d, d->part, kW32Blocks, kW32Row, d->grads + off, s);
+                       d->gpart[gi]);
+    return check_hip(hipGetLastError(), "dw32 launch");
 }
 
-// Weights and bias of the input layer.
+// Weights and bias of the input layer, into gpart[3].
 qld_status dw1(qld_denoiser *d, int B, hipStream_t s) {
     hipLaunchKernelGGL(dw1_kernel, dim3(kW1Blocks), dim3(256), 0, s, d->x0, d->dzC, B, d->H, d->W,
-                       dw32_rows(B, d->H, d->W, kW1Blocks), d->part);
-    QLD_TRY(check_hip(hipGetLastError(), "dw1 launch"));
-    return reduce_rows(d, d->part, kW1Blocks, kW1Row, d->grads + OFF_W1, s);
+                       dw32_rows(B, d->H, d->W, kW1Blocks), d->gpart[3]);
+    return check_hip(hipGetLastError(), "dw1 launch");
 }
 
-// Output layer backward: dW4, db4 and dz3 (into dzA) in one pass.
+// Output layer backward: dW4, db4 (into gpart[0]) and dz3 (into dzA) in one pass.
 qld_status out_grad(qld_denoiser *d, int B, hipStream_t s) {
     const int blocks = out_grad_blocks();
     hipLaunchKernelGGL(out_grad_kernel, dim3(blocks), dim3(256), 0, s, d->a3, d->dy, d->w4, B, d->H, d->W,
-                       dw32_rows(B, d->H, d->W, blocks), d->dzA, d->part);
-    QLD_TRY(check_hip(hipGetLastError(), "out_grad launch"));
-    return reduce_rows(d, d->part, 2 * blocks, kOutRow, d->grads + OFF_W4, s);
+                       dw32_rows(B, d->H, d->W, blocks), d->dzA, d->gpart[0]);
+    return check_hip(hipGetLastError(), "out_grad launch");
+}
+
+// The four weight gradients from their partial rows, in two launches: the
+// first adds each array's rows in slabs of 64 (or all of them, for at most 64
+// rows, straight into the gradient), the second adds the slabs in order.
+qld_status reduce_grads(qld_denoiser *d, hipStream_t s) {
+    static const int64_t kOff[4] = {OFF_W4, OFF_W3, OFF_W2, OFF_W1};
+    RedJob j1{}, j2{};
+    int b1 = 0, b2 = 0;
+    for (int i = 0; i < 4; ++i) {
+        const int R = d->gpart_R[i], n = d->gpart_n[i], bx = (int)ceil_div(n, 64);
+        const int slabs = (int)ceil_div(R, 64);
+        float *dst = d->grads + kOff[i];
+        if (slabs > 64) {
+            set_error("reduction too large");
+            return QLD_E_INVAL;
+        }
+        RedSeg &a = j1.seg[j1.n_seg++];
+        a = RedSeg{d->gpart[i], slabs > 1 ? d->gslab + d->gslab_off[i] : dst, R, n, bx, b1};
+        b1 += bx * slabs;
+        if (slabs > 1) {
+            RedSeg &c = j2.seg[j2.n_seg++];
+            c = RedSeg{d->gslab + d->gslab_off[i], dst, slabs, n, bx, b2};
+            b2 += bx;
+        }
+    }
+    hipLaunchKernelGGL(reduce_segs_kernel, dim3((unsigned)b1), dim3(256), 0, s, j1);
+    if (j2.n_seg > 0) hipLaunchKernelGGL(reduce_segs_kernel, dim3((unsigned)b2), dim3(256), 0, s, j2);
+    return check_hip(hipGetLastError(), "reduce_grads launch");
 }
 
 }  // namespace
@@ -1179,10 +1210,19 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     d->W = W;
     d->max_batch = max_batch;
     const size_t npx = (size_t)max_batch * H * W;
-    // Largest user of the partials: the 32 -> 32 weight gradient, or the
-    // gate's row sums (one row of 32 channel sums per tile row).
-    d->part_floats = std::max<int64_t>((int64_t)kW32Blocks * kW32Row,
-                                       (int64_t)conv_grid(max_batch, H, W) * kRows * 32);
+    // The forward's partials: the gate's row sums (one row of 32 channel sums
+    // per tile row).
+    d->part_floats = (int64_t)conv_grid(max_batch, H, W) * kRows * 32;
+    // The backward's weight-gradient partial rows (W4, W3, W2, W1).
+    const int gR[4] = {2 * out_grad_blocks(), kW32Blocks, kW32Blocks, kW1Blocks};
+    const int gn[4] = {kOutRow, kW32Row, kW32Row, kW1Row};
+    int64_t slab_floats = 0;
+    for (int i = 0; i < 4; ++i) {
+        d->gpart_R[i] = gR[i];
+        d->gpart_n[i] = gn[i];
+        d->gslab_off[i] = slab_floats;
+        slab_floats += ceil_div(gR[i], 64) * (int64_t)gn[i];
+    }
     qld_status st = QLD_OK;
     if (st == QLD_OK) st = dalloc(d, &d->params, N_ALL);
     if (st == QLD_OK) st = dalloc(d, &d->grads, N_ALL);
@@ -1208,6 +1248,8 @@ extern "C" qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batc
     if (st == QLD_OK) st = dalloc(d, &d->gate, (size_t)max_batch);
     if (st == QLD_OK) st = dalloc(d, &d->part, (size_t)d->part_floats);
     if (st == QLD_OK) st = dalloc(d, &d->part2, (size_t)d->part_floats / 16 + 65536);
+    for (int i = 0; i < 4 && st == QLD_OK; ++i) st = dalloc(d, &d->gpart[i], (size_t)gR[i] * gn[i]);
+    if (st == QLD_OK) st = dalloc(d, &d->gslab, (size_t)slab_floats);
     if (st == QLD_OK) st = dalloc(d, &d->loss, 2);
     if (st == QLD_OK) st = dalloc(d, &d->lpart, kLossBlocks);
     if (st == QLD_OK) {
@@ -1364,15 +1406,16 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     QLD_TRY(out_grad(d, B, s));
     const int g = conv_grid(B, H, W), gp = conv_persistent_grid(g);
     // Layer 3: dW3 from (a2, dz3); dz2 = bf16(conv^T(dz3, W3) * (a2 > 0)).
-    QLD_TRY(dw32(d, d->a2, d->dzA, B, OFF_W3, s));   // and b3
+    QLD_TRY(dw32(d, d->a2, d->dzA, B, 1, s));   // and b3
     hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(gp), dim3(256), 0, s, d->dzA, d->w3b, nullptr, d->a2, d->dzB, H, W,
                        g, nullptr);
     // Layer 2: dW2 from (a1, dz2); dz1 = bf16(conv^T(dz2, W2) * (a1 > 0)).
-    QLD_TRY(dw32(d, d->a1, d->dzB, B, OFF_W2, s));   // and b2
+    QLD_TRY(dw32(d, d->a1, d->dzB, B, 2, s));   // and b2
     hipLaunchKernelGGL((conv_tile_kernel<1>), dim3(gp), dim3(256), 0, s, d->dzB, d->w2b, nullptr, d->a1, d->dzC, H, W,
                        g, nullptr);
     // Layer 1: dW1 from (x0, dz1).
     QLD_TRY(dw1(d, B, s));   // and b1
+    QLD_TRY(reduce_grads(d, s));
     // Gate (its own loss; its gradient reaches only Wg, bg).
     if (e_a) {
         hipLaunchKernelGGL(gate_back_kernel, dim3(1), dim3(64), 0, s, d->pool, d->gate, e_a, e_b, gate_weight, B,
