@@ -143,21 +143,35 @@ constexpr int kTilePer = (kTileItems + 255) / 256;          // per lane
 #ifndef QLD_OUT_LAYER_GROUPS_PER_CU
 #define QLD_OUT_LAYER_GROUPS_PER_CU 3
 #endif
+#ifndef QLD_CONV_GROUPS_PER_CU
+#define QLD_CONV_GROUPS_PER_CU 3
+#endif
 template <int MODE>
-__global__ __launch_bounds__(256, MODE == 2 ? QLD_OUT_LAYER_GROUPS_PER_CU : 2) void conv_tile_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
+__global__ __launch_bounds__(256, MODE == 2 ? QLD_OUT_LAYER_GROUPS_PER_CU : QLD_CONV_GROUPS_PER_CU) void conv_tile_kernel(const __bf16 *__restrict__ in, const __bf16 *__restrict__ wt,
                                                         const float *__restrict__ bias, const __bf16 *__restrict__ act,
                                                         void *__restrict__ out, int H, int W, int n_tiles,
                                                         float *__restrict__ pool_part) {
     constexpr int NCB = MODE == 2 ? 1 : 2;          // 16-channel output blocks
+    // The 32-channel layers keep their weights in LDS (18 KB, read per tap),
+    // which leaves registers for three work-groups per CU; the output layer's
+    // fit in registers.
+    constexpr bool kWLds = MODE != 2;
     __shared__ __align__(16) __bf16 tile[kRows + 2][kCols + 2][32];
+    __shared__ __align__(16) __bf16 wS[kWLds ? 9 * 16 * NCB * 32 : 8];
     const int tx = (W + kCols - 1) / kCols, ty = (H + kRows - 1) / kRows;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
-    bf16x8 w[9][NCB];
+    bf16x8 w[kWLds ? 1 : 9][NCB];
+    if constexpr (kWLds) {
+        // Visible to every wave after the first tile's barriers.
+        for (int i = t; i < 9 * 16 * NCB * 4; i += 256)
+            reinterpret_cast<bf16x8 *>(wS)[i] = reinterpret_cast<const bf16x8 *>(wt)[i];
+    } else {
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
+        for (int k = 0; k < 9; ++k)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-            w[k][cb] = *reinterpret_cast<const bf16x8 *>(wt + ((k * 16 * NCB + cb * 16 + m) * 32 + kb * 8));
+            for (int cb = 0; cb < NCB; ++cb)
+                w[k][cb] = *reinterpret_cast<const bf16x8 *>(wt + ((k * 16 * NCB + cb * 16 + m) * 32 + kb * 8));
+    }
     float bco[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) bco[cb] = MODE == 1 ? 0.f : bias[MODE == 2 ? 0 : 16 * cb + m];
@@ -238,10 +252,15 @@ __global__ __launch_bounds__(256, MODE == 2 ? QLD_OUT_LAYER_GROUPS_PER_CU : 2) v
 #pragma unroll
             for (int g = 0; g < 4; ++g)
                 a[g] = *reinterpret_cast<const bf16x8 *>(&tile[wave + 1 + sy][16 * g + m + 1 + sx][kb * 8]);
+            bf16x8 wk[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+                wk[cb] = kWLds ? *reinterpret_cast<const bf16x8 *>(&wS[(k * 16 * NCB + cb * 16 + m) * 32 + kb * 8])
+                               : w[k][cb];
 #pragma unroll
             for (int g = 0; g < 4; ++g)
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) acc[g][cb] = mfma16(a[g], w[k][cb], acc[g][cb]);
+                for (int cb = 0; cb < NCB; ++cb) acc[g][cb] = mfma16(a[g], wk[cb], acc[g][cb]);
         }
         if constexpr (MODE == 2) {
             if (y < H && m == 0) {
@@ -1142,7 +1161,7 @@ int conv_grid(int B, int H, int W) {
 
 // Persistent grid of conv_tile_kernel: at most kConvGroupsPerCU work-groups
 // per CU (a multiple of 8), looping over the tiles.
-constexpr int kConvGroupsPerCU = 2;
+constexpr int kConvGroupsPerCU = QLD_CONV_GROUPS_PER_CU;
 int conv_persistent_grid(int n_tiles, int per_cu = kConvGroupsPerCU) {
     const int64_t cap = std::max<int64_t>(8, (int64_t)per_cu * device_cu_count() / 8 * 8);
     return (int)std::min<int64_t>(n_tiles, cap);
