@@ -58,6 +58,13 @@ class Batch:
         self.invL = torch.full((B,), 1.0 / M_L, dtype=torch.float32, device="cuda")
         self.invS = torch.full((B,), 1.0 / M_S, dtype=torch.float32, device="cuda")
 
+    def record_stream(self, stream):
+        """Mark every device tensor as used on ``stream`` (made on another
+        stream), so its memory is not reused before that stream's work on it."""
+        for v in vars(self).values():
+            if isinstance(v, torch.Tensor) and v.is_cuda:
+                v.record_stream(stream)
+
 
 TILES_CONFIG4 = dict(background=2000.0, ballistic=5e-4, smin=16, smax=256, max_rects=5)
 
@@ -72,14 +79,34 @@ def tile_batch(step, batch, H, W, M_S, M_L, seed, tiles=None):
 
 def train(steps=200, batch=8, H=512, W=512, M_S=8, M_L=512, lr=2e-3, seed=1511033904, gate_weight=0.1,
           log=None, first_step=0, tiles=None):
+    """Train on generated batches.  Batch s + 1 is generated on a second
+    stream while step s trains (the generator is bound by its VALU work, the
+    training by memory and the matrix cores); an event orders each step after
+    its batch.  The steps and their results are those of generating and
+    training one after the other."""
     d = qld.Denoiser(H, W, batch)
     d.set_params(he_init(seed))
     y = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
     loss = torch.zeros(2, dtype=torch.float32, device="cuda")
     hist = []
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+
+    def generate(s):
+        with torch.cuda.stream(side):
+            b = tile_batch(first_step + s, batch, H, W, M_S, M_L, seed, tiles)
+            done = torch.cuda.Event()
+            done.record(side)
+        return b, done
+
     t0 = time.perf_counter()
+    nxt = generate(0) if steps > 0 else None
     for s in range(steps):
-        b = tile_batch(first_step + s, batch, H, W, M_S, M_L, seed, tiles)
+        b, done = nxt
+        main.wait_event(done)
+        b.record_stream(main)
+        if s + 1 < steps:
+            nxt = generate(s + 1)
         d.forward(b.x, y)
         nl = qld.judge_nrmse(y, b.clean, b.scale)
         npl = qld.judge_nrmse(b.ampL, b.clean, b.invL)
