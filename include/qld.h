@@ -592,6 +592,9 @@ qld_status qld_judge_cnr(const float *img, const uint8_t *labels, int32_t B, int
  * W1[3][3][2][32] b1[32] W2[3][3][32][32] b2[32] W3[3][3][32][32] b3[32]
  * W4[3][3][32][1] b4[1] Wg[32] bg[1].  Work is enqueued on `stream`; the
  * object keeps the activations of its last forward for the backward.
+ * Device memory: about 400 bytes per pixel of max_batch x H x W (bf16
+ * activations and their gradients, fp32 output and its gradient) plus about
+ * 85 MB whatever the size (the weight gradients' partial rows).
  */
 int32_t qld_denoiser_param_count(void);
 qld_status qld_denoiser_create(int32_t H, int32_t W, int32_t max_batch, qld_denoiser **out);
