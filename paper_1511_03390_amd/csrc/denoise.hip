@@ -29,6 +29,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4c __attribute__((ext_vector_type(4)));
 
 // Canonical parameter order (fp32): W[3][3][Cin][Cout] then b[Cout], per layer; then the gate.
 constexpr int64_t OFF_W1 = 0, OFF_B1 = 576, OFF_W2 = 608, OFF_B2 = 9824, OFF_W3 = 9856, OFF_B3 = 19072,
@@ -318,32 +319,39 @@ __global__ __launch_bounds__(256, MODE == 2 ? QLD_OUT_LAYER_GROUPS_PER_CU : QLD_
 }
 
 // 2 -> 32 input layer: the 18 (tap, channel) products form one K = 32 MFMA.
+// The work-group's input (rows y0-1 .. y0+4, pixels xs-1 .. xs+64, both
+// channels of a pixel as one 4-byte word, zero outside the image) is staged
+// in LDS once; a lane's operand dword e is then tap 4 kb + e's word.
 __global__ __launch_bounds__(256) void conv1_kernel(const __bf16 *__restrict__ x0, const __bf16 *__restrict__ w1f,
                                                     const float *__restrict__ bias, __bf16 *__restrict__ out, int H,
                                                     int W) {
+    __shared__ uint32_t xt[kRows + 2][kCols + 2];
     int b, y, xs;
-    if (!tile_of(H, W, b, y, xs)) return;
-    const int lane = threadIdx.x & 63, m = lane & 15, kb = lane >> 4;
+    const bool row_ok = tile_of(H, W, b, y, xs);
+    const int wave = threadIdx.x >> 6, y0 = y - wave;
     const int64_t img = (int64_t)b * H;
+    for (int i = threadIdx.x; i < (kRows + 2) * (kCols + 2); i += 256) {
+        const int r = i / (kCols + 2), c = i % (kCols + 2);
+        const int iy = y0 - 1 + r, ix = xs - 1 + c;
+        xt[r][c] = iy >= 0 && iy < H && ix >= 0 && ix < W
+                       ? *reinterpret_cast<const uint32_t *>(x0 + ((img + iy) * W + ix) * 2)
+                       : 0u;
+    }
+    __syncthreads();
+    if (!row_ok) return;
+    const int lane = threadIdx.x & 63, m = lane & 15, kb = lane >> 4;
     const bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(w1f + (m * 32 + kb * 8));
     const bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(w1f + ((16 + m) * 32 + kb * 8));
     f32x4 acc[4][2];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        const int px = xs + 16 * g + m;
-        bf16x8 a = zero8();
+        u32x4c aw;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {          // k = 8 kb + 2 e + ch: tap 4 kb + e
             const int t = 4 * kb + e;
-            if (t < 9) {
-                const int iy = y + tap_dy(t), ix = px + tap_dx(t);
-                if (iy >= 0 && iy < H && ix >= 0 && ix < W) {
-                    const int64_t o = ((img + iy) * W + ix) * 2;
-                    a[2 * e] = x0[o];
-                    a[2 * e + 1] = x0[o + 1];
-                }
-            }
+            aw[e] = t < 9 ? xt[wave + 1 + tap_dy(t)][16 * g + m + 1 + tap_dx(t)] : 0u;
         }
+        const bf16x8 a = __builtin_bit_cast(bf16x8, aw);
         acc[g][0] = mfma16(a, w0, f32x4{0.f, 0.f, 0.f, 0.f});
         acc[g][1] = mfma16(a, w1, f32x4{0.f, 0.f, 0.f, 0.f});
     }
