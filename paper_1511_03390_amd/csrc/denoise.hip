@@ -932,12 +932,47 @@ struct RedSeg {
     float *out;
     int R, n, bx, b0;
 };
+// The loss's last stage, taken by one more block of a reduction launch:
+// lane j < 64 adds partials j*c .. j*c+c-1 in order (c = n_blocks / 64,
+// n_blocks a multiple of 64), then lane 0 adds the 64 sums in lane order;
+// zero_n floats at zero_out (the gate's gradient when the step has no gate
+// loss) are cleared.
+struct LossFinish {
+    const double *part;
+    int n_blocks;
+    int64_t n;
+    float *loss, *zero_out;
+    int zero_n;
+};
 struct RedJob {
     int n_seg;
     RedSeg seg[kMaxRedSegs];
+    int b_end;          // blocks of the segments; block b_end takes lf (if lf.part)
+    LossFinish lf;
 };
 
+__device__ void loss_finish_block(const LossFinish &f) {
+    __shared__ double lane_sum[64];
+    const int j = threadIdx.x, c = f.n_blocks / 64;
+    for (int i = j; i < f.zero_n; i += blockDim.x) f.zero_out[i] = 0.f;
+    if (j < 64) {
+        double s = 0.0;
+        for (int b = j * c; b < (j + 1) * c; ++b) s += f.part[b];
+        lane_sum[j] = s;
+    }
+    __syncthreads();
+    if (j == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < 64; ++i) tot += lane_sum[i];
+        f.loss[0] = (float)(tot / (double)f.n);
+    }
+}
+
 __global__ __launch_bounds__(256) void reduce_segs_kernel(RedJob job) {
+    if ((int)blockIdx.x == job.b_end) {
+        if (job.lf.part) loss_finish_block(job.lf);
+        return;
+    }
     int si = 0;
     while (si + 1 < job.n_seg && (int)blockIdx.x >= job.seg[si + 1].b0) ++si;
     const RedSeg &S = job.seg[si];
@@ -1047,26 +1082,6 @@ __global__ void gate_back_kernel(const float *__restrict__ pool, const float *__
     }
 }
 
-// One wave: lane j adds partials j*c .. j*c+c-1 in order (c = n_blocks / 64,
-// n_blocks a multiple of 64), then lane 0 adds the 64 sums in lane order.
-// Also clears zero_n floats at zero_out (the gate's gradient when the step
-// has no gate loss), or none.
-__global__ __launch_bounds__(64) void loss_finish_kernel(const double *__restrict__ part, int n_blocks, int64_t n,
-                                                         float *__restrict__ loss, float *__restrict__ zero_out,
-                                                         int zero_n) {
-    __shared__ double lane_sum[64];
-    const int j = threadIdx.x, c = n_blocks / 64;
-    for (int i = j; i < zero_n; i += 64) zero_out[i] = 0.f;
-    double s = 0.0;
-    for (int b = j * c; b < (j + 1) * c; ++b) s += part[b];
-    lane_sum[j] = s;
-    __syncthreads();
-    if (j == 0) {
-        double tot = 0.0;
-        for (int i = 0; i < 64; ++i) tot += lane_sum[i];
-        loss[0] = (float)(tot / (double)n);
-    }
-}
 
 // One Adam step with the weights' bf16 copies refreshed in the same launch:
 // thread j updates parameter j (m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
@@ -1148,7 +1163,7 @@ int dw32_rows(int B, int H, int W, int blocks = kW32Blocks) {
 // out_grad_kernel: QLD_OUT_GRAD_BLOCKS_PER_CU work-groups per CU (its launch
 // bound keeps that many resident), one unit each.
 int out_grad_blocks() { return std::max(8, QLD_OUT_GRAD_BLOCKS_PER_CU * device_cu_count() / 8 * 8); }
-constexpr int kLossBlocks = 1024;   // a multiple of 64 (loss_finish_kernel)
+constexpr int kLossBlocks = 1024;   // a multiple of 64 (loss_finish_block)
 
 template <typename T>
 qld_status dalloc(qld_denoiser *d, T **p, size_t count) {
@@ -1207,7 +1222,7 @@ qld_status out_grad(qld_denoiser *d, int B, hipStream_t s) {
 // The four weight gradients from their partial rows, in two launches: the
 // first adds each array's rows in slabs of 64 (or all of them, for at most 64
 // rows, straight into the gradient), the second adds the slabs in order.
-qld_status reduce_grads(qld_denoiser *d, hipStream_t s) {
+qld_status reduce_grads(qld_denoiser *d, const LossFinish &lf, hipStream_t s) {
     static const int64_t kOff[4] = {OFF_W4, OFF_W3, OFF_W2, OFF_W1};
     RedJob j1{}, j2{};
     int b1 = 0, b2 = 0;
@@ -1228,7 +1243,10 @@ qld_status reduce_grads(qld_denoiser *d, hipStream_t s) {
             b2 += bx;
         }
     }
-    hipLaunchKernelGGL(reduce_segs_kernel, dim3((unsigned)b1), dim3(256), 0, s, j1);
+    j1.b_end = b1;
+    j1.lf = lf;
+    j2.b_end = b2;
+    hipLaunchKernelGGL(reduce_segs_kernel, dim3((unsigned)b1 + 1), dim3(256), 0, s, j1);
     if (j2.n_seg > 0) hipLaunchKernelGGL(reduce_segs_kernel, dim3((unsigned)b2), dim3(256), 0, s, j2);
     return check_hip(hipGetLastError(), "reduce_grads launch");
 }
@@ -1439,9 +1457,6 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
     const int H = d->H, W = d->W;
     const int64_t npx = (int64_t)B * H * W;
     hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, s, d->y, t, d->dy, npx, d->lpart);
-    // Without a gate loss the gate's gradient is zero (cleared here).
-    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, d->lpart, kLossBlocks, npx, d->loss,
-                       e_a ? nullptr : d->grads + OFF_WG, e_a ? 0 : 33);
     // Output layer: dW4, db4, and dz3 = bf16(d a3 * (a3 > 0)).
     QLD_TRY(out_grad(d, B, s));
     const int g = conv_grid(B, H, W), gp = conv_persistent_grid(g);
@@ -1455,7 +1470,10 @@ extern "C" qld_status qld_denoiser_backward(qld_denoiser *d, const float *t, con
                        g, nullptr);
     // Layer 1: dW1 from (x0, dz1).
     QLD_TRY(dw1(d, B, s));   // and b1
-    QLD_TRY(reduce_grads(d, s));
+    // The weight gradients' sums, and the loss's last stage in the same launch
+    // (without a gate loss the gate's gradient is zero, cleared there too).
+    const LossFinish lf{d->lpart, kLossBlocks, npx, d->loss, e_a ? nullptr : d->grads + OFF_WG, e_a ? 0 : 33};
+    QLD_TRY(reduce_grads(d, lf, s));
     // Gate (its own loss; its gradient reaches only Wg, bg).
     if (e_a) {
         hipLaunchKernelGGL(gate_back_kernel, dim3(1), dim3(64), 0, s, d->pool, d->gate, e_a, e_b, gate_weight, B,
