@@ -749,6 +749,9 @@ __global__ __launch_bounds__(256, QLD_OUT_GRAD_BLOCKS_PER_CU) void out_grad_kern
                                                        __bf16 *__restrict__ dz, float *__restrict__ part) {
     __shared__ __align__(16) __bf16 aT[3][32][kAStride];
     __shared__ __align__(16) uint16_t dyP[4][3][kAStride];   // slot 3: zeros
+    // The same parts interleaved per column (hi | mid << 16, lo) for dz3's
+    // operand gathers: one 8-byte read per column; slot 3: zeros.
+    __shared__ __align__(16) uint32_t dyQ[4][kAStride][2];
     __shared__ __align__(16) float dyS[3][72];               // pixels x0-1 .. x0+64 at 3 .. 68
     __shared__ __align__(16) __bf16 stg[4][16][kStgRow];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, m = lane & 15, kb = lane >> 4;
@@ -757,6 +760,7 @@ __global__ __launch_bounds__(256, QLD_OUT_GRAD_BLOCKS_PER_CU) void out_grad_kern
     const int64_t n_units = (int64_t)B * segs_x * runs_y;
     const bf16x8 zero = zero8();
     for (int i = t; i < 3 * kAStride; i += 256) dyP[3][i / kAStride][i % kAStride] = 0;
+    for (int i = t; i < 2 * kAStride; i += 256) dyQ[3][i / 2][i % 2] = 0u;
     // dz3's B operand: lane (channel n = m, kb) holds w4[3 kb + i][16 cb + m]
     // for i < 3 and kb < 3 (K slot 4 kb + i), zero elsewhere.
     s16x4 bw[2];
@@ -806,6 +810,8 @@ __global__ __launch_bounds__(256, QLD_OUT_GRAD_BLOCKS_PER_CU) void out_grad_kern
             dyP[slot][0][t + 7] = h;
             dyP[slot][1][t + 7] = md;
             dyP[slot][2][t + 7] = l;
+            dyQ[slot][t + 7][0] = (uint32_t)h | ((uint32_t)md << 16);
+            dyQ[slot][t + 7][1] = l;
         }
     };
     auto work = [&](int64_t img, int x0, int y) {
@@ -835,16 +841,19 @@ __global__ __launch_bounds__(256, QLD_OUT_GRAD_BLOCKS_PER_CU) void out_grad_kern
         // at (y + 1 - kb, x + 1 - i), i < 3.
         s16x4 ap[3];
         {
+            typedef uint32_t u32x2q __attribute__((ext_vector_type(2)));
             const int sl = kb < 3 ? ring_slot(y + 1 - kb) : 3;
-            const int cq = 16 * wave + m + 9;                    // dyP column of pixel x + 1
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                const uint16_t *rp = &dyP[sl][s][cq];
-                ap[s][0] = (short)rp[0];
-                ap[s][1] = (short)rp[-1];
-                ap[s][2] = (short)rp[-2];
-                ap[s][3] = 0;
-            }
+            const int cq = 16 * wave + m + 9;                    // dyQ column of pixel x + 1
+            const u32x2q q0 = *reinterpret_cast<const u32x2q *>(&dyQ[sl][cq][0]);
+            const u32x2q q1 = *reinterpret_cast<const u32x2q *>(&dyQ[sl][cq - 1][0]);
+            const u32x2q q2 = *reinterpret_cast<const u32x2q *>(&dyQ[sl][cq - 2][0]);
+            // Part s of columns cq, cq - 1, cq - 2 in K slots 0, 1, 2; slot 3 zero.
+            const u32x2q hi = {(q0[0] & 0xffffu) | (q1[0] << 16), q2[0] & 0xffffu};
+            const u32x2q mid = {(q0[0] >> 16) | (q1[0] & 0xffff0000u), q2[0] >> 16};
+            const u32x2q lo = {(q0[1] & 0xffffu) | (q1[1] << 16), q2[1] & 0xffffu};
+            ap[0] = __builtin_bit_cast(s16x4, hi);
+            ap[1] = __builtin_bit_cast(s16x4, mid);
+            ap[2] = __builtin_bit_cast(s16x4, lo);
         }
         f32x4 dv[2];
 #pragma unroll
